@@ -1,0 +1,177 @@
+"""ctypes binding of the plain FP64 CPU oracle of the two-phase DUGKS step.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The product package never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle_dugks2p.so")
+SRC_PATH = os.path.join(_HERE, "dugks2p_oracle.c")
+
+
+def build(openmp: bool = True) -> str:
+    """Compile the oracle with gcc: -O2, no fast-math, no FMA contraction."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+    if openmp:
+        cmd.append("-fopenmp")
+    cmd += ["-o", LIB_PATH + ".tmp", SRC_PATH, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        d = ctypes.c_double
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [P(OrcParams), P(d), P(d), P(d), P(d)]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_last_error.restype = ctypes.c_char_p
+        L.orc_dt.restype = d
+        L.orc_dt.argtypes = [ctypes.c_void_p]
+        L.orc_step_count.restype = ctypes.c_long
+        L.orc_step_count.argtypes = [ctypes.c_void_p]
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+        L.orc_moments.argtypes = [ctypes.c_void_p] + [P(d)] * 6
+        L.orc_monitors.argtypes = [ctypes.c_void_p, P(d)]
+        L.orc_get_pops.argtypes = [ctypes.c_void_p, P(d)]
+        L.orc_set_pops.argtypes = [ctypes.c_void_p, P(d)]
+        L.orc_point_eq.argtypes = [ctypes.c_void_p, P(d), P(d), P(d), P(d), P(d)]
+        L.orc_deriv.argtypes = [ctypes.c_void_p, ctypes.c_int, P(d), P(d), P(d)]
+        L.orc_cell_transforms.argtypes = [ctypes.c_void_p, P(d), P(d)]
+        L.orc_reconstruct.argtypes = [ctypes.c_void_p, P(d), P(d), P(d)]
+        L.orc_face_dists.argtypes = [ctypes.c_void_p, P(d), P(d)]
+        _lib = L
+    return _lib
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("x_faces", ctypes.POINTER(ctypes.c_double)),
+                ("y_faces", ctypes.POINTER(ctypes.c_double)),
+                ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
+                ("recon", ctypes.c_int), ("phi_clamp", ctypes.c_int)] + \
+               [(n, ctypes.c_double) for n in (
+                   "cfl", "c_max", "dt", "rt", "tau_g", "mobility", "tau_f", "beta", "kappa",
+                   "phi_a", "phi_b", "rho_a", "rho_b", "nu_a", "nu_b", "gx", "gy", "rho_ref")]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Oracle:
+    """One oracle simulation.  `params` uses the same keys as the product's
+    parameter dictionary (see paper_1802_02868_amd.workloads.base_params)."""
+
+    def __init__(self, params: dict, x_faces, y_faces, phi0, ux0, uy0, p0):
+        L = lib()
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        self._xf, self._yf = _f64(x_faces), _f64(y_faces)
+        P = OrcParams()
+        for name, _ in OrcParams._fields_:
+            if name in ("x_faces", "y_faces"):
+                continue
+            setattr(P, name, params[name])
+        P.x_faces, P.y_faces = _ptr(self._xf), _ptr(self._yf)
+        shape = (self.ny, self.nx)
+        arrs = [_f64(a).reshape(shape) for a in (phi0, ux0, uy0, p0)]
+        h = L.orc_create(ctypes.byref(P), *[_ptr(a) for a in arrs])
+        if not h:
+            raise ValueError(L.orc_last_error().decode())
+        self._h = h
+
+    @classmethod
+    def from_case(cls, case, **over):
+        p = dict(case.params)
+        p.update(over)
+        return cls(p, case.x_faces, case.y_faces, case.phi0, case.ux0, case.uy0, case.p0)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().orc_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    @property
+    def dt(self):
+        return lib().orc_dt(self._h)
+
+    @property
+    def nstep(self):
+        return lib().orc_step_count(self._h)
+
+    def step(self, n=1):
+        lib().orc_step(self._h, int(n))
+
+    def moments(self):
+        shape = (self.ny, self.nx)
+        out = [np.empty(shape) for _ in range(6)]
+        lib().orc_moments(self._h, *[_ptr(a) for a in out])
+        return dict(zip(("phi", "rho", "ux", "uy", "p", "mu"), out))
+
+    def monitors(self):
+        out = np.empty(6)
+        lib().orc_monitors(self._h, _ptr(out))
+        return out
+
+    def pops(self):
+        out = np.empty((18, self.ny, self.nx))
+        lib().orc_get_pops(self._h, _ptr(out))
+        return out
+
+    def set_pops(self, a):
+        a = _f64(a).reshape(18, self.ny, self.nx)
+        lib().orc_set_pops(self._h, _ptr(a))
+
+    def point_eq(self, inp):
+        inp = _f64(inp)
+        out = [np.empty(9) for _ in range(4)]
+        lib().orc_point_eq(self._h, _ptr(inp), *[_ptr(a) for a in out])
+        return out
+
+    def deriv(self, axis, field):
+        field = _f64(field).reshape(self.ny, self.nx)
+        d1, d2 = np.empty_like(field), np.empty_like(field)
+        lib().orc_deriv(self._h, int(axis), _ptr(field), _ptr(d1), _ptr(d2))
+        return d1, d2
+
+    def cell_transforms(self):
+        b = np.empty((18, self.ny, self.nx))
+        t = np.empty_like(b)
+        lib().orc_cell_transforms(self._h, _ptr(b), _ptr(t))
+        return b, t
+
+    def reconstruct(self, barp):
+        barp = _f64(barp).reshape(18, self.ny, self.nx)
+        fx = np.empty((18, self.ny, self.nx + 1))
+        fy = np.empty((18, self.ny + 1, self.nx))
+        lib().orc_reconstruct(self._h, _ptr(barp), _ptr(fx), _ptr(fy))
+        return fx, fy
+
+    def face_dists(self):
+        fx = np.empty((18, self.ny, self.nx + 1))
+        fy = np.empty((18, self.ny + 1, self.nx))
+        lib().orc_face_dists(self._h, _ptr(fx), _ptr(fy))
+        return fx, fy

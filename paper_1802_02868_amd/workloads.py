@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs for the two-phase DUGKS step: meshes, initial
+fields and physical -> solver parameter helpers.
+
+This module computes none of the scheme's arithmetic; it only builds the
+arrays and the parameter dictionaries that both the HIP path and the test
+oracle receive, so that the two see bit-identical inputs.
+
+Test problems follow Sec. 3 of Zhang, Yang & Guo (arXiv:1802.02868):
+stationary drop (Sec. 3.1, eq. droplet), layered Poiseuille flow on a
+tanh-stretched mesh (Sec. 3.2, stretched-mesh formula), rising bubble
+(Sec. 3.3, eq. dimensionless) and Rayleigh-Taylor instability (Sec. 3.4).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+RT_DEFAULT = 1.0 / 3.0  # Sec. 3: RT fixed at 1/3
+
+
+def uniform_faces(n: int, x0: float = 0.0, dx: float = 1.0) -> np.ndarray:
+    """n+1 equally spaced face coordinates starting at x0."""
+    return x0 + dx * np.arange(n + 1, dtype=np.float64)
+
+
+def stretched_faces(n: int, eps: float, half_width: float = 1.0) -> np.ndarray:
+    """Face coordinates of the layered-Poiseuille mesh (Sec. 3.2): two tanh
+    stretched halves, clustered at the walls y = +-H and at y = 0.
+
+    Reading of the garbled index range: faces k = -n/2..n/2, with
+    xi_k = +-1/2 + tanh(eps (k/(n/2) -+ 1/2)) / (2 tanh(eps/2)), y_k = H xi_k;
+    cell centres are face midpoints."""
+    if n % 2:
+        raise ValueError("stretched mesh needs an even cell count")
+    m = n // 2
+    k = np.arange(-m, m + 1, dtype=np.float64)
+    s = k / m
+    t2 = 2.0 * math.tanh(eps / 2.0)
+    xi = np.where(k >= 0, 0.5 + np.tanh(eps * (s - 0.5)) / t2,
+                  -0.5 + np.tanh(eps * (s + 0.5)) / t2)
+    xi[m] = 0.0
+    xi[0], xi[-1] = -1.0, 1.0
+    return half_width * xi
+
+
+def centres(faces: np.ndarray) -> np.ndarray:
+    return 0.5 * (faces[:-1] + faces[1:])
+
+
+def beta_kappa(sigma: float, width: float, phi_a: float = 1.0, phi_b: float = 0.0):
+    """Invert eqs. thickness and sigma: W = sqrt(8 kappa/beta)/(phi_A-phi_B),
+    sigma = |phi_A-phi_B|^3 sqrt(2 kappa beta)/6."""
+    d = abs(phi_a - phi_b)
+    beta = 12.0 * sigma / (width * d ** 4)
+    kappa = 1.5 * sigma * width / d ** 2
+    return beta, kappa
+
+
+def tanh_profile(dist, width, phi_a=1.0, phi_b=0.0):
+    """Flat-interface equilibrium profile (eq. equilibriuminterface, first
+    term read as (phi_A+phi_B)/2 as in eq. droplet); dist > 0 inside A."""
+    return 0.5 * (phi_a + phi_b) + 0.5 * (phi_a - phi_b) * np.tanh(2.0 * np.asarray(dist) / width)
+
+
+def bubble_numbers(g, rho_heavy, rho_light, diameter, sigma, mu_heavy):
+    """Eotvos, Morton and Reynolds numbers of eq. dimensionless (fluid B is
+    the surrounding heavy fluid)."""
+    dr = rho_heavy - rho_light
+    eo = g * dr * diameter ** 2 / sigma
+    mo = g * dr * mu_heavy ** 4 / (rho_heavy ** 2 * sigma ** 3)
+    re = math.sqrt(g * rho_heavy * dr * diameter ** 3) / mu_heavy
+    return eo, mo, re
+
+
+def bubble_scales(eo, mo, diameter, rho_l=1.0, rho_g=1e-3, u_ref=0.04):
+    """Given Eo and Mo, fix sqrt(g D) = u_ref and solve eq. dimensionless for
+    g, sigma and the liquid viscosity."""
+    g = u_ref ** 2 / diameter
+    dr = rho_l - rho_g
+    sigma = g * dr * diameter ** 2 / eo
+    mu_l = (mo * rho_l ** 2 * sigma ** 3 / (g * dr)) ** 0.25
+    return g, sigma, mu_l / rho_l
+
+
+@dataclass
+class Case:
+    """One synthetic problem: solver parameters plus initial fields."""
+    name: str
+    params: dict
+    x_faces: np.ndarray
+    y_faces: np.ndarray
+    phi0: np.ndarray
+    ux0: np.ndarray
+    uy0: np.ndarray
+    p0: np.ndarray
+    steps: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nx(self):
+        return self.params["nx"]
+
+    @property
+    def ny(self):
+        return self.params["ny"]
+
+
+def base_params(**kw) -> dict:
+    p = dict(nx=0, ny=0, bc_x=0, bc_y=0, recon=0, phi_clamp=0,
+             cfl=0.0, c_max=0.0, dt=0.0, rt=RT_DEFAULT,
+             tau_g=0.5, mobility=0.1, tau_f=0.0,
+             beta=0.0, kappa=0.0, phi_a=1.0, phi_b=0.0, rho_a=1.0, rho_b=1.0,
+             nu_a=0.1, nu_b=0.1, gx=0.0, gy=0.0, rho_ref=0.0)
+    p.update(kw)
+    return p
+
+
+def drop_case(n=64, radius=16.0, width=4.0, sigma=1e-3, rho_a=1.0, rho_b=0.1, nu=0.1,
+              mobility=0.1, cfl=0.5, c_max=1.0, noise=1e-6, seed=1234, steps=1000,
+              tau_f=0.0, recon=0, centre=None) -> Case:
+    """Stationary drop, periodic square, drop = fluid A (phi_A = 1)."""
+    xf = uniform_faces(n)
+    yf = uniform_faces(n)
+    xc, yc = centres(xf), centres(yf)
+    c0 = (n / 2.0, n / 2.0) if centre is None else centre
+    X, Y = np.meshgrid(xc, yc)
+    r = np.sqrt((X - c0[0]) ** 2 + (Y - c0[1]) ** 2)
+    phi = tanh_profile(radius - r, width)
+    if noise:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        phi = phi + rng.uniform(-noise, noise, size=phi.shape)
+    beta, kappa = beta_kappa(sigma, width)
+    p = base_params(nx=n, ny=n, cfl=cfl, c_max=c_max, beta=beta, kappa=kappa,
+                    rho_a=rho_a, rho_b=rho_b, nu_a=nu, nu_b=nu, mobility=mobility,
+                    tau_f=tau_f, recon=recon)
+    z = np.zeros_like(phi)
+    return Case("drop%d" % n, p, xf, yf, np.ascontiguousarray(phi), z.copy(), z.copy(),
+                z.copy(), steps, dict(radius=radius, sigma=sigma, width=width))
+
+
+def poiseuille_case(nx=4, ny=128, eps=1.5, half=1.0, nu_a=0.01, nu_b=1.0, gx=1e-6,
+                    width_cells=4.0, sigma=1e-4, mobility=1e-2, cfl=0.5, steps=1000,
+                    stretched=True, recon=0) -> Case:
+    """Layered Poiseuille flow between walls y = -H and y = H, fluid A below
+    y = 0 and B above, driven by a body force along x."""
+    yf = stretched_faces(ny, eps, half) if stretched else uniform_faces(ny, -half, 2 * half / ny)
+    dy_min = float(np.min(np.diff(yf)))
+    xf = uniform_faces(nx, 0.0, 2.0 * half / 128.0 if stretched else 2.0 * half / ny)
+    width = width_cells * dy_min
+    yc = centres(yf)
+    phi1 = tanh_profile(-yc, width)
+    phi = np.ascontiguousarray(np.tile(phi1[:, None], (1, nx)))
+    beta, kappa = beta_kappa(sigma, width)
+    p = base_params(nx=nx, ny=ny, bc_x=0, bc_y=1, cfl=cfl, beta=beta, kappa=kappa,
+                    rho_a=1.0, rho_b=1.0, nu_a=nu_a, nu_b=nu_b, mobility=mobility,
+                    gx=gx, rho_ref=0.0, recon=recon)
+    z = np.zeros_like(phi)
+    return Case("poiseuille%dx%d" % (nx, ny), p, xf, yf, phi, z.copy(), z.copy(), z.copy(),
+                steps, dict(half=half, gx=gx, width=width))
+
+
+def poiseuille_profile(y, half, gx, mu_a, mu_b):
+    """Analytic layered Poiseuille profile (Sec. 3.2) with fluid A below y = 0
+    (the paper's formula with y -> -y), body force gx playing G."""
+    y = np.asarray(y, dtype=np.float64)
+    s = -y / half
+    r = (mu_a - mu_b) / (mu_a + mu_b)
+    ua = gx * half ** 2 / (2 * mu_a) * (-s ** 2 - s * r + 2 * mu_a / (mu_a + mu_b))
+    ub = gx * half ** 2 / (2 * mu_b) * (-s ** 2 - s * r + 2 * mu_b / (mu_a + mu_b))
+    return np.where(s >= 0, ua, ub)
+
+
+def rt_case(nx=256, ny=None, atwood=0.5, re=3000.0, pe=1000.0, sigma=5e-5, width=4.0,
+            amp_frac=0.1, cfl=0.283, steps=20000, recon=0) -> Case:
+    """Rayleigh-Taylor instability: heavy A (phi_A = 1) over light B, periodic
+    in x, walls in y, domain nx x 4nx with the interface at mid height."""
+    ny = 4 * nx if ny is None else ny
+    xf, yf = uniform_faces(nx), uniform_faces(ny)
+    xc, yc = centres(xf), centres(yf)
+    rho_b = 1.0
+    rho_a = rho_b * (1 + atwood) / (1 - atwood)
+    u_ref = 0.04
+    g = u_ref ** 2 / nx
+    nu = u_ref * nx / re
+    beta, kappa = beta_kappa(sigma, width)
+    lam = u_ref * nx / (pe * beta)
+    X, Y = np.meshgrid(xc, yc)
+    yi = ny / 2.0 + amp_frac * nx * np.cos(2 * np.pi * X / nx)
+    phi = np.ascontiguousarray(tanh_profile(Y - yi, width))
+    p = base_params(nx=nx, ny=ny, bc_x=0, bc_y=1, cfl=cfl, beta=beta, kappa=kappa,
+                    rho_a=rho_a, rho_b=rho_b, nu_a=nu, nu_b=nu, mobility=lam,
+                    gx=0.0, gy=-g, rho_ref=rho_b, recon=recon)
+    z = np.zeros_like(phi)
+    return Case("rt%dx%d" % (nx, ny), p, xf, yf, phi, z.copy(), z.copy(), z.copy(), steps,
+                dict(g=g, nu=nu, lam=lam))
+
+
+def bubble_case(nx, ny, eo, mo, rho_l=1.0, rho_g=1e-3, visc_ratio=100.0, width=4.0,
+                cfl=0.354, steps=5000, recon=0) -> Case:
+    """Rising bubble in a closed box (four walls): bubble = fluid A (phi_A = 1,
+    light), liquid = B.  Radius nx/8 centred at (nx/2, ny/4)."""
+    xf, yf = uniform_faces(nx), uniform_faces(ny)
+    xc, yc = centres(xf), centres(yf)
+    d = nx / 4.0
+    g, sigma, nu_l = bubble_scales(eo, mo, d, rho_l, rho_g)
+    beta, kappa = beta_kappa(sigma, width)
+    X, Y = np.meshgrid(xc, yc)
+    r = np.sqrt((X - nx / 2.0) ** 2 + (Y - ny / 4.0) ** 2)
+    phi = np.ascontiguousarray(tanh_profile(d / 2.0 - r, width))
+    tau_g = 0.5
+    lam = RT_DEFAULT * tau_g * 2.0  # eta = 2.0 as in Sec. 3.3
+    p = base_params(nx=nx, ny=ny, bc_x=1, bc_y=1, cfl=cfl, beta=beta, kappa=kappa,
+                    rho_a=rho_g, rho_b=rho_l, nu_a=nu_l / visc_ratio, nu_b=nu_l,
+                    mobility=lam, tau_g=tau_g, gx=0.0, gy=-g, rho_ref=rho_l, phi_clamp=1,
+                    recon=recon)
+    z = np.zeros_like(phi)
+    return Case("bubble%dx%d" % (nx, ny), p, xf, yf, phi, z.copy(), z.copy(), z.copy(),
+                steps, dict(g=g, sigma=sigma, nu_l=nu_l, eo=eo, mo=mo))
+
+
+BUBBLE_SIZES = ((128, 256), (160, 320), (192, 384), (256, 512))
+
+
+def bubble_batch(n=48, seed=4242, steps=5000):
+    """48 rising bubbles with seeded sizes, Eo ~ U[10, 100], log10 Mo ~ U[-5, -1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        nx, ny = BUBBLE_SIZES[int(rng.integers(0, len(BUBBLE_SIZES)))]
+        eo = float(rng.uniform(10.0, 100.0))
+        mo = float(10.0 ** rng.uniform(-5.0, -1.0))
+        c = bubble_case(nx, ny, eo, mo, steps=steps)
+        c.name = "bubble%02d_%dx%d" % (k, nx, ny)
+        out.append(c)
+    return out
+
+
+def drop_mass_median(phi, phi_a=1.0, phi_b=0.0):
+    """Droplet mass by the median level of the order parameter (Sec. 3.1):
+    number of cells with phi strictly above (phi_A + phi_B)/2."""
+    return int(np.count_nonzero(np.asarray(phi) > 0.5 * (phi_a + phi_b)))
+
+
+def table1_initial_phi(radius, n=100, width=4.0):
+    """Initial drop of Table 1: 100 x 100 cells with centres at integer
+    coordinates 0..99 and the drop centre at (50, 50)."""
+    c = np.arange(n, dtype=np.float64)
+    X, Y = np.meshgrid(c, c)
+    r = np.sqrt((X - 50.0) ** 2 + (Y - 50.0) ** 2)
+    return tanh_profile(radius - r, width)
+
+
+def config(name: str) -> Case:
+    """The five named workloads of the benchmark plan."""
+    if name == "drop64":
+        return drop_case()
+    if name == "poiseuille4x128":
+        return poiseuille_case(steps=250000)
+    if name == "rt256x1024":
+        return rt_case(256)
+    if name == "rt512x2048":
+        return rt_case(512, steps=2000)
+    raise KeyError(name)
