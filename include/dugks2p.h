@@ -1,0 +1,159 @@
+/*
+ * dugks2p.h -- C ABI of the MI355X (gfx950) two-phase DUGKS library.
+ *
+ * The library advances the discrete unified gas-kinetic scheme for
+ * immiscible two-phase flows of Zhang, Yang & Guo (arXiv:1802.02868): two
+ * D2Q9 populations per cell, f~ for pressure and momentum (eq. bgkf) and g~
+ * for the Cahn-Hilliard order parameter (eq. bgkg), on a tensor-product mesh
+ * that may be non-uniform in each axis (Sec. 3.2, App. B).  One call of
+ * dugks2p_step performs the seven-step procedure at the end of Sec. 2.2 once
+ * per time step, entirely in HIP kernels on the caller's stream.
+ *
+ * Conventions for every entry point:
+ *   - return value: DUGKS2P_OK (0) or a negative DUGKS2P_E* code; the
+ *     library never aborts or exits.  dugks2p_last_error() returns a
+ *     thread-local message describing the last failure of this thread.
+ *   - "device" pointers are HIP device allocations on the handle's device
+ *     (for instance torch CUDA tensors); "host" pointers are host memory.
+ *   - the caller owns every buffer it passes; the library owns the handle
+ *     and, unless params.workspace is given, its device workspace.
+ *   - fields are FP64, row-major [ny][nx] with x fastest; cell centres are
+ *     midpoints of consecutive faces.
+ *   - work is enqueued on the stream given at creation; functions that
+ *     return host data synchronise that stream.  A handle is not thread safe.
+ */
+#ifndef DUGKS2P_H
+#define DUGKS2P_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DUGKS2P_ABI_VERSION 1
+
+enum {
+  DUGKS2P_OK = 0,
+  DUGKS2P_EINVAL = -1,      /* invalid argument; nothing was enqueued        */
+  DUGKS2P_ENOMEM = -2,      /* device allocation failed or workspace too small */
+  DUGKS2P_EHIP = -3,        /* a HIP runtime call failed                     */
+  DUGKS2P_ENONFINITE = -4,  /* a population became NaN or infinite            */
+  DUGKS2P_EUNSUPPORTED = -5 /* valid request this build cannot perform        */
+};
+
+enum { DUGKS2P_BC_PERIODIC = 0, DUGKS2P_BC_WALL = 1 };
+enum { DUGKS2P_FP64 = 0, DUGKS2P_FP32_STATE = 1 };
+enum { DUGKS2P_RECON_CENTRAL = 0, DUGKS2P_RECON_UPWIND = 1 };
+enum { DUGKS2P_KERNEL_AUTO = 0, DUGKS2P_KERNEL_STAGED = 1, DUGKS2P_KERNEL_FUSED = 2 };
+
+/*
+ * Problem statement (Sec. 2 and 3 of the paper).
+ *   x_faces, y_faces: host, nx+1 / ny+1 strictly increasing coordinates,
+ *                copied at creation (tensor-product mesh, App. B).
+ *   bc_x, bc_y:  DUGKS2P_BC_PERIODIC, or DUGKS2P_BC_WALL = bounce-back
+ *                no-slip walls at both ends of that axis (needs >= 2 cells).
+ *   dt:          > 0 explicit time step; otherwise dt = cfl * h_min / c_max
+ *                (eq. cfl) with h_min the smallest cell width of either axis
+ *                and c_max = sqrt(6 rt) when c_max <= 0 (Sec. 3).
+ *   rt:          RT = c_s^2; discrete speed c = sqrt(3 RT) (eq. D2Q9).
+ *   tau_g:       relaxation time of g; mobility lambda gives
+ *                eta = lambda / (c_s^2 tau_g) (eq. kineticandmobility).
+ *   tau_f:       > 0 uniform relaxation time of f; otherwise
+ *                tau_f = mu_d(phi) / (rho c_s^2) with the mixture viscosity
+ *                of eq. mixvis built from nu_a, nu_b.
+ *   beta, kappa: double-well and gradient coefficients (eqs. doublewell,
+ *                chemicalpotential).
+ *   phi_a, phi_b, rho_a, rho_b: bulk order parameters and densities
+ *                (eqs. oderrho, Gama).
+ *   gx, gy, rho_ref: body force F_b = (rho - rho_ref) (gx, gy).
+ *   phi_clamp:   nonzero clamps phi into [phi_b, phi_a] inside rho() and
+ *                mu_d() only (never in the state).
+ *   precision:   DUGKS2P_FP64 (state and arithmetic in double) or
+ *                DUGKS2P_FP32_STATE (float state, float arithmetic except the
+ *                order parameter sum and the chemical potential, in double).
+ *   recon:       face reconstruction of Step 3: CENTRAL = linear
+ *                interpolation of value and gradient (the paper's choice);
+ *                UPWIND = expansion from the upwind cell.
+ *   kernel:      DUGKS2P_KERNEL_* implementation choice (AUTO = fused).
+ *   workspace:   optional device memory of at least
+ *                dugks2p_workspace_bytes(params) bytes, 256-byte aligned,
+ *                owned by the caller and used instead of a library allocation.
+ */
+typedef struct {
+  int32_t abi_version; /* DUGKS2P_ABI_VERSION */
+  int32_t nx, ny;
+  int32_t bc_x, bc_y;
+  int32_t precision;
+  int32_t recon;
+  int32_t phi_clamp;
+  int32_t kernel;
+  int32_t reserved0;
+  const double *x_faces;
+  const double *y_faces;
+  double cfl, c_max, dt, rt;
+  double tau_g, mobility, tau_f;
+  double beta, kappa;
+  double phi_a, phi_b, rho_a, rho_b, nu_a, nu_b;
+  double gx, gy, rho_ref;
+  void *workspace;
+  size_t workspace_bytes;
+} dugks2p_params;
+
+typedef struct dugks2p dugks2p;
+
+/* Bytes of device workspace the handle needs for these parameters
+ * (0 if the parameters are invalid). */
+size_t dugks2p_workspace_bytes(const dugks2p_params *params);
+
+/*
+ * Step 1 of Sec. 2.2: validate the parameters, build the mesh tables, and
+ * initialise f~, g~ from the initial fields phi0, ux0, uy0, p0 (device, FP64,
+ * [ny][nx]) with f = f^eq, g = g^eq, i.e. tilde = eq - (dt/2) F (eq. auxf).
+ * hip_stream is a hipStream_t (NULL = default stream).  On success *out
+ * holds a new handle; on failure *out is NULL and no work is left enqueued.
+ */
+int dugks2p_create(const dugks2p_params *params, const double *phi0, const double *ux0,
+                   const double *uy0, const double *p0, void *hip_stream, dugks2p **out);
+
+/* Advance nsteps >= 0 time steps (Steps 2-7 of Sec. 2.2), asynchronously on
+ * the handle's stream. */
+int dugks2p_step(dugks2p *h, int64_t nsteps);
+
+/* Cell fields at the current time (Step 7: eqs. oderrho, phi, u, P): writes
+ * phi, rho, ux, uy, p (device, FP64, [ny][nx]); any pointer may be NULL. */
+int dugks2p_moments(dugks2p *h, double *phi, double *rho, double *ux, double *uy, double *p);
+
+/* Monitors at the current time, host out[6]: total order parameter
+ * sum phi |V|, kinetic energy sum rho |u|^2 |V| / 2, free energy of eq.
+ * freeenergyfunction, max |u|, number of non-finite populations, step
+ * count.  Reductions are FP64 with a fixed order (deterministic).  Syncs the
+ * stream.  Returns DUGKS2P_ENONFINITE if the count is nonzero (out is still
+ * filled). */
+int dugks2p_monitors(dugks2p *h, double out[6]);
+
+/* The 18 populations (q = 0..8 f~, 9..17 g~) converted to FP64,
+ * [18][ny][nx], into / from device memory. */
+int dugks2p_get_populations(dugks2p *h, double *dst);
+int dugks2p_set_populations(dugks2p *h, const double *src);
+
+/* Raw state snapshot for checkpoint / restart: dugks2p_state_bytes() bytes
+ * of device memory; restoring a snapshot reproduces the run bit for bit. */
+size_t dugks2p_state_bytes(const dugks2p *h);
+int dugks2p_get_state(dugks2p *h, void *dst);
+int dugks2p_set_state(dugks2p *h, const void *src);
+
+/* Time step actually used, and step counter. */
+double dugks2p_dt(const dugks2p *h);
+int64_t dugks2p_step_count(const dugks2p *h);
+
+/* Release the handle and its device memory (NULL is accepted). */
+int dugks2p_destroy(dugks2p *h);
+
+const char *dugks2p_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,388 @@
+// dugks2p.hip -- C-ABI runtime of the MI355X two-phase DUGKS library
+// (declarations and argument contracts in include/dugks2p.h).
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+
+#include <string>
+#include <vector>
+
+#include "dugks2p_fused.hpp"
+#include "dugks2p_host.hpp"
+
+using namespace dg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess)                                                            \
+      return fail(DUGKS2P_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+// One thread per (i, j) in a 64 x 4 block.
+template <class F>
+__global__ __launch_bounds__(256) void k_grid(F f, int n0, int n1) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  if (i < n0 && j < n1) f(i, j);
+}
+
+struct GpuEx {
+  hipStream_t s;
+  hipError_t err;
+  template <class F>
+  void grid(const F &f, int n0, int n1) {
+    if (n0 <= 0 || n1 <= 0) return;
+    const dim3 b(64, 4), g((n0 + 63) / 64, (n1 + 3) / 4);
+    hipLaunchKernelGGL(k_grid<F>, g, b, 0, s, f, n0, n1);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess && err == hipSuccess) err = e;
+  }
+};
+
+// Monitor partial sums: one 64 x 4 block of cells per workgroup, fixed-order
+// tree in LDS, one partial per block.  A single-workgroup pass then adds the
+// partials in block order, so the result is deterministic.
+template <class T>
+__global__ __launch_bounds__(256) void k_mon_partial(Consts K, Work w, const T *st,
+                                                     double *part) {
+  __shared__ double sh[5][256];
+  const int t = threadIdx.y * 64 + threadIdx.x;
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i < K.nx && j < K.ny) monitor_terms(K, w, st, i, j, v);
+  for (int m = 0; m < 5; ++m) sh[m][t] = v[m];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      for (int m = 0; m < 5; ++m) {
+        if (m == 3)
+          sh[m][t] = sh[m][t] > sh[m][t + s] ? sh[m][t] : sh[m][t + s];
+        else
+          sh[m][t] = sh[m][t] + sh[m][t + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    for (int m = 0; m < 5; ++m) part[5 * b + m] = sh[m][0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mon_final(const double *part, long long nb, double *out) {
+  __shared__ double sh[5][256];
+  const int t = threadIdx.x;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (long long b = t; b < nb; b += 256)
+    for (int m = 0; m < 5; ++m) {
+      const double x = part[5 * b + m];
+      if (m == 3)
+        v[m] = v[m] > x ? v[m] : x;
+      else
+        v[m] += x;
+    }
+  for (int m = 0; m < 5; ++m) sh[m][t] = v[m];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s)
+      for (int m = 0; m < 5; ++m) {
+        if (m == 3)
+          sh[m][t] = sh[m][t] > sh[m][t + s] ? sh[m][t] : sh[m][t + s];
+        else
+          sh[m][t] = sh[m][t] + sh[m][t + s];
+      }
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int m = 0; m < 5; ++m) out[m] = sh[m][0];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pops_out(Consts K, const T *st, double *dst) {
+  const i64 n = (i64)K.nx * K.ny;
+  for (i64 k = (i64)blockIdx.x * 256 + threadIdx.x; k < 18 * n; k += (i64)gridDim.x * 256) {
+    const i64 q = k / n, r = k - q * n;
+    const i64 j = r / K.nx, i = r - j * K.nx;
+    dst[k] = (double)st[q * K.plane + j * K.ld + i];
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pops_in(Consts K, const double *src, T *st) {
+  const i64 n = (i64)K.nx * K.ny;
+  for (i64 k = (i64)blockIdx.x * 256 + threadIdx.x; k < 18 * n; k += (i64)gridDim.x * 256) {
+    const i64 q = k / n, r = k - q * n;
+    const i64 j = r / K.nx, i = r - j * K.nx;
+    st[q * K.plane + j * K.ld + i] = (T)src[k];
+  }
+}
+
+}  // namespace
+
+struct dugks2p {
+  Consts K;
+  Layout L;
+  hipStream_t stream;
+  int precision, kernel;
+  unsigned char *ws;
+  bool own_ws;
+  void *state[2];
+  int cur;
+  Work w;
+  double *mon_part, *mon_out;
+  int64_t nstep;
+  FusedPlan fp;
+};
+
+namespace {
+
+bool use_staged(const dugks2p_params *P) { return P->kernel != DUGKS2P_KERNEL_FUSED; }
+
+struct Prepared {
+  AxisHost ax, ay;
+  Consts K;
+  Layout L;
+};
+
+std::string prepare(const dugks2p_params *P, Prepared &pr) {
+  std::string e = validate(P);
+  if (!e.empty()) return e;
+  build_axis(pr.ax, P->nx, P->bc_x, P->x_faces);
+  build_axis(pr.ay, P->ny, P->bc_y, P->y_faces);
+  pr.K = make_consts(P, pr.ax, pr.ay);
+  if (!(pr.K.dt > 0.0) || !isfinite(pr.K.dt)) return "time step is not positive";
+  if (P->precision == DUGKS2P_FP32_STATE && use_staged(P))
+    return "the staged kernels are FP64 only";
+  if (!use_staged(P)) return "the fused kernel is not available in this build";
+  pr.L = make_layout(pr.K, pr.ax, pr.ay, P->precision, use_staged(P));
+  return std::string();
+}
+
+template <class T>
+int launch_step(dugks2p *h) {
+  GpuEx ex{h->stream, hipSuccess};
+  const T *src = (const T *)h->state[h->cur];
+  T *dst = (T *)h->state[1 - h->cur];
+  if (h->kernel == DUGKS2P_KERNEL_STAGED)
+    seq_staged_step(ex, h->K, h->w, src, dst);
+  else
+    fused_step<T>(h->fp, h->K, src, dst, h->stream, ex.err);
+  if (ex.err != hipSuccess)
+    return fail(DUGKS2P_EHIP, std::string("kernel launch: ") + hipGetErrorString(ex.err));
+  h->cur = 1 - h->cur;
+  h->nstep++;
+  return DUGKS2P_OK;
+}
+
+template <class T>
+int launch_macros(dugks2p *h) {
+  GpuEx ex{h->stream, hipSuccess};
+  seq_macros(ex, h->K, h->w, (const T *)h->state[h->cur]);
+  if (ex.err != hipSuccess)
+    return fail(DUGKS2P_EHIP, std::string("kernel launch: ") + hipGetErrorString(ex.err));
+  return DUGKS2P_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dugks2p_workspace_bytes(const dugks2p_params *P) {
+  Prepared pr;
+  if (!prepare(P, pr).empty()) return 0;
+  return pr.L.total;
+}
+
+int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux0,
+                   const double *uy0, const double *p0, void *hip_stream, dugks2p **out) {
+  if (!out) return fail(DUGKS2P_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!phi0 || !ux0 || !uy0 || !p0) return fail(DUGKS2P_EINVAL, "initial field pointer is NULL");
+  Prepared pr;
+  const std::string e = prepare(P, pr);
+  if (!e.empty()) return fail(DUGKS2P_EINVAL, e);
+  if (P->workspace && P->workspace_bytes < pr.L.total)
+    return fail(DUGKS2P_ENOMEM, "workspace smaller than dugks2p_workspace_bytes()");
+  if (P->workspace && ((uintptr_t)P->workspace & 255))
+    return fail(DUGKS2P_EINVAL, "workspace must be 256-byte aligned");
+
+  dugks2p *h = new dugks2p();
+  h->K = pr.K;
+  h->L = pr.L;
+  h->stream = (hipStream_t)hip_stream;
+  h->precision = P->precision;
+  h->kernel = use_staged(P) ? DUGKS2P_KERNEL_STAGED : DUGKS2P_KERNEL_FUSED;
+  h->cur = 0;
+  h->nstep = 0;
+  if (P->workspace) {
+    h->ws = (unsigned char *)P->workspace;
+    h->own_ws = false;
+  } else {
+    void *p = nullptr;
+    const hipError_t err = hipMalloc(&p, pr.L.total);
+    if (err != hipSuccess) {
+      delete h;
+      return fail(DUGKS2P_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(err));
+    }
+    h->ws = (unsigned char *)p;
+    h->own_ws = true;
+  }
+  int rc = DUGKS2P_OK;
+  do {
+    std::vector<unsigned char> tb;
+    pack_axis(pr.ax, tb);
+    if (hipMemcpyAsync(h->ws + pr.L.tables[0], tb.data(), tb.size(), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess) { rc = fail(DUGKS2P_EHIP, "table upload"); break; }
+    // the staging vector must outlive the copy
+    if (hipStreamSynchronize(h->stream) != hipSuccess) { rc = fail(DUGKS2P_EHIP, "sync"); break; }
+    pack_axis(pr.ay, tb);
+    if (hipMemcpyAsync(h->ws + pr.L.tables[1], tb.data(), tb.size(), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess) { rc = fail(DUGKS2P_EHIP, "table upload"); break; }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) { rc = fail(DUGKS2P_EHIP, "sync"); break; }
+    h->K.ax[0] = bind_axis(pr.ax, h->ws + pr.L.tables[0]);
+    h->K.ax[1] = bind_axis(pr.ay, h->ws + pr.L.tables[1]);
+    h->w = bind_work(pr.L, h->K, h->ws);
+    h->state[0] = h->ws + pr.L.state[0];
+    h->state[1] = h->ws + pr.L.state[1];
+    h->mon_part = (double *)(h->ws + pr.L.mon);
+    h->mon_out = h->mon_part + 5 * pr.L.mon_blocks;
+    if (hipMemsetAsync(h->state[0], 0, pr.L.state_bytes, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->state[1], 0, pr.L.state_bytes, h->stream) != hipSuccess) {
+      rc = fail(DUGKS2P_EHIP, "state clear");
+      break;
+    }
+    h->fp = make_fused_plan(h->K, P->precision);
+    GpuEx ex{h->stream, hipSuccess};
+    if (P->precision == DUGKS2P_FP64)
+      seq_init(ex, h->K, h->w, phi0, ux0, uy0, p0, (double *)h->state[0]);
+    else
+      seq_init(ex, h->K, h->w, phi0, ux0, uy0, p0, (float *)h->state[0]);
+    if (ex.err != hipSuccess) {
+      rc = fail(DUGKS2P_EHIP, std::string("init launch: ") + hipGetErrorString(ex.err));
+      break;
+    }
+  } while (0);
+  if (rc != DUGKS2P_OK) {
+    hipStreamSynchronize(h->stream);
+    if (h->own_ws) hipFree(h->ws);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return DUGKS2P_OK;
+}
+
+int dugks2p_step(dugks2p *h, int64_t nsteps) {
+  if (!h) return fail(DUGKS2P_EINVAL, "handle is NULL");
+  if (nsteps < 0) return fail(DUGKS2P_EINVAL, "nsteps must be >= 0");
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const int rc = h->precision == DUGKS2P_FP64 ? launch_step<double>(h) : launch_step<float>(h);
+    if (rc) return rc;
+  }
+  return DUGKS2P_OK;
+}
+
+int dugks2p_moments(dugks2p *h, double *phi, double *rho, double *ux, double *uy, double *p) {
+  if (!h) return fail(DUGKS2P_EINVAL, "handle is NULL");
+  const int rc = h->precision == DUGKS2P_FP64 ? launch_macros<double>(h) : launch_macros<float>(h);
+  if (rc) return rc;
+  GpuEx ex{h->stream, hipSuccess};
+  ex.grid(FMoments{h->K, h->w, phi, rho, ux, uy, p}, h->K.nx, h->K.ny);
+  if (ex.err != hipSuccess)
+    return fail(DUGKS2P_EHIP, std::string("moments launch: ") + hipGetErrorString(ex.err));
+  return DUGKS2P_OK;
+}
+
+int dugks2p_monitors(dugks2p *h, double out[6]) {
+  if (!h || !out) return fail(DUGKS2P_EINVAL, "NULL argument");
+  int rc = h->precision == DUGKS2P_FP64 ? launch_macros<double>(h) : launch_macros<float>(h);
+  if (rc) return rc;
+  const dim3 b(64, 4), g((h->K.nx + 63) / 64, (h->K.ny + 3) / 4);
+  const long long nb = (long long)g.x * g.y;
+  if (nb > (long long)h->L.mon_blocks) return fail(DUGKS2P_EHIP, "monitor partial buffer too small");
+  if (h->precision == DUGKS2P_FP64)
+    hipLaunchKernelGGL(k_mon_partial<double>, g, b, 0, h->stream, h->K, h->w,
+                       (const double *)h->state[h->cur], h->mon_part);
+  else
+    hipLaunchKernelGGL(k_mon_partial<float>, g, b, 0, h->stream, h->K, h->w,
+                       (const float *)h->state[h->cur], h->mon_part);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_mon_final, dim3(1), dim3(256), 0, h->stream, h->mon_part, nb, h->mon_out);
+  HIPCHK(hipGetLastError());
+  double v[5];
+  HIPCHK(hipMemcpyAsync(v, h->mon_out, sizeof v, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out[0] = v[0];
+  out[1] = v[1];
+  out[2] = v[2];
+  out[3] = sqrt(v[3]);
+  out[4] = v[4];
+  out[5] = (double)h->nstep;
+  if (v[4] > 0.0) return fail(DUGKS2P_ENONFINITE, "non-finite populations in the state");
+  return DUGKS2P_OK;
+}
+
+int dugks2p_get_populations(dugks2p *h, double *dst) {
+  if (!h || !dst) return fail(DUGKS2P_EINVAL, "NULL argument");
+  if (h->precision == DUGKS2P_FP64)
+    hipLaunchKernelGGL(k_pops_out<double>, dim3(1024), dim3(256), 0, h->stream, h->K,
+                       (const double *)h->state[h->cur], dst);
+  else
+    hipLaunchKernelGGL(k_pops_out<float>, dim3(1024), dim3(256), 0, h->stream, h->K,
+                       (const float *)h->state[h->cur], dst);
+  HIPCHK(hipGetLastError());
+  return DUGKS2P_OK;
+}
+
+int dugks2p_set_populations(dugks2p *h, const double *src) {
+  if (!h || !src) return fail(DUGKS2P_EINVAL, "NULL argument");
+  if (h->precision == DUGKS2P_FP64)
+    hipLaunchKernelGGL(k_pops_in<double>, dim3(1024), dim3(256), 0, h->stream, h->K, src,
+                       (double *)h->state[h->cur]);
+  else
+    hipLaunchKernelGGL(k_pops_in<float>, dim3(1024), dim3(256), 0, h->stream, h->K, src,
+                       (float *)h->state[h->cur]);
+  HIPCHK(hipGetLastError());
+  return DUGKS2P_OK;
+}
+
+size_t dugks2p_state_bytes(const dugks2p *h) { return h ? h->L.state_bytes : 0; }
+
+int dugks2p_get_state(dugks2p *h, void *dst) {
+  if (!h || !dst) return fail(DUGKS2P_EINVAL, "NULL argument");
+  HIPCHK(hipMemcpyAsync(dst, h->state[h->cur], h->L.state_bytes, hipMemcpyDeviceToDevice,
+                        h->stream));
+  return DUGKS2P_OK;
+}
+
+int dugks2p_set_state(dugks2p *h, const void *src) {
+  if (!h || !src) return fail(DUGKS2P_EINVAL, "NULL argument");
+  HIPCHK(hipMemcpyAsync(h->state[h->cur], src, h->L.state_bytes, hipMemcpyDeviceToDevice,
+                        h->stream));
+  return DUGKS2P_OK;
+}
+
+double dugks2p_dt(const dugks2p *h) { return h ? h->K.dt : 0.0; }
+int64_t dugks2p_step_count(const dugks2p *h) { return h ? h->nstep : -1; }
+
+int dugks2p_destroy(dugks2p *h) {
+  if (!h) return DUGKS2P_OK;
+  hipStreamSynchronize(h->stream);
+  if (h->own_ws) hipFree(h->ws);
+  delete h;
+  return DUGKS2P_OK;
+}
+
+const char *dugks2p_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

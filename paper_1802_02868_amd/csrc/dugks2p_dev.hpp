@@ -1,0 +1,539 @@
+// dugks2p_dev.hpp -- device arithmetic of the two-phase DUGKS step
+// (Zhang, Yang & Guo, arXiv:1802.02868, Sec. 2.2).
+//
+// Every function here is __host__ __device__ so that the exact same code runs
+// in the gfx950 kernels and in a host build used for testing the kernel logic.
+// FP64 arithmetic is written in a fixed evaluation order and compiled without
+// FMA contraction, so the FP64 path is reproducible bit for bit across the
+// staged and fused kernels.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define DFN __host__ __device__ __forceinline__
+#else
+#define DFN inline
+#endif
+
+namespace dg {
+
+typedef long long i64;
+
+// D2Q9 (eq. D2Q9): 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1)
+// 7:(-1,-1) 8:(1,-1); opposites 1-3, 2-4, 5-7, 6-8.
+DFN int ex_of(int i) { return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0); }
+DFN int ey_of(int i) { return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0); }
+DFN int opp_of(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5); }
+
+// One mesh axis (App. B tensor-product mesh).  Cell k: neighbours lo/hi
+// (periodic wrap, or the cell itself standing for the mirror ghost across a
+// wall), three-point weights (minus, centre, plus) of the first and second
+// derivative and of the population gradient.  Face k is the low face of cell
+// k; fl/fr are the cells on either side (-1 = wall).
+struct Axis {
+  int n, bc, nf, pad;
+  const int *lo, *hi, *fl, *fr;
+  const double *d1, *d2, *pg, *rdt, *w;
+  const double *fwl, *fwr, *finv, *foffl, *foffr;
+};
+
+struct Consts {
+  int nx, ny, ld, nfx, nfy, recon, phi_clamp, pad0;
+  i64 plane;   // ny * ld: stride between populations / fields
+  i64 xplane;  // ny * nfx: stride of x-face arrays
+  i64 yplane;  // nfy * ld: stride of y-face arrays
+  double dt, h, hdt, hh, cs2, k1, k2, k3, eta, gam, inv_dphi, drho, mumu, mu_a, mu_b;
+  double c4b, phimid, lo_phi, hi_phi, tau_g, tau_f, mobility, kappa, beta;
+  double phi_a, phi_b, rho_a, rho_b, gx, gy, rho_ref;
+  double hdtcs2, hhcs2, ch0;
+  double w9[9], chi[9], wics2[9], xi0[9], xi1[9];
+  double gca, gcb, gcc, gk1, gk2, gk3;  // transforms of g (constant tau_g)
+  Axis ax[2];
+};
+
+// Macroscopic state at a point: input of the equilibria and sources.
+template <class R>
+struct Mac {
+  R phi, rho, ux, uy, p, mu, grx, gry, D, Fx, Fy, gpx, gpy, icr;
+};
+
+// eq. oderrho (optional clamp of phi inside rho() only)
+template <class R>
+DFN R rho_of(const Consts &K, R phi) {
+  R ph = phi;
+  if (K.phi_clamp) ph = ph < (R)K.lo_phi ? (R)K.lo_phi : (ph > (R)K.hi_phi ? (R)K.hi_phi : ph);
+  return ((ph - (R)K.phi_b) * (R)K.rho_a + ((R)K.phi_a - ph) * (R)K.rho_b) * (R)K.inv_dphi;
+}
+
+// eqs. kineticandmobility and mixvis: tau_f = mu_d / (rho c_s^2)
+template <class R>
+DFN R tauf_of(const Consts &K, R phi, R rho) {
+  if (K.tau_f > 0.0) return (R)K.tau_f;
+  R ph = phi;
+  if (K.phi_clamp) ph = ph < (R)K.lo_phi ? (R)K.lo_phi : (ph > (R)K.hi_phi ? (R)K.hi_phi : ph);
+  const R mud = (R)K.mumu / ((ph - (R)K.phi_b) * (R)K.mu_b + ((R)K.phi_a - ph) * (R)K.mu_a);
+  return mud / (rho * (R)K.cs2);
+}
+
+// eqs. feq, geq, su, Hi, F, G at one point, direction i.
+template <class R>
+DFN void point_eq1(const Consts &K, const Mac<R> &m, R uu, int i, R &feq, R &geq, R &ff, R &fg) {
+  const R cs2 = (R)K.cs2;
+  const R wi = (R)K.w9[i], xx = (R)K.xi0[i], xy = (R)K.xi1[i];
+  const R eu = xx * m.ux + xy * m.uy;
+  const R si = wi * (eu * (R)K.k1 + eu * eu * (R)K.k2 - uu * (R)K.k3);
+  feq = wi * m.p + cs2 * m.rho * si;
+  const R Hi = (i == 0) ? m.phi - (R)K.ch0 * m.mu : (R)K.chi[i] * m.mu;
+  geq = Hi + m.phi * si;
+  const R G = wi + si;
+  const R cx = xx - m.ux, cy = xy - m.uy;
+  ff = cx * (m.Fx * G + si * cs2 * m.grx) + cy * (m.Fy * G + si * cs2 * m.gry) -
+       (R)K.wics2[i] * m.rho * (R)K.gam * m.D;
+  fg = m.phi * m.icr * (cx * (m.Fx - m.gpx) + cy * (m.Fy - m.gpy)) * G;
+}
+
+// Three-point stencil along x (axis 0) or y (axis 1) of a cell field with
+// row pitch ld.
+DFN double stx(const Consts &K, const double *w3, const double *F, int i, int j) {
+  const Axis &a = K.ax[0];
+  const double *w = w3 + 3 * i;
+  const i64 r = (i64)j * K.ld;
+  return w[0] * F[r + a.lo[i]] + w[1] * F[r + i] + w[2] * F[r + a.hi[i]];
+}
+DFN double sty(const Consts &K, const double *w3, const double *F, int i, int j) {
+  const Axis &a = K.ax[1];
+  const double *w = w3 + 3 * j;
+  return w[0] * F[(i64)a.lo[j] * K.ld + i] + w[1] * F[(i64)j * K.ld + i] +
+         w[2] * F[(i64)a.hi[j] * K.ld + i];
+}
+
+// Scratch fields of the staged step (all FP64, pitch ld, stride plane).
+struct Work {
+  double *phi, *rho, *mu, *dphx, *dphy, *dmux, *dmuy, *D, *Fx, *Fy, *ux, *uy, *p, *dpx, *dpy,
+      *tauf;
+  double *barp;   // 18 x plane
+  double *facex;  // 18 x xplane: [q][j][k]
+  double *facey;  // 18 x yplane: [q][k][i]
+};
+
+// ---------------------------------------------------------------------------
+// Staged step: one functor per stage, one call per cell or face.
+// ---------------------------------------------------------------------------
+
+// eq. phi and eq. oderrho
+template <class T>
+struct FPhi {
+  Consts K;
+  Work w;
+  const T *st;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    double acc = 0.0;
+    for (int q = 9; q < 18; ++q) acc += (double)st[q * K.plane + c];
+    w.phi[c] = acc;
+    w.rho[c] = rho_of<double>(K, acc);
+  }
+};
+
+// eq. chemicalpotential with the App. B Laplacian; grad phi.
+struct FMu {
+  Consts K;
+  Work w;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    const double ph = w.phi[c];
+    const double lap = stx(K, K.ax[0].d2, w.phi, i, j) + sty(K, K.ax[1].d2, w.phi, i, j);
+    w.mu[c] = K.c4b * (ph - K.phi_a) * (ph - K.phi_b) * (ph - K.phimid) - K.kappa * lap;
+    w.dphx[c] = stx(K, K.ax[0].d1, w.phi, i, j);
+    w.dphy[c] = sty(K, K.ax[1].d1, w.phi, i, j);
+  }
+};
+
+// grad mu, D = div(lambda grad mu), F, eq. u, eq. P.
+template <class T>
+struct FMacro {
+  Consts K;
+  Work w;
+  const T *st;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    w.dmux[c] = stx(K, K.ax[0].d1, w.mu, i, j);
+    w.dmuy[c] = sty(K, K.ax[1].d1, w.mu, i, j);
+    const double lapmu = stx(K, K.ax[0].d2, w.mu, i, j) + sty(K, K.ax[1].d2, w.mu, i, j);
+    const double D = K.mobility * lapmu;
+    w.D[c] = D;
+    const double ph = w.phi[c], rh = w.rho[c];
+    const double Fx = -ph * w.dmux[c] + (rh - K.rho_ref) * K.gx;
+    const double Fy = -ph * w.dmuy[c] + (rh - K.rho_ref) * K.gy;
+    w.Fx[c] = Fx;
+    w.Fy[c] = Fy;
+    double s0 = 0.0, jx = 0.0, jy = 0.0;
+    double f[9];
+    for (int q = 0; q < 9; ++q) f[q] = (double)st[q * K.plane + c];
+    for (int q = 0; q < 9; ++q) s0 += f[q];
+    for (int q = 0; q < 9; ++q) jx += K.xi0[q] * f[q];
+    for (int q = 0; q < 9; ++q) jy += K.xi1[q] * f[q];
+    const double icr = 1.0 / (K.cs2 * rh);
+    const double ux = (jx + K.hdtcs2 * Fx) * icr;
+    const double uy = (jy + K.hdtcs2 * Fy) * icr;
+    w.ux[c] = ux;
+    w.uy[c] = uy;
+    const double grx = K.drho * w.dphx[c], gry = K.drho * w.dphy[c];
+    w.p[c] = s0 + K.hdtcs2 * (ux * grx + uy * gry - K.gam * rh * D);
+  }
+};
+
+template <class R>
+DFN void cell_mac(const Consts &K, const Work &w, i64 c, Mac<R> &m) {
+  m.phi = (R)w.phi[c];
+  m.rho = (R)w.rho[c];
+  m.ux = (R)w.ux[c];
+  m.uy = (R)w.uy[c];
+  m.p = (R)w.p[c];
+  m.mu = (R)w.mu[c];
+  m.grx = (R)(K.drho * w.dphx[c]);
+  m.gry = (R)(K.drho * w.dphy[c]);
+  m.D = (R)w.D[c];
+  m.Fx = (R)w.Fx[c];
+  m.Fy = (R)w.Fy[c];
+  m.gpx = (R)w.dpx[c];
+  m.gpy = (R)w.dpy[c];
+  m.icr = (R)1.0 / ((R)K.cs2 * m.rho);
+}
+
+// grad p, tau_f, and Step 2 (eqs. relations1, relations2): bar+ into w.barp.
+template <class T>
+struct FCell {
+  Consts K;
+  Work w;
+  const T *st;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    w.dpx[c] = stx(K, K.ax[0].d1, w.p, i, j);
+    w.dpy[c] = sty(K, K.ax[1].d1, w.p, i, j);
+    const double tf = tauf_of<double>(K, w.phi[c], w.rho[c]);
+    w.tauf[c] = tf;
+    Mac<double> m;
+    cell_mac(K, w, c, m);
+    const double uu = m.ux * m.ux + m.uy * m.uy;
+    const double den = 1.0 / (2.0 * tf + K.dt);
+    const double fca = (2.0 * tf - K.h) * den, fcb = 3.0 * K.h * den, fcc = 3.0 * tf * K.h * den;
+    for (int i2 = 0; i2 < 9; ++i2) {
+      double feq, geq, ff, fg;
+      point_eq1(K, m, uu, i2, feq, geq, ff, fg);
+      const double tf_ = (double)st[i2 * K.plane + c];
+      const double tg_ = (double)st[(9 + i2) * K.plane + c];
+      w.barp[i2 * K.plane + c] = fca * tf_ + fcb * feq + fcc * ff;
+      w.barp[(9 + i2) * K.plane + c] = K.gca * tg_ + K.gcb * geq + K.gcc * fg;
+    }
+  }
+};
+
+// Population gradient (App. B first derivative, one-sided at a wall cell).
+DFN double pgx(const Consts &K, const double *A, int i, int j) {
+  return stx(K, K.ax[0].pg, A, i, j);
+}
+DFN double pgy(const Consts &K, const double *A, int i, int j) {
+  return sty(K, K.ax[1].pg, A, i, j);
+}
+
+// R5: value, normal derivative and tangential derivative of a cell field at
+// an interior face between cells L and R (weights of the face).
+struct FaceW {
+  double wl, wr, inv;
+};
+DFN void face_field(const FaceW &fw, double FL, double FR, double TL, double TR, double &v,
+                    double &dn, double &dt) {
+  v = fw.wl * FL + fw.wr * FR;
+  dn = (FR - FL) * fw.inv;
+  dt = fw.wl * TL + fw.wr * TR;
+}
+
+// Step 4 at a face: macros from bar (eq. conservedVariable with h), face
+// equilibria and sources, eq. original-function; wall: bounce-back of the
+// populations entering the fluid.  Inputs are the face fields.
+struct FaceFields {
+  double mu, D, gmx, gmy, gfx, gfy, gpx, gpy;
+};
+
+DFN void face_dist(const Consts &K, const FaceFields &fl, const double bar[18], double out[18]) {
+  Mac<double> m;
+  double phib = 0.0;
+  for (int i = 0; i < 9; ++i) phib += bar[9 + i];
+  m.phi = phib;
+  m.rho = rho_of<double>(K, phib);
+  m.mu = fl.mu;
+  m.D = fl.D;
+  m.grx = K.drho * fl.gfx;
+  m.gry = K.drho * fl.gfy;
+  m.gpx = fl.gpx;
+  m.gpy = fl.gpy;
+  m.Fx = -phib * fl.gmx + (m.rho - K.rho_ref) * K.gx;
+  m.Fy = -phib * fl.gmy + (m.rho - K.rho_ref) * K.gy;
+  m.icr = 1.0 / (K.cs2 * m.rho);
+  double s0 = 0.0, jx = 0.0, jy = 0.0;
+  for (int i = 0; i < 9; ++i) s0 += bar[i];
+  for (int i = 0; i < 9; ++i) jx += K.xi0[i] * bar[i];
+  for (int i = 0; i < 9; ++i) jy += K.xi1[i] * bar[i];
+  m.ux = (jx + K.hhcs2 * m.Fx) * m.icr;
+  m.uy = (jy + K.hhcs2 * m.Fy) * m.icr;
+  m.p = s0 + K.hhcs2 * (m.ux * m.grx + m.uy * m.gry - K.gam * m.rho * m.D);
+  const double uu = m.ux * m.ux + m.uy * m.uy;
+  const double tf = tauf_of<double>(K, phib, m.rho);
+  const double den = 1.0 / (2.0 * tf + K.h);
+  const double fk1 = 2.0 * tf * den, fk2 = K.h * den, fk3 = tf * K.h * den;
+  for (int i = 0; i < 9; ++i) {
+    double feq, geq, ff, fg;
+    point_eq1(K, m, uu, i, feq, geq, ff, fg);
+    out[i] = fk1 * bar[i] + fk2 * feq + fk3 * ff;
+    out[9 + i] = K.gk1 * bar[9 + i] + K.gk2 * geq + K.gk3 * fg;
+  }
+}
+
+// Steps 3-4 at face k of axis A (0: x-face between cells (k-1, t) and (k, t);
+// 1: y-face between (t, k-1) and (t, k)).  Writes the 18 face distributions.
+template <int A>
+DFN void face_full(const Consts &K, const Work &w, int k, int t, double out[18]) {
+  const Axis &ax = K.ax[A];
+  const int cl = ax.fl[k], cr = ax.fr[k];
+  const double h = K.h;
+  double bar[18];
+  FaceFields fl;
+#define CID(ia) (A == 0 ? (i64)t * K.ld + (ia) : (i64)(ia) * K.ld + t)
+#define CX(ia) (A == 0 ? (ia) : t)
+#define CY(ia) (A == 0 ? t : (ia))
+  if (cl < 0 || cr < 0) {
+    // wall face: expand from the fluid cell C; bounce-back of entering ones
+    const int cc = cl < 0 ? cr : cl;
+    const double off = cl < 0 ? ax.foffr[k] : ax.foffl[k];
+    const int nout = cl < 0 ? -1 : 1;
+    const i64 C = CID(cc);
+    for (int q = 0; q < 18; ++q) {
+      const int i = q % 9;
+      const int en = A == 0 ? ex_of(i) : ey_of(i);
+      if (en * nout < 0) continue;
+      const double *Aq = w.barp + q * K.plane;
+      const double Ac = Aq[C];
+      const double gx = pgx(K, Aq, CX(cc), CY(cc)), gy = pgy(K, Aq, CX(cc), CY(cc));
+      const double Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
+      const double val = Ac + off * Gn;
+      const double sgx = A == 0 ? Gn : Gt, sgy = A == 0 ? Gt : Gn;
+      bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
+    }
+    for (int q = 0; q < 18; ++q) {
+      const int i = q % 9;
+      const int en = A == 0 ? ex_of(i) : ey_of(i);
+      if (en * nout < 0) bar[q] = bar[q - i + opp_of(i)];
+    }
+    const double *Tmu = A == 0 ? w.dmuy : w.dmux;
+    const double *Tph = A == 0 ? w.dphy : w.dphx;
+    const double *Tp = A == 0 ? w.dpy : w.dpx;
+    fl.mu = w.mu[C];
+    fl.D = w.D[C];
+    fl.gmx = A == 0 ? 0.0 : Tmu[C];
+    fl.gmy = A == 0 ? Tmu[C] : 0.0;
+    fl.gfx = A == 0 ? 0.0 : Tph[C];
+    fl.gfy = A == 0 ? Tph[C] : 0.0;
+    fl.gpx = A == 0 ? 0.0 : Tp[C];
+    fl.gpy = A == 0 ? Tp[C] : 0.0;
+    face_dist(K, fl, bar, out);
+    for (int q = 0; q < 18; ++q) {
+      const int i = q % 9;
+      const int en = A == 0 ? ex_of(i) : ey_of(i);
+      if (en * nout < 0) out[q] = out[q - i + opp_of(i)];
+    }
+    return;
+  }
+  const i64 L = CID(cl), R = CID(cr);
+  FaceW fw;
+  fw.wl = ax.fwl[k];
+  fw.wr = ax.fwr[k];
+  fw.inv = ax.finv[k];
+  for (int q = 0; q < 18; ++q) {
+    const int i = q % 9;
+    const int en = A == 0 ? ex_of(i) : ey_of(i);
+    const double *Aq = w.barp + q * K.plane;
+    const double AL = Aq[L], AR = Aq[R];
+    double val, sn, st;
+    if (K.recon == 1 && en > 0) {
+      const double gx = pgx(K, Aq, CX(cl), CY(cl)), gy = pgy(K, Aq, CX(cl), CY(cl));
+      const double Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
+      val = AL + ax.foffl[k] * Gn;
+      sn = Gn;
+      st = Gt;
+    } else if (K.recon == 1 && en < 0) {
+      const double gx = pgx(K, Aq, CX(cr), CY(cr)), gy = pgy(K, Aq, CX(cr), CY(cr));
+      const double Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
+      val = AR + ax.foffr[k] * Gn;
+      sn = Gn;
+      st = Gt;
+    } else {
+      const double GtL = A == 0 ? pgy(K, Aq, CX(cl), CY(cl)) : pgx(K, Aq, CX(cl), CY(cl));
+      const double GtR = A == 0 ? pgy(K, Aq, CX(cr), CY(cr)) : pgx(K, Aq, CX(cr), CY(cr));
+      val = fw.wl * AL + fw.wr * AR;
+      sn = (AR - AL) * fw.inv;
+      st = fw.wl * GtL + fw.wr * GtR;
+    }
+    const double sgx = A == 0 ? sn : st, sgy = A == 0 ? st : sn;
+    bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
+  }
+  const double *Tmu = A == 0 ? w.dmuy : w.dmux;
+  const double *Tph = A == 0 ? w.dphy : w.dphx;
+  const double *Tp = A == 0 ? w.dpy : w.dpx;
+  double tmp, gn, gt;
+  face_field(fw, w.mu[L], w.mu[R], Tmu[L], Tmu[R], fl.mu, gn, gt);
+  fl.gmx = A == 0 ? gn : gt;
+  fl.gmy = A == 0 ? gt : gn;
+  face_field(fw, w.D[L], w.D[R], w.D[L], w.D[R], fl.D, tmp, tmp);
+  face_field(fw, w.phi[L], w.phi[R], Tph[L], Tph[R], tmp, gn, gt);
+  fl.gfx = A == 0 ? gn : gt;
+  fl.gfy = A == 0 ? gt : gn;
+  face_field(fw, w.p[L], w.p[R], Tp[L], Tp[R], tmp, gn, gt);
+  fl.gpx = A == 0 ? gn : gt;
+  fl.gpy = A == 0 ? gt : gn;
+  face_dist(K, fl, bar, out);
+#undef CID
+#undef CX
+#undef CY
+}
+
+struct FXFace {
+  Consts K;
+  Work w;
+  DFN void operator()(int k, int j) const {
+    double out[18];
+    face_full<0>(K, w, k, j, out);
+    for (int q = 0; q < 18; ++q) w.facex[q * K.xplane + (i64)j * K.nfx + k] = out[q];
+  }
+};
+struct FYFace {
+  Consts K;
+  Work w;
+  DFN void operator()(int i, int k) const {
+    double out[18];
+    face_full<1>(K, w, k, i, out);
+    for (int q = 0; q < 18; ++q) w.facey[q * K.yplane + (i64)k * K.ld + i] = out[q];
+  }
+};
+
+// Steps 5-6: eq. updatef with tilde+ = 4/3 bar+ - 1/3 tilde (eq. relations2).
+template <class T>
+struct FUpdate {
+  Consts K;
+  Work w;
+  const T *st;
+  T *dst;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    const int ie = (K.ax[0].bc == 0 && i == K.nx - 1) ? 0 : i + 1;
+    const int jn = (K.ax[1].bc == 0 && j == K.ny - 1) ? 0 : j + 1;
+    const double rx = K.ax[0].rdt[i], ry = K.ax[1].rdt[j];
+    for (int q = 0; q < 18; ++q) {
+      const int d = q % 9;
+      const double bp = w.barp[q * K.plane + c];
+      const double til = (double)st[q * K.plane + c];
+      const double tilp = (4.0 / 3.0) * bp - (1.0 / 3.0) * til;
+      const double W = w.facex[q * K.xplane + (i64)j * K.nfx + i];
+      const double E = w.facex[q * K.xplane + (i64)j * K.nfx + ie];
+      const double S = w.facey[q * K.yplane + (i64)j * K.ld + i];
+      const double N = w.facey[q * K.yplane + (i64)jn * K.ld + i];
+      dst[q * K.plane + c] = (T)(tilp - rx * K.xi0[d] * (E - W) - ry * K.xi1[d] * (N - S));
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Step 1 (initialisation) from phi0, u0, p0.
+// ---------------------------------------------------------------------------
+struct FInit0 {
+  Consts K;
+  Work w;
+  const double *phi0, *ux0, *uy0, *p0;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i, c0 = (i64)j * K.nx + i;
+    w.phi[c] = phi0[c0];
+    w.rho[c] = rho_of<double>(K, phi0[c0]);
+    w.ux[c] = ux0[c0];
+    w.uy[c] = uy0[c0];
+    w.p[c] = p0[c0];
+  }
+};
+
+struct FInit1 {
+  Consts K;
+  Work w;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    w.dmux[c] = stx(K, K.ax[0].d1, w.mu, i, j);
+    w.dmuy[c] = sty(K, K.ax[1].d1, w.mu, i, j);
+    const double lapmu = stx(K, K.ax[0].d2, w.mu, i, j) + sty(K, K.ax[1].d2, w.mu, i, j);
+    w.D[c] = K.mobility * lapmu;
+    w.Fx[c] = -w.phi[c] * w.dmux[c] + (w.rho[c] - K.rho_ref) * K.gx;
+    w.Fy[c] = -w.phi[c] * w.dmuy[c] + (w.rho[c] - K.rho_ref) * K.gy;
+    w.dpx[c] = stx(K, K.ax[0].d1, w.p, i, j);
+    w.dpy[c] = sty(K, K.ax[1].d1, w.p, i, j);
+  }
+};
+
+template <class T>
+struct FInit2 {
+  Consts K;
+  Work w;
+  T *dst;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    Mac<double> m;
+    cell_mac(K, w, c, m);
+    const double uu = m.ux * m.ux + m.uy * m.uy;
+    for (int i2 = 0; i2 < 9; ++i2) {
+      double feq, geq, ff, fg;
+      point_eq1(K, m, uu, i2, feq, geq, ff, fg);
+      dst[i2 * K.plane + c] = (T)(feq - K.hdt * ff);
+      dst[(9 + i2) * K.plane + c] = (T)(geq - K.hdt * fg);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Moments and monitors.
+// ---------------------------------------------------------------------------
+struct FMoments {
+  Consts K;
+  Work w;
+  double *phi, *rho, *ux, *uy, *p;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i, o = (i64)j * K.nx + i;
+    if (phi) phi[o] = w.phi[c];
+    if (rho) rho[o] = w.rho[c];
+    if (ux) ux[o] = w.ux[c];
+    if (uy) uy[o] = w.uy[c];
+    if (p) p[o] = w.p[c];
+  }
+};
+
+// Per-cell monitor terms: phi |V|, rho |u|^2 |V| / 2, free-energy density
+// (eqs. doublewell, freeenergyfunction) times |V|, |u|, non-finite count.
+template <class T>
+DFN void monitor_terms(const Consts &K, const Work &w, const T *st, int i, int j, double out[5]) {
+  const i64 c = (i64)j * K.ld + i;
+  const double V = K.ax[0].w[i] * K.ax[1].w[j];
+  const double ph = w.phi[c];
+  const double u2 = w.ux[c] * w.ux[c] + w.uy[c] * w.uy[c];
+  const double a1 = ph - K.phi_a, b1 = ph - K.phi_b;
+  const double psi = K.beta * a1 * a1 * b1 * b1;
+  const double g2 = w.dphx[c] * w.dphx[c] + w.dphy[c] * w.dphy[c];
+  out[0] = ph * V;
+  out[1] = 0.5 * w.rho[c] * u2 * V;
+  out[2] = (psi + 0.5 * K.kappa * g2) * V;
+  out[3] = u2;  // max of u2, sqrt at the end
+  double bad = 0.0;
+  for (int q = 0; q < 18; ++q) {
+    const double v = (double)st[q * K.plane + c];
+    if (!(v - v == 0.0)) bad += 1.0;
+  }
+  out[4] = bad;
+}
+
+}  // namespace dg

@@ -1,0 +1,199 @@
+"""Python binding of the MI355X two-phase DUGKS library (include/dugks2p.h).
+
+Argument marshalling only: every step runs in the HIP kernels of
+libdugks2p.so.  torch supplies device memory (initial fields, outputs,
+optional workspace) and the stream.  Importing this module fails loudly if
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdugks2p.so")
+
+from .dugks2p_params import (ABI_VERSION, BC_PERIODIC, BC_WALL, EHIP, EINVAL,  # noqa: F401
+                             ENOMEM, ENONFINITE, EUNSUPPORTED, FP32_STATE, FP64,
+                             KERNEL_AUTO, KERNEL_FUSED, KERNEL_STAGED, OK, RECON_CENTRAL,
+                             RECON_UPWIND, Params, make_params)
+
+
+class DugksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("dugks2p error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libdugks2p.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_1802_02868_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, P = ctypes.c_void_p, ctypes.POINTER
+    d = ctypes.c_double
+    L.dugks2p_workspace_bytes.restype = ctypes.c_size_t
+    L.dugks2p_workspace_bytes.argtypes = [P(Params)]
+    L.dugks2p_create.restype = ctypes.c_int
+    L.dugks2p_create.argtypes = [P(Params), vp, vp, vp, vp, vp, P(vp)]
+    L.dugks2p_step.restype = ctypes.c_int
+    L.dugks2p_step.argtypes = [vp, ctypes.c_int64]
+    L.dugks2p_moments.restype = ctypes.c_int
+    L.dugks2p_moments.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.dugks2p_monitors.restype = ctypes.c_int
+    L.dugks2p_monitors.argtypes = [vp, P(d)]
+    L.dugks2p_get_populations.restype = ctypes.c_int
+    L.dugks2p_get_populations.argtypes = [vp, vp]
+    L.dugks2p_set_populations.restype = ctypes.c_int
+    L.dugks2p_set_populations.argtypes = [vp, vp]
+    L.dugks2p_state_bytes.restype = ctypes.c_size_t
+    L.dugks2p_state_bytes.argtypes = [vp]
+    L.dugks2p_get_state.restype = ctypes.c_int
+    L.dugks2p_get_state.argtypes = [vp, vp]
+    L.dugks2p_set_state.restype = ctypes.c_int
+    L.dugks2p_set_state.argtypes = [vp, vp]
+    L.dugks2p_dt.restype = d
+    L.dugks2p_dt.argtypes = [vp]
+    L.dugks2p_step_count.restype = ctypes.c_int64
+    L.dugks2p_step_count.argtypes = [vp]
+    L.dugks2p_destroy.restype = ctypes.c_int
+    L.dugks2p_destroy.argtypes = [vp]
+    L.dugks2p_last_error.restype = ctypes.c_char_p
+    L.dugks2p_last_error.argtypes = []
+    return L
+
+
+lib = _load()
+
+EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2p_moments",
+            "dugks2p_monitors", "dugks2p_get_populations", "dugks2p_set_populations",
+            "dugks2p_state_bytes", "dugks2p_get_state", "dugks2p_set_state", "dugks2p_dt",
+            "dugks2p_step_count", "dugks2p_destroy", "dugks2p_last_error")
+
+
+def _check(rc):
+    if rc != OK:
+        raise DugksError(rc, lib.dugks2p_last_error().decode())
+    return rc
+
+
+def workspace_bytes(p: dict, x_faces, y_faces, precision=FP64, kernel=KERNEL_AUTO) -> int:
+    P = make_params(p, x_faces, y_faces, precision, kernel)
+    return int(lib.dugks2p_workspace_bytes(ctypes.byref(P)))
+
+
+class Simulation:
+    """One DUGKS simulation on the current CUDA/HIP device.
+
+    phi0, ux0, uy0, p0: torch float64 CUDA tensors (or numpy arrays, copied to
+    the device) of shape [ny, nx]."""
+
+    def __init__(self, params: dict, x_faces, y_faces, phi0, ux0, uy0, p0, precision=FP64,
+                 kernel=KERNEL_AUTO, stream=None, torch_workspace=True):
+        import torch
+        self.torch = torch
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        P = make_params(params, x_faces, y_faces, precision, kernel)
+        self._ws = None
+        if torch_workspace:
+            nb = int(lib.dugks2p_workspace_bytes(ctypes.byref(P)))
+            if nb == 0:
+                self._create_fail(P)
+            self._ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            P.workspace = (base + 255) & ~255
+            P.workspace_bytes = nb
+        fields = [self._dev(a) for a in (phi0, ux0, uy0, p0)]
+        h = ctypes.c_void_p()
+        rc = lib.dugks2p_create(ctypes.byref(P), *[f.data_ptr() for f in fields],
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        _check(rc)
+        self._h = h
+        self._P = P
+        self.precision = P.precision
+        # keep inputs alive until the init kernels have consumed them
+        self.stream.synchronize()
+
+    def _create_fail(self, P):
+        h = ctypes.c_void_p()
+        z = self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        rc = lib.dugks2p_create(ctypes.byref(P), z.data_ptr(), z.data_ptr(), z.data_ptr(),
+                                z.data_ptr(), None, ctypes.byref(h))
+        _check(rc if rc != OK else EINVAL)
+
+    def _dev(self, a):
+        t = self.torch
+        if isinstance(a, np.ndarray):
+            a = t.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        a = a.to(device=self.device, dtype=t.float64).contiguous()
+        if tuple(a.shape) != (self.ny, self.nx):
+            raise ValueError("field shape %s != (%d, %d)" % (tuple(a.shape), self.ny, self.nx))
+        return a
+
+    @classmethod
+    def from_case(cls, case, **kw):
+        return cls(case.params, case.x_faces, case.y_faces, case.phi0, case.ux0, case.uy0,
+                   case.p0, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.dugks2p_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dt(self):
+        return lib.dugks2p_dt(self._h)
+
+    @property
+    def nstep(self):
+        return lib.dugks2p_step_count(self._h)
+
+    def step(self, n=1):
+        _check(lib.dugks2p_step(self._h, int(n)))
+
+    def moments(self):
+        t = self.torch
+        out = {k: t.empty((self.ny, self.nx), dtype=t.float64, device=self.device)
+               for k in ("phi", "rho", "ux", "uy", "p")}
+        _check(lib.dugks2p_moments(self._h, *[out[k].data_ptr()
+                                              for k in ("phi", "rho", "ux", "uy", "p")]))
+        return out
+
+    def monitors(self, raise_nonfinite=True):
+        out = (ctypes.c_double * 6)()
+        rc = lib.dugks2p_monitors(self._h, out)
+        if rc != OK and (raise_nonfinite or rc != ENONFINITE):
+            _check(rc)
+        return np.array(out[:])
+
+    def populations(self):
+        t = self.torch
+        out = t.empty((18, self.ny, self.nx), dtype=t.float64, device=self.device)
+        _check(lib.dugks2p_get_populations(self._h, out.data_ptr()))
+        return out
+
+    def set_populations(self, pops):
+        pops = pops.to(device=self.device, dtype=self.torch.float64).contiguous()
+        _check(lib.dugks2p_set_populations(self._h, pops.data_ptr()))
+        self.stream.synchronize()
+
+    def get_state(self):
+        t = self.torch
+        nb = int(lib.dugks2p_state_bytes(self._h))
+        buf = t.empty(nb, dtype=t.uint8, device=self.device)
+        _check(lib.dugks2p_get_state(self._h, buf.data_ptr()))
+        return buf
+
+    def set_state(self, buf):
+        _check(lib.dugks2p_set_state(self._h, buf.data_ptr()))
+        self.stream.synchronize()

@@ -1,0 +1,49 @@
+"""ctypes mirror of dugks2p_params (include/dugks2p.h) and the constants of
+the C ABI; no library is loaded here."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+BC_PERIODIC, BC_WALL = 0, 1
+FP64, FP32_STATE = 0, 1
+RECON_CENTRAL, RECON_UPWIND = 0, 1
+KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED = 0, 1, 2
+ABI_VERSION = 1
+
+_DOUBLE_FIELDS = ("cfl", "c_max", "dt", "rt", "tau_g", "mobility", "tau_f", "beta", "kappa",
+                  "phi_a", "phi_b", "rho_a", "rho_b", "nu_a", "nu_b", "gx", "gy", "rho_ref")
+_INT_FIELDS = ("abi_version", "nx", "ny", "bc_x", "bc_y", "precision", "recon", "phi_clamp",
+               "kernel", "reserved0")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in _INT_FIELDS] + \
+               [("x_faces", ctypes.POINTER(ctypes.c_double)),
+                ("y_faces", ctypes.POINTER(ctypes.c_double))] + \
+               [(n, ctypes.c_double) for n in _DOUBLE_FIELDS] + \
+               [("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+def make_params(p: dict, x_faces, y_faces, precision=FP64, kernel=KERNEL_AUTO):
+    """Fill a Params struct from the parameter dictionary used by the
+    workloads module; keeps the face arrays alive on the struct."""
+    P = Params()
+    P.abi_version = ABI_VERSION
+    for n in _INT_FIELDS[1:]:
+        if n in p:
+            setattr(P, n, int(p[n]))
+    P.precision = int(p.get("precision", precision))
+    P.kernel = int(p.get("kernel", kernel))
+    for n in _DOUBLE_FIELDS:
+        setattr(P, n, float(p[n]))
+    xf = np.ascontiguousarray(x_faces, dtype=np.float64)
+    yf = np.ascontiguousarray(y_faces, dtype=np.float64)
+    P.x_faces = xf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    P.y_faces = yf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    P._keep = (xf, yf)
+    return P
+
+

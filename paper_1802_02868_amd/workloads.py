@@ -197,7 +197,7 @@ def rt_case(nx=256, ny=None, atwood=0.5, re=3000.0, pe=1000.0, sigma=5e-5, width
                 dict(g=g, nu=nu, lam=lam))
 
 
-def bubble_case(nx, ny, eo, mo, rho_l=1.0, rho_g=1e-3, visc_ratio=100.0, width=4.0,
+def bubble_case(nx, ny, eo, mo, rho_l=1.0, rho_g=0.1, visc_ratio=100.0, width=4.0,
                 cfl=0.354, steps=5000, recon=0) -> Case:
     """Rising bubble in a closed box (four walls): bubble = fluid A (phi_A = 1,
     light), liquid = B.  Radius nx/8 centred at (nx/2, ny/4)."""
