@@ -1,0 +1,136 @@
+"""Benchmark of the two-phase DUGKS step on one MI355X.
+
+Prints one JSON line: lattice updates per second (MLUPS: one update advances
+both D2Q9 populations f and g of one cell by one time step) on the
+Rayleigh-Taylor workload (256 x 1024 cells, FP64 unless --precision fp32),
+with the roofline of the step kernel and the FP64 CPU oracle timed on a
+bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP64_VEC_PEAK_TF = 78.6    # MI355X FP64 vector
+FP32_VEC_PEAK_TF = 157.3
+
+
+def workload(name: str):
+    from paper_1802_02868_amd import workloads as W
+    if name == "rt256x1024":
+        return W.rt_case(256)
+    if name.startswith("rt"):
+        nx = int(name[2:].split("x")[0])
+        return W.rt_case(nx)
+    if name == "drop64":
+        return W.drop_case()
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(case, seconds=10.0):
+    """The oracle as it stands, on the host cores, over a bounded number of
+    steps of the same workload."""
+    import oracle
+    o = oracle.Oracle.from_case(case)
+    o.step(1)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 2000:
+            break
+    cells = case.nx * case.ny
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d steps of %s (%dx%d), FP64, OpenMP over rows" % (
+                n, case.name, case.nx, case.ny)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="rt256x1024")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
+    ap.add_argument("--kernel", choices=("auto", "staged", "fused"), default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the step has no multi-GPU path; "
+              "see the sharding paragraph of the design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1802_02868_amd import dugks2p as D
+
+    torch.cuda.set_device(0)
+    case = workload(args.workload)
+    prec = D.FP64 if args.precision == "fp64" else D.FP32_STATE
+    kern = {"auto": D.KERNEL_AUTO, "staged": D.KERNEL_STAGED, "fused": D.KERNEL_FUSED}[args.kernel]
+    sim = D.Simulation.from_case(case, precision=prec, kernel=kern)
+    stream = sim.stream
+    cells = case.nx * case.ny
+    if args.warmup:
+        sim.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / max(args.steps, 1)
+    mlups = cells * args.steps / (ms / 1e3) / 1e6
+    mon = sim.monitors(raise_nonfinite=False)
+
+    bytes_per_cell = 288 if prec == D.FP64 else 144
+    fused = sim.kernel_kind == D.KERNEL_FUSED
+    launches_per_step = 1 if fused else 7
+    achieved = bytes_per_cell * cells / (ms_per_step / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "dugks2p fused step" if fused else "staged step (7 kernels, summed)",
+            "algorithmic_bytes_per_cell": bytes_per_cell,
+            "launches_per_step": launches_per_step}
+    out = {
+        "metric": "MLUPS (f+g D2Q9)",
+        "value": round(mlups, 3),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == D.FP64 else "f32-state",
+        "data": "synthetic",
+        "config": {"workload": "%s %s (%dx%d cells, Rayleigh-Taylor, walls in y)" % (
+            case.name, args.precision, case.nx, case.ny), "cells": cells,
+            "kernel": args.kernel, "dt": sim.dt},
+        "roofline": roof,
+        "wall_s": round(wall, 3),
+        "monitor_nonfinite": int(mon[4]),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

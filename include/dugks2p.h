@@ -144,9 +144,11 @@ size_t dugks2p_state_bytes(const dugks2p *h);
 int dugks2p_get_state(dugks2p *h, void *dst);
 int dugks2p_set_state(dugks2p *h, const void *src);
 
-/* Time step actually used, and step counter. */
+/* Time step actually used, step counter, and the DUGKS2P_KERNEL_* value
+ * the handle runs (AUTO resolved). */
 double dugks2p_dt(const dugks2p *h);
 int64_t dugks2p_step_count(const dugks2p *h);
+int dugks2p_kernel(const dugks2p *h);
 
 /* Release the handle and its device memory (NULL is accepted). */
 int dugks2p_destroy(dugks2p *h);

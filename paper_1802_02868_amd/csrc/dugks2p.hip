@@ -161,8 +161,6 @@ std::string prepare(const dugks2p_params *P, Prepared &pr) {
   build_axis(pr.ay, P->ny, P->bc_y, P->y_faces);
   pr.K = make_consts(P, pr.ax, pr.ay);
   if (!(pr.K.dt > 0.0) || !isfinite(pr.K.dt)) return "time step is not positive";
-  if (P->precision == DUGKS2P_FP32_STATE && use_staged(P))
-    return "the staged kernels are FP64 only";
   if (!use_staged(P)) return "the fused kernel is not available in this build";
   pr.L = make_layout(pr.K, pr.ax, pr.ay, P->precision, use_staged(P));
   return std::string();
@@ -174,7 +172,7 @@ int launch_step(dugks2p *h) {
   const T *src = (const T *)h->state[h->cur];
   T *dst = (T *)h->state[1 - h->cur];
   if (h->kernel == DUGKS2P_KERNEL_STAGED)
-    seq_staged_step(ex, h->K, h->w, src, dst);
+    seq_staged_step<GpuEx, T, T>(ex, h->K, h->w, src, dst);
   else
     fused_step<T>(h->fp, h->K, src, dst, h->stream, ex.err);
   if (ex.err != hipSuccess)
@@ -374,6 +372,7 @@ int dugks2p_set_state(dugks2p *h, const void *src) {
 
 double dugks2p_dt(const dugks2p *h) { return h ? h->K.dt : 0.0; }
 int64_t dugks2p_step_count(const dugks2p *h) { return h ? h->nstep : -1; }
+int dugks2p_kernel(const dugks2p *h) { return h ? h->kernel : DUGKS2P_EINVAL; }
 
 int dugks2p_destroy(dugks2p *h) {
   if (!h) return DUGKS2P_OK;

@@ -204,7 +204,9 @@ DFN void cell_mac(const Consts &K, const Work &w, i64 c, Mac<R> &m) {
 }
 
 // grad p, tau_f, and Step 2 (eqs. relations1, relations2): bar+ into w.barp.
-template <class T>
+// R is the arithmetic type of the transforms (double, or float for the
+// FP32-state form).
+template <class T, class R = double>
 struct FCell {
   Consts K;
   Work w;
@@ -213,20 +215,22 @@ struct FCell {
     const i64 c = (i64)j * K.ld + i;
     w.dpx[c] = stx(K, K.ax[0].d1, w.p, i, j);
     w.dpy[c] = sty(K, K.ax[1].d1, w.p, i, j);
-    const double tf = tauf_of<double>(K, w.phi[c], w.rho[c]);
-    w.tauf[c] = tf;
-    Mac<double> m;
+    const R tf = tauf_of<R>(K, (R)w.phi[c], (R)w.rho[c]);
+    w.tauf[c] = (double)tf;
+    Mac<R> m;
     cell_mac(K, w, c, m);
-    const double uu = m.ux * m.ux + m.uy * m.uy;
-    const double den = 1.0 / (2.0 * tf + K.dt);
-    const double fca = (2.0 * tf - K.h) * den, fcb = 3.0 * K.h * den, fcc = 3.0 * tf * K.h * den;
+    const R uu = m.ux * m.ux + m.uy * m.uy;
+    const R den = (R)1.0 / ((R)2.0 * tf + (R)K.dt);
+    const R fca = ((R)2.0 * tf - (R)K.h) * den, fcb = (R)3.0 * (R)K.h * den,
+            fcc = (R)3.0 * tf * (R)K.h * den;
     for (int i2 = 0; i2 < 9; ++i2) {
-      double feq, geq, ff, fg;
-      point_eq1(K, m, uu, i2, feq, geq, ff, fg);
-      const double tf_ = (double)st[i2 * K.plane + c];
-      const double tg_ = (double)st[(9 + i2) * K.plane + c];
-      w.barp[i2 * K.plane + c] = fca * tf_ + fcb * feq + fcc * ff;
-      w.barp[(9 + i2) * K.plane + c] = K.gca * tg_ + K.gcb * geq + K.gcc * fg;
+      R feq, geq, ff, fg;
+      point_eq1<R>(K, m, uu, i2, feq, geq, ff, fg);
+      const R tf_ = (R)st[i2 * K.plane + c];
+      const R tg_ = (R)st[(9 + i2) * K.plane + c];
+      w.barp[i2 * K.plane + c] = (double)(fca * tf_ + fcb * feq + fcc * ff);
+      w.barp[(9 + i2) * K.plane + c] =
+          (double)((R)K.gca * tg_ + (R)K.gcb * geq + (R)K.gcc * fg);
     }
   }
 };
@@ -254,53 +258,55 @@ DFN void face_field(const FaceW &fw, double FL, double FR, double TL, double TR,
 // Step 4 at a face: macros from bar (eq. conservedVariable with h), face
 // equilibria and sources, eq. original-function; wall: bounce-back of the
 // populations entering the fluid.  Inputs are the face fields.
+template <class R>
 struct FaceFields {
-  double mu, D, gmx, gmy, gfx, gfy, gpx, gpy;
+  R mu, D, gmx, gmy, gfx, gfy, gpx, gpy;
 };
 
-DFN void face_dist(const Consts &K, const FaceFields &fl, const double bar[18], double out[18]) {
-  Mac<double> m;
-  double phib = 0.0;
+template <class R>
+DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R out[18]) {
+  Mac<R> m;
+  R phib = (R)0.0;
   for (int i = 0; i < 9; ++i) phib += bar[9 + i];
   m.phi = phib;
-  m.rho = rho_of<double>(K, phib);
+  m.rho = rho_of<R>(K, phib);
   m.mu = fl.mu;
   m.D = fl.D;
-  m.grx = K.drho * fl.gfx;
-  m.gry = K.drho * fl.gfy;
+  m.grx = (R)K.drho * fl.gfx;
+  m.gry = (R)K.drho * fl.gfy;
   m.gpx = fl.gpx;
   m.gpy = fl.gpy;
-  m.Fx = -phib * fl.gmx + (m.rho - K.rho_ref) * K.gx;
-  m.Fy = -phib * fl.gmy + (m.rho - K.rho_ref) * K.gy;
-  m.icr = 1.0 / (K.cs2 * m.rho);
-  double s0 = 0.0, jx = 0.0, jy = 0.0;
+  m.Fx = -phib * fl.gmx + (m.rho - (R)K.rho_ref) * (R)K.gx;
+  m.Fy = -phib * fl.gmy + (m.rho - (R)K.rho_ref) * (R)K.gy;
+  m.icr = (R)1.0 / ((R)K.cs2 * m.rho);
+  R s0 = (R)0.0, jx = (R)0.0, jy = (R)0.0;
   for (int i = 0; i < 9; ++i) s0 += bar[i];
-  for (int i = 0; i < 9; ++i) jx += K.xi0[i] * bar[i];
-  for (int i = 0; i < 9; ++i) jy += K.xi1[i] * bar[i];
-  m.ux = (jx + K.hhcs2 * m.Fx) * m.icr;
-  m.uy = (jy + K.hhcs2 * m.Fy) * m.icr;
-  m.p = s0 + K.hhcs2 * (m.ux * m.grx + m.uy * m.gry - K.gam * m.rho * m.D);
-  const double uu = m.ux * m.ux + m.uy * m.uy;
-  const double tf = tauf_of<double>(K, phib, m.rho);
-  const double den = 1.0 / (2.0 * tf + K.h);
-  const double fk1 = 2.0 * tf * den, fk2 = K.h * den, fk3 = tf * K.h * den;
+  for (int i = 0; i < 9; ++i) jx += (R)K.xi0[i] * bar[i];
+  for (int i = 0; i < 9; ++i) jy += (R)K.xi1[i] * bar[i];
+  m.ux = (jx + (R)K.hhcs2 * m.Fx) * m.icr;
+  m.uy = (jy + (R)K.hhcs2 * m.Fy) * m.icr;
+  m.p = s0 + (R)K.hhcs2 * (m.ux * m.grx + m.uy * m.gry - (R)K.gam * m.rho * m.D);
+  const R uu = m.ux * m.ux + m.uy * m.uy;
+  const R tf = tauf_of<R>(K, phib, m.rho);
+  const R den = (R)1.0 / ((R)2.0 * tf + (R)K.h);
+  const R fk1 = (R)2.0 * tf * den, fk2 = (R)K.h * den, fk3 = tf * (R)K.h * den;
   for (int i = 0; i < 9; ++i) {
-    double feq, geq, ff, fg;
-    point_eq1(K, m, uu, i, feq, geq, ff, fg);
+    R feq, geq, ff, fg;
+    point_eq1<R>(K, m, uu, i, feq, geq, ff, fg);
     out[i] = fk1 * bar[i] + fk2 * feq + fk3 * ff;
-    out[9 + i] = K.gk1 * bar[9 + i] + K.gk2 * geq + K.gk3 * fg;
+    out[9 + i] = (R)K.gk1 * bar[9 + i] + (R)K.gk2 * geq + (R)K.gk3 * fg;
   }
 }
 
 // Steps 3-4 at face k of axis A (0: x-face between cells (k-1, t) and (k, t);
 // 1: y-face between (t, k-1) and (t, k)).  Writes the 18 face distributions.
-template <int A>
-DFN void face_full(const Consts &K, const Work &w, int k, int t, double out[18]) {
+template <int A, class R = double>
+DFN void face_full(const Consts &K, const Work &w, int k, int t, R out[18]) {
   const Axis &ax = K.ax[A];
   const int cl = ax.fl[k], cr = ax.fr[k];
-  const double h = K.h;
-  double bar[18];
-  FaceFields fl;
+  const R h = (R)K.h;
+  R bar[18];
+  FaceFields<R> fl;
 #define CID(ia) (A == 0 ? (i64)t * K.ld + (ia) : (i64)(ia) * K.ld + t)
 #define CX(ia) (A == 0 ? (ia) : t)
 #define CY(ia) (A == 0 ? t : (ia))
@@ -315,12 +321,12 @@ DFN void face_full(const Consts &K, const Work &w, int k, int t, double out[18])
       const int en = A == 0 ? ex_of(i) : ey_of(i);
       if (en * nout < 0) continue;
       const double *Aq = w.barp + q * K.plane;
-      const double Ac = Aq[C];
-      const double gx = pgx(K, Aq, CX(cc), CY(cc)), gy = pgy(K, Aq, CX(cc), CY(cc));
-      const double Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
-      const double val = Ac + off * Gn;
-      const double sgx = A == 0 ? Gn : Gt, sgy = A == 0 ? Gt : Gn;
-      bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
+      const R Ac = (R)Aq[C];
+      const R gx = (R)pgx(K, Aq, CX(cc), CY(cc)), gy = (R)pgy(K, Aq, CX(cc), CY(cc));
+      const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
+      const R val = Ac + (R)off * Gn;
+      const R sgx = A == 0 ? Gn : Gt, sgy = A == 0 ? Gt : Gn;
+      bar[q] = val - h * ((R)K.xi0[i] * sgx + (R)K.xi1[i] * sgy);
     }
     for (int q = 0; q < 18; ++q) {
       const int i = q % 9;
@@ -330,15 +336,15 @@ DFN void face_full(const Consts &K, const Work &w, int k, int t, double out[18])
     const double *Tmu = A == 0 ? w.dmuy : w.dmux;
     const double *Tph = A == 0 ? w.dphy : w.dphx;
     const double *Tp = A == 0 ? w.dpy : w.dpx;
-    fl.mu = w.mu[C];
-    fl.D = w.D[C];
-    fl.gmx = A == 0 ? 0.0 : Tmu[C];
-    fl.gmy = A == 0 ? Tmu[C] : 0.0;
-    fl.gfx = A == 0 ? 0.0 : Tph[C];
-    fl.gfy = A == 0 ? Tph[C] : 0.0;
-    fl.gpx = A == 0 ? 0.0 : Tp[C];
-    fl.gpy = A == 0 ? Tp[C] : 0.0;
-    face_dist(K, fl, bar, out);
+    fl.mu = (R)w.mu[C];
+    fl.D = (R)w.D[C];
+    fl.gmx = A == 0 ? (R)0.0 : (R)Tmu[C];
+    fl.gmy = A == 0 ? (R)Tmu[C] : (R)0.0;
+    fl.gfx = A == 0 ? (R)0.0 : (R)Tph[C];
+    fl.gfy = A == 0 ? (R)Tph[C] : (R)0.0;
+    fl.gpx = A == 0 ? (R)0.0 : (R)Tp[C];
+    fl.gpy = A == 0 ? (R)Tp[C] : (R)0.0;
+    face_dist<R>(K, fl, bar, out);
     for (int q = 0; q < 18; ++q) {
       const int i = q % 9;
       const int en = A == 0 ? ex_of(i) : ey_of(i);
@@ -346,7 +352,7 @@ DFN void face_full(const Consts &K, const Work &w, int k, int t, double out[18])
     }
     return;
   }
-  const i64 L = CID(cl), R = CID(cr);
+  const i64 L = CID(cl), Rr = CID(cr);
   FaceW fw;
   fw.wl = ax.fwl[k];
   fw.wr = ax.fwr[k];
@@ -355,71 +361,75 @@ DFN void face_full(const Consts &K, const Work &w, int k, int t, double out[18])
     const int i = q % 9;
     const int en = A == 0 ? ex_of(i) : ey_of(i);
     const double *Aq = w.barp + q * K.plane;
-    const double AL = Aq[L], AR = Aq[R];
-    double val, sn, st;
+    const R AL = (R)Aq[L], AR = (R)Aq[Rr];
+    R val, sn, st;
     if (K.recon == 1 && en > 0) {
-      const double gx = pgx(K, Aq, CX(cl), CY(cl)), gy = pgy(K, Aq, CX(cl), CY(cl));
-      const double Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
-      val = AL + ax.foffl[k] * Gn;
+      const R gx = (R)pgx(K, Aq, CX(cl), CY(cl)), gy = (R)pgy(K, Aq, CX(cl), CY(cl));
+      const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
+      val = AL + (R)ax.foffl[k] * Gn;
       sn = Gn;
       st = Gt;
     } else if (K.recon == 1 && en < 0) {
-      const double gx = pgx(K, Aq, CX(cr), CY(cr)), gy = pgy(K, Aq, CX(cr), CY(cr));
-      const double Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
-      val = AR + ax.foffr[k] * Gn;
+      const R gx = (R)pgx(K, Aq, CX(cr), CY(cr)), gy = (R)pgy(K, Aq, CX(cr), CY(cr));
+      const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
+      val = AR + (R)ax.foffr[k] * Gn;
       sn = Gn;
       st = Gt;
     } else {
-      const double GtL = A == 0 ? pgy(K, Aq, CX(cl), CY(cl)) : pgx(K, Aq, CX(cl), CY(cl));
-      const double GtR = A == 0 ? pgy(K, Aq, CX(cr), CY(cr)) : pgx(K, Aq, CX(cr), CY(cr));
-      val = fw.wl * AL + fw.wr * AR;
-      sn = (AR - AL) * fw.inv;
-      st = fw.wl * GtL + fw.wr * GtR;
+      const R GtL = (R)(A == 0 ? pgy(K, Aq, CX(cl), CY(cl)) : pgx(K, Aq, CX(cl), CY(cl)));
+      const R GtR = (R)(A == 0 ? pgy(K, Aq, CX(cr), CY(cr)) : pgx(K, Aq, CX(cr), CY(cr)));
+      val = (R)fw.wl * AL + (R)fw.wr * AR;
+      sn = (AR - AL) * (R)fw.inv;
+      st = (R)fw.wl * GtL + (R)fw.wr * GtR;
     }
-    const double sgx = A == 0 ? sn : st, sgy = A == 0 ? st : sn;
-    bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
+    const R sgx = A == 0 ? sn : st, sgy = A == 0 ? st : sn;
+    bar[q] = val - h * ((R)K.xi0[i] * sgx + (R)K.xi1[i] * sgy);
   }
   const double *Tmu = A == 0 ? w.dmuy : w.dmux;
   const double *Tph = A == 0 ? w.dphy : w.dphx;
   const double *Tp = A == 0 ? w.dpy : w.dpx;
-  double tmp, gn, gt;
-  face_field(fw, w.mu[L], w.mu[R], Tmu[L], Tmu[R], fl.mu, gn, gt);
-  fl.gmx = A == 0 ? gn : gt;
-  fl.gmy = A == 0 ? gt : gn;
-  face_field(fw, w.D[L], w.D[R], w.D[L], w.D[R], fl.D, tmp, tmp);
-  face_field(fw, w.phi[L], w.phi[R], Tph[L], Tph[R], tmp, gn, gt);
-  fl.gfx = A == 0 ? gn : gt;
-  fl.gfy = A == 0 ? gt : gn;
-  face_field(fw, w.p[L], w.p[R], Tp[L], Tp[R], tmp, gn, gt);
-  fl.gpx = A == 0 ? gn : gt;
-  fl.gpy = A == 0 ? gt : gn;
-  face_dist(K, fl, bar, out);
+  double v, tmp, gn, gt;
+  face_field(fw, w.mu[L], w.mu[Rr], Tmu[L], Tmu[Rr], v, gn, gt);
+  fl.mu = (R)v;
+  fl.gmx = (R)(A == 0 ? gn : gt);
+  fl.gmy = (R)(A == 0 ? gt : gn);
+  face_field(fw, w.D[L], w.D[Rr], w.D[L], w.D[Rr], v, tmp, tmp);
+  fl.D = (R)v;
+  face_field(fw, w.phi[L], w.phi[Rr], Tph[L], Tph[Rr], tmp, gn, gt);
+  fl.gfx = (R)(A == 0 ? gn : gt);
+  fl.gfy = (R)(A == 0 ? gt : gn);
+  face_field(fw, w.p[L], w.p[Rr], Tp[L], Tp[Rr], tmp, gn, gt);
+  fl.gpx = (R)(A == 0 ? gn : gt);
+  fl.gpy = (R)(A == 0 ? gt : gn);
+  face_dist<R>(K, fl, bar, out);
 #undef CID
 #undef CX
 #undef CY
 }
 
+template <class R = double>
 struct FXFace {
   Consts K;
   Work w;
   DFN void operator()(int k, int j) const {
-    double out[18];
-    face_full<0>(K, w, k, j, out);
-    for (int q = 0; q < 18; ++q) w.facex[q * K.xplane + (i64)j * K.nfx + k] = out[q];
+    R out[18];
+    face_full<0, R>(K, w, k, j, out);
+    for (int q = 0; q < 18; ++q) w.facex[q * K.xplane + (i64)j * K.nfx + k] = (double)out[q];
   }
 };
+template <class R = double>
 struct FYFace {
   Consts K;
   Work w;
   DFN void operator()(int i, int k) const {
-    double out[18];
-    face_full<1>(K, w, k, i, out);
-    for (int q = 0; q < 18; ++q) w.facey[q * K.yplane + (i64)k * K.ld + i] = out[q];
+    R out[18];
+    face_full<1, R>(K, w, k, i, out);
+    for (int q = 0; q < 18; ++q) w.facey[q * K.yplane + (i64)k * K.ld + i] = (double)out[q];
   }
 };
 
 // Steps 5-6: eq. updatef with tilde+ = 4/3 bar+ - 1/3 tilde (eq. relations2).
-template <class T>
+template <class T, class R = double>
 struct FUpdate {
   Consts K;
   Work w;
@@ -429,17 +439,18 @@ struct FUpdate {
     const i64 c = (i64)j * K.ld + i;
     const int ie = (K.ax[0].bc == 0 && i == K.nx - 1) ? 0 : i + 1;
     const int jn = (K.ax[1].bc == 0 && j == K.ny - 1) ? 0 : j + 1;
-    const double rx = K.ax[0].rdt[i], ry = K.ax[1].rdt[j];
+    const R rx = (R)K.ax[0].rdt[i], ry = (R)K.ax[1].rdt[j];
     for (int q = 0; q < 18; ++q) {
       const int d = q % 9;
-      const double bp = w.barp[q * K.plane + c];
-      const double til = (double)st[q * K.plane + c];
-      const double tilp = (4.0 / 3.0) * bp - (1.0 / 3.0) * til;
-      const double W = w.facex[q * K.xplane + (i64)j * K.nfx + i];
-      const double E = w.facex[q * K.xplane + (i64)j * K.nfx + ie];
-      const double S = w.facey[q * K.yplane + (i64)j * K.ld + i];
-      const double N = w.facey[q * K.yplane + (i64)jn * K.ld + i];
-      dst[q * K.plane + c] = (T)(tilp - rx * K.xi0[d] * (E - W) - ry * K.xi1[d] * (N - S));
+      const R bp = (R)w.barp[q * K.plane + c];
+      const R til = (R)st[q * K.plane + c];
+      const R tilp = (R)(4.0 / 3.0) * bp - (R)(1.0 / 3.0) * til;
+      const R W = (R)w.facex[q * K.xplane + (i64)j * K.nfx + i];
+      const R E = (R)w.facex[q * K.xplane + (i64)j * K.nfx + ie];
+      const R S = (R)w.facey[q * K.yplane + (i64)j * K.ld + i];
+      const R N = (R)w.facey[q * K.yplane + (i64)jn * K.ld + i];
+      dst[q * K.plane + c] =
+          (T)(tilp - rx * (R)K.xi0[d] * (E - W) - ry * (R)K.xi1[d] * (N - S));
     }
   }
 };

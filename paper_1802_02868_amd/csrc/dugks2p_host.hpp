@@ -400,13 +400,14 @@ void seq_macros(Ex &ex, const Consts &K, const Work &w, const T *src) {
 }
 
 // One time step with the staged kernels (one pass per stage).
-template <class Ex, class T>
+// R: arithmetic type of Steps 2-6 (double; float for the FP32-state form).
+template <class Ex, class T, class R = double>
 void seq_staged_step(Ex &ex, const Consts &K, const Work &w, const T *src, T *dst) {
   seq_macros(ex, K, w, src);
-  ex.grid(FCell<T>{K, w, src}, K.nx, K.ny);
-  ex.grid(FXFace{K, w}, K.nfx, K.ny);
-  ex.grid(FYFace{K, w}, K.nx, K.nfy);
-  ex.grid(FUpdate<T>{K, w, src, dst}, K.nx, K.ny);
+  ex.grid(FCell<T, R>{K, w, src}, K.nx, K.ny);
+  ex.grid(FXFace<R>{K, w}, K.nfx, K.ny);
+  ex.grid(FYFace<R>{K, w}, K.nx, K.nfy);
+  ex.grid(FUpdate<T, R>{K, w, src, dst}, K.nx, K.ny);
 }
 
 }  // namespace dg

@@ -58,6 +58,8 @@ def _load():
     L.dugks2p_dt.argtypes = [vp]
     L.dugks2p_step_count.restype = ctypes.c_int64
     L.dugks2p_step_count.argtypes = [vp]
+    L.dugks2p_kernel.restype = ctypes.c_int
+    L.dugks2p_kernel.argtypes = [vp]
     L.dugks2p_destroy.restype = ctypes.c_int
     L.dugks2p_destroy.argtypes = [vp]
     L.dugks2p_last_error.restype = ctypes.c_char_p
@@ -70,7 +72,7 @@ lib = _load()
 EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2p_moments",
             "dugks2p_monitors", "dugks2p_get_populations", "dugks2p_set_populations",
             "dugks2p_state_bytes", "dugks2p_get_state", "dugks2p_set_state", "dugks2p_dt",
-            "dugks2p_step_count", "dugks2p_destroy", "dugks2p_last_error")
+            "dugks2p_step_count", "dugks2p_kernel", "dugks2p_destroy", "dugks2p_last_error")
 
 
 def _check(rc):
@@ -153,6 +155,10 @@ class Simulation:
     @property
     def dt(self):
         return lib.dugks2p_dt(self._h)
+
+    @property
+    def kernel_kind(self):
+        return lib.dugks2p_kernel(self._h)
 
     @property
     def nstep(self):
