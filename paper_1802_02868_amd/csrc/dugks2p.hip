@@ -47,6 +47,14 @@ struct GpuEx {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess && err == hipSuccess) err = e;
   }
+  template <class T, class R, bool U>
+  void tiles(const Consts &K, const Work &w, const T *src, T *dst) {
+    const int ntx = tiles_x(K), nt = ntx * tiles_y(K);
+    hipLaunchKernelGGL((k_fused_tile<T, R, U>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst, ntx,
+                       nt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess && err == hipSuccess) err = e;
+  }
 };
 
 // Monitor partial sums: one 64 x 4 block of cells per workgroup, fixed-order
@@ -141,12 +149,17 @@ struct dugks2p {
   Work w;
   double *mon_part, *mon_out;
   int64_t nstep;
-  FusedPlan fp;
 };
 
 namespace {
 
-bool use_staged(const dugks2p_params *P) { return P->kernel != DUGKS2P_KERNEL_FUSED; }
+// The fused tile kernel implements CENTRAL reconstruction (its bar+ ring is
+// one cell wide); UPWIND runs on the staged kernels.
+bool use_staged(const dugks2p_params *P) {
+  if (P->kernel == DUGKS2P_KERNEL_STAGED) return true;
+  if (P->kernel == DUGKS2P_KERNEL_AUTO) return P->recon != DUGKS2P_RECON_CENTRAL;
+  return false;
+}
 
 struct Prepared {
   AxisHost ax, ay;
@@ -161,7 +174,8 @@ std::string prepare(const dugks2p_params *P, Prepared &pr) {
   build_axis(pr.ay, P->ny, P->bc_y, P->y_faces);
   pr.K = make_consts(P, pr.ax, pr.ay);
   if (!(pr.K.dt > 0.0) || !isfinite(pr.K.dt)) return "time step is not positive";
-  if (!use_staged(P)) return "the fused kernel is not available in this build";
+  if (P->kernel == DUGKS2P_KERNEL_FUSED && P->recon != DUGKS2P_RECON_CENTRAL)
+    return "the fused kernel implements CENTRAL reconstruction only";
   pr.L = make_layout(pr.K, pr.ax, pr.ay, P->precision, use_staged(P));
   return std::string();
 }
@@ -174,7 +188,12 @@ int launch_step(dugks2p *h) {
   if (h->kernel == DUGKS2P_KERNEL_STAGED)
     seq_staged_step<GpuEx, T, T>(ex, h->K, h->w, src, dst);
   else
-    fused_step<T>(h->fp, h->K, src, dst, h->stream, ex.err);
+  {
+    if (h->K.unit)
+      seq_fused_step<GpuEx, T, T, true>(ex, h->K, h->w, src, dst);
+    else
+      seq_fused_step<GpuEx, T, T, false>(ex, h->K, h->w, src, dst);
+  }
   if (ex.err != hipSuccess)
     return fail(DUGKS2P_EHIP, std::string("kernel launch: ") + hipGetErrorString(ex.err));
   h->cur = 1 - h->cur;
@@ -259,7 +278,6 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
       rc = fail(DUGKS2P_EHIP, "state clear");
       break;
     }
-    h->fp = make_fused_plan(h->K, P->precision);
     GpuEx ex{h->stream, hipSuccess};
     if (P->precision == DUGKS2P_FP64)
       seq_init(ex, h->K, h->w, phi0, ux0, uy0, p0, (double *)h->state[0]);

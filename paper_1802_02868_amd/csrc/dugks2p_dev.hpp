@@ -27,6 +27,29 @@ DFN int ex_of(int i) { return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i =
 DFN int ey_of(int i) { return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0); }
 DFN int opp_of(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5); }
 
+// Unit lattice speed (c = sqrt(3 RT) = 1, i.e. RT = 1/3 as in every test of
+// the paper): xi_i = e_i in {-1, 0, 1}^2 and the weights are literals, so the
+// per-direction products fold away.  Each helper returns the value the
+// general expression yields, with the same association (x * 1 = x, x + 0 =
+// x, x * -1 = -x are exact), so both variants agree bit for bit.
+DFN double w9_lit(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+// e_i . (a, b) in the order (e_x a) + (e_y b)
+template <class R>
+DFN R edot(int i, R a, R b) {
+  switch (i) {
+    case 0: return (R)0.0;
+    case 1: return a;
+    case 2: return b;
+    case 3: return -a;
+    case 4: return -b;
+    case 5: return a + b;
+    case 6: return -a + b;
+    case 7: return -a + -b;
+    default: return a + -b;
+  }
+}
+
 // One mesh axis (App. B tensor-product mesh).  Cell k: neighbours lo/hi
 // (periodic wrap, or the cell itself standing for the mirror ghost across a
 // wall), three-point weights (minus, centre, plus) of the first and second
@@ -40,7 +63,7 @@ struct Axis {
 };
 
 struct Consts {
-  int nx, ny, ld, nfx, nfy, recon, phi_clamp, pad0;
+  int nx, ny, ld, nfx, nfy, recon, phi_clamp, unit;  // unit: c = sqrt(3 RT) == 1
   i64 plane;   // ny * ld: stride between populations / fields
   i64 xplane;  // ny * nfx: stride of x-face arrays
   i64 yplane;  // nfy * ld: stride of y-face arrays
@@ -77,21 +100,40 @@ DFN R tauf_of(const Consts &K, R phi, R rho) {
   return mud / (rho * (R)K.cs2);
 }
 
-// eqs. feq, geq, su, Hi, F, G at one point, direction i.
-template <class R>
+// eqs. feq, geq, su, Hi, F, G at one point, direction i.  U: unit speed.
+template <class R, bool U = false>
 DFN void point_eq1(const Consts &K, const Mac<R> &m, R uu, int i, R &feq, R &geq, R &ff, R &fg) {
   const R cs2 = (R)K.cs2;
-  const R wi = (R)K.w9[i], xx = (R)K.xi0[i], xy = (R)K.xi1[i];
-  const R eu = xx * m.ux + xy * m.uy;
+  const R wi = U ? (R)w9_lit(i) : (R)K.w9[i];
+  const R xx = U ? (R)ex_of(i) : (R)K.xi0[i], xy = U ? (R)ey_of(i) : (R)K.xi1[i];
+  const R eu = U ? edot<R>(i, m.ux, m.uy) : xx * m.ux + xy * m.uy;
   const R si = wi * (eu * (R)K.k1 + eu * eu * (R)K.k2 - uu * (R)K.k3);
   feq = wi * m.p + cs2 * m.rho * si;
-  const R Hi = (i == 0) ? m.phi - (R)K.ch0 * m.mu : (R)K.chi[i] * m.mu;
+  // chi and wics2 take three distinct values (one per weight class)
+  const int wc = U ? (i == 0 ? 0 : (i < 5 ? 1 : 5)) : i;
+  const R Hi = (i == 0) ? m.phi - (R)K.ch0 * m.mu : (R)K.chi[wc] * m.mu;
   geq = Hi + m.phi * si;
   const R G = wi + si;
   const R cx = xx - m.ux, cy = xy - m.uy;
   ff = cx * (m.Fx * G + si * cs2 * m.grx) + cy * (m.Fy * G + si * cs2 * m.gry) -
-       (R)K.wics2[i] * m.rho * (R)K.gam * m.D;
+       (R)K.wics2[wc] * m.rho * (R)K.gam * m.D;
   fg = m.phi * m.icr * (cx * (m.Fx - m.gpx) + cy * (m.Fy - m.gpy)) * G;
+}
+
+// sum_i xi_x,i v_i and sum_i xi_y,i v_i over 9 values, ascending i.
+template <class R, bool U>
+DFN void xi_sums(const Consts &K, const R v[9], R &jx, R &jy) {
+  if (U) {
+    jx = ((((v[1] - v[3]) + v[5]) - v[6]) - v[7]) + v[8];
+    jy = ((((v[2] - v[4]) + v[5]) + v[6]) - v[7]) - v[8];
+    return;
+  }
+  jx = (R)0.0;
+  jy = (R)0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) jx += (R)K.xi0[i] * v[i];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) jy += (R)K.xi1[i] * v[i];
 }
 
 // Three-point stencil along x (axis 0) or y (axis 1) of a cell field with
@@ -112,7 +154,7 @@ DFN double sty(const Consts &K, const double *w3, const double *F, int i, int j)
 // Scratch fields of the staged step (all FP64, pitch ld, stride plane).
 struct Work {
   double *phi, *rho, *mu, *dphx, *dphy, *dmux, *dmuy, *D, *Fx, *Fy, *ux, *uy, *p, *dpx, *dpy,
-      *tauf;
+      *tauf, *s0, *jx, *jy;
   double *barp;   // 18 x plane
   double *facex;  // 18 x xplane: [q][j][k]
   double *facey;  // 18 x yplane: [q][k][i]
@@ -131,21 +173,27 @@ struct FPhi {
   DFN void operator()(int i, int j) const {
     const i64 c = (i64)j * K.ld + i;
     double acc = 0.0;
+    #pragma unroll
     for (int q = 9; q < 18; ++q) acc += (double)st[q * K.plane + c];
     w.phi[c] = acc;
     w.rho[c] = rho_of<double>(K, acc);
   }
 };
 
-// eq. chemicalpotential with the App. B Laplacian; grad phi.
+// eq. chemicalpotential with the App. B Laplacian of phi at cell (i, j).
+DFN double mu_at(const Consts &K, const double *phi, int i, int j) {
+  const double ph = phi[(i64)j * K.ld + i];
+  const double lap = stx(K, K.ax[0].d2, phi, i, j) + sty(K, K.ax[1].d2, phi, i, j);
+  return K.c4b * (ph - K.phi_a) * (ph - K.phi_b) * (ph - K.phimid) - K.kappa * lap;
+}
+
+// eq. chemicalpotential; grad phi.
 struct FMu {
   Consts K;
   Work w;
   DFN void operator()(int i, int j) const {
     const i64 c = (i64)j * K.ld + i;
-    const double ph = w.phi[c];
-    const double lap = stx(K, K.ax[0].d2, w.phi, i, j) + sty(K, K.ax[1].d2, w.phi, i, j);
-    w.mu[c] = K.c4b * (ph - K.phi_a) * (ph - K.phi_b) * (ph - K.phimid) - K.kappa * lap;
+    w.mu[c] = mu_at(K, w.phi, i, j);
     w.dphx[c] = stx(K, K.ax[0].d1, w.phi, i, j);
     w.dphy[c] = sty(K, K.ax[1].d1, w.phi, i, j);
   }
@@ -171,9 +219,13 @@ struct FMacro {
     w.Fy[c] = Fy;
     double s0 = 0.0, jx = 0.0, jy = 0.0;
     double f[9];
+    #pragma unroll
     for (int q = 0; q < 9; ++q) f[q] = (double)st[q * K.plane + c];
+    #pragma unroll
     for (int q = 0; q < 9; ++q) s0 += f[q];
+    #pragma unroll
     for (int q = 0; q < 9; ++q) jx += K.xi0[q] * f[q];
+    #pragma unroll
     for (int q = 0; q < 9; ++q) jy += K.xi1[q] * f[q];
     const double icr = 1.0 / (K.cs2 * rh);
     const double ux = (jx + K.hdtcs2 * Fx) * icr;
@@ -203,9 +255,25 @@ DFN void cell_mac(const Consts &K, const Work &w, i64 c, Mac<R> &m) {
   m.icr = (R)1.0 / ((R)K.cs2 * m.rho);
 }
 
-// grad p, tau_f, and Step 2 (eqs. relations1, relations2): bar+ into w.barp.
-// R is the arithmetic type of the transforms (double, or float for the
-// FP32-state form).
+// Step 2 at one cell (eqs. relations1, relations2): bar+ of the 18
+// populations from tilde, the cell macros and tau_f.
+template <class R, bool U = false>
+DFN void cell_barp(const Consts &K, const Mac<R> &m, R tf, const R til[18], R out[18]) {
+  const R uu = m.ux * m.ux + m.uy * m.uy;
+  const R den = (R)1.0 / ((R)2.0 * tf + (R)K.dt);
+  const R fca = ((R)2.0 * tf - (R)K.h) * den, fcb = (R)3.0 * (R)K.h * den,
+          fcc = (R)3.0 * tf * (R)K.h * den;
+  #pragma unroll
+  for (int i2 = 0; i2 < 9; ++i2) {
+    R feq, geq, ff, fg;
+    point_eq1<R, U>(K, m, uu, i2, feq, geq, ff, fg);
+    out[i2] = fca * til[i2] + fcb * feq + fcc * ff;
+    out[9 + i2] = (R)K.gca * til[9 + i2] + (R)K.gcb * geq + (R)K.gcc * fg;
+  }
+}
+
+// grad p, tau_f, and Step 2: bar+ into w.barp.  R is the arithmetic type of
+// the transforms (double, or float for the FP32-state form).
 template <class T, class R = double>
 struct FCell {
   Consts K;
@@ -219,29 +287,14 @@ struct FCell {
     w.tauf[c] = (double)tf;
     Mac<R> m;
     cell_mac(K, w, c, m);
-    const R uu = m.ux * m.ux + m.uy * m.uy;
-    const R den = (R)1.0 / ((R)2.0 * tf + (R)K.dt);
-    const R fca = ((R)2.0 * tf - (R)K.h) * den, fcb = (R)3.0 * (R)K.h * den,
-            fcc = (R)3.0 * tf * (R)K.h * den;
-    for (int i2 = 0; i2 < 9; ++i2) {
-      R feq, geq, ff, fg;
-      point_eq1<R>(K, m, uu, i2, feq, geq, ff, fg);
-      const R tf_ = (R)st[i2 * K.plane + c];
-      const R tg_ = (R)st[(9 + i2) * K.plane + c];
-      w.barp[i2 * K.plane + c] = (double)(fca * tf_ + fcb * feq + fcc * ff);
-      w.barp[(9 + i2) * K.plane + c] =
-          (double)((R)K.gca * tg_ + (R)K.gcb * geq + (R)K.gcc * fg);
-    }
+    R til[18], out[18];
+    #pragma unroll
+    for (int q = 0; q < 18; ++q) til[q] = (R)st[q * K.plane + c];
+    cell_barp<R>(K, m, tf, til, out);
+    #pragma unroll
+    for (int q = 0; q < 18; ++q) w.barp[q * K.plane + c] = (double)out[q];
   }
 };
-
-// Population gradient (App. B first derivative, one-sided at a wall cell).
-DFN double pgx(const Consts &K, const double *A, int i, int j) {
-  return stx(K, K.ax[0].pg, A, i, j);
-}
-DFN double pgy(const Consts &K, const double *A, int i, int j) {
-  return sty(K, K.ax[1].pg, A, i, j);
-}
 
 // R5: value, normal derivative and tangential derivative of a cell field at
 // an interior face between cells L and R (weights of the face).
@@ -256,17 +309,17 @@ DFN void face_field(const FaceW &fw, double FL, double FR, double TL, double TR,
 }
 
 // Step 4 at a face: macros from bar (eq. conservedVariable with h), face
-// equilibria and sources, eq. original-function; wall: bounce-back of the
-// populations entering the fluid.  Inputs are the face fields.
+// equilibria and sources, eq. original-function.  Inputs are the face fields.
 template <class R>
 struct FaceFields {
   R mu, D, gmx, gmy, gfx, gfy, gpx, gpy;
 };
 
-template <class R>
+template <class R, bool U = false>
 DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R out[18]) {
   Mac<R> m;
   R phib = (R)0.0;
+  #pragma unroll
   for (int i = 0; i < 9; ++i) phib += bar[9 + i];
   m.phi = phib;
   m.rho = rho_of<R>(K, phib);
@@ -280,8 +333,11 @@ DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R 
   m.Fy = -phib * fl.gmy + (m.rho - (R)K.rho_ref) * (R)K.gy;
   m.icr = (R)1.0 / ((R)K.cs2 * m.rho);
   R s0 = (R)0.0, jx = (R)0.0, jy = (R)0.0;
+  #pragma unroll
   for (int i = 0; i < 9; ++i) s0 += bar[i];
+  #pragma unroll
   for (int i = 0; i < 9; ++i) jx += (R)K.xi0[i] * bar[i];
+  #pragma unroll
   for (int i = 0; i < 9; ++i) jy += (R)K.xi1[i] * bar[i];
   m.ux = (jx + (R)K.hhcs2 * m.Fx) * m.icr;
   m.uy = (jy + (R)K.hhcs2 * m.Fy) * m.icr;
@@ -290,24 +346,26 @@ DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R 
   const R tf = tauf_of<R>(K, phib, m.rho);
   const R den = (R)1.0 / ((R)2.0 * tf + (R)K.h);
   const R fk1 = (R)2.0 * tf * den, fk2 = (R)K.h * den, fk3 = tf * (R)K.h * den;
+  #pragma unroll
   for (int i = 0; i < 9; ++i) {
     R feq, geq, ff, fg;
-    point_eq1<R>(K, m, uu, i, feq, geq, ff, fg);
+    point_eq1<R, U>(K, m, uu, i, feq, geq, ff, fg);
     out[i] = fk1 * bar[i] + fk2 * feq + fk3 * ff;
     out[9 + i] = (R)K.gk1 * bar[9 + i] + (R)K.gk2 * geq + (R)K.gk3 * fg;
   }
 }
 
 // Steps 3-4 at face k of axis A (0: x-face between cells (k-1, t) and (k, t);
-// 1: y-face between (t, k-1) and (t, k)).  Writes the 18 face distributions.
-template <int A, class R = double>
-DFN void face_full(const Consts &K, const Work &w, int k, int t, R out[18]) {
+// 1: y-face between (t, k-1) and (t, k)).  Acc provides bar+ (A), the cell
+// fields mu, D, phi, p and their derivatives dmu, dphi, dp along an axis.
+template <int A, class R, class Acc, bool U = false>
+DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
   const Axis &ax = K.ax[A];
   const int cl = ax.fl[k], cr = ax.fr[k];
   const R h = (R)K.h;
+  const int TA = 1 - A;  // tangential axis
   R bar[18];
   FaceFields<R> fl;
-#define CID(ia) (A == 0 ? (i64)t * K.ld + (ia) : (i64)(ia) * K.ld + t)
 #define CX(ia) (A == 0 ? (ia) : t)
 #define CY(ia) (A == 0 ? t : (ia))
   if (cl < 0 || cr < 0) {
@@ -315,36 +373,36 @@ DFN void face_full(const Consts &K, const Work &w, int k, int t, R out[18]) {
     const int cc = cl < 0 ? cr : cl;
     const double off = cl < 0 ? ax.foffr[k] : ax.foffl[k];
     const int nout = cl < 0 ? -1 : 1;
-    const i64 C = CID(cc);
+    const typename Acc::H HC = acc.cell(CX(cc), CY(cc));
+    #pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int i = q % 9;
       const int en = A == 0 ? ex_of(i) : ey_of(i);
       if (en * nout < 0) continue;
-      const double *Aq = w.barp + q * K.plane;
-      const R Ac = (R)Aq[C];
-      const R gx = (R)pgx(K, Aq, CX(cc), CY(cc)), gy = (R)pgy(K, Aq, CX(cc), CY(cc));
+      const R Ac = (R)acc.A(q, HC);
+      const R gx = (R)acc.pgrad(0, q, HC), gy = (R)acc.pgrad(1, q, HC);
       const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
       const R val = Ac + (R)off * Gn;
       const R sgx = A == 0 ? Gn : Gt, sgy = A == 0 ? Gt : Gn;
-      bar[q] = val - h * ((R)K.xi0[i] * sgx + (R)K.xi1[i] * sgy);
+      bar[q] = val - h * (U ? edot<R>(i, sgx, sgy) : (R)K.xi0[i] * sgx + (R)K.xi1[i] * sgy);
     }
+    #pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int i = q % 9;
       const int en = A == 0 ? ex_of(i) : ey_of(i);
       if (en * nout < 0) bar[q] = bar[q - i + opp_of(i)];
     }
-    const double *Tmu = A == 0 ? w.dmuy : w.dmux;
-    const double *Tph = A == 0 ? w.dphy : w.dphx;
-    const double *Tp = A == 0 ? w.dpy : w.dpx;
-    fl.mu = (R)w.mu[C];
-    fl.D = (R)w.D[C];
-    fl.gmx = A == 0 ? (R)0.0 : (R)Tmu[C];
-    fl.gmy = A == 0 ? (R)Tmu[C] : (R)0.0;
-    fl.gfx = A == 0 ? (R)0.0 : (R)Tph[C];
-    fl.gfy = A == 0 ? (R)Tph[C] : (R)0.0;
-    fl.gpx = A == 0 ? (R)0.0 : (R)Tp[C];
-    fl.gpy = A == 0 ? (R)Tp[C] : (R)0.0;
-    face_dist<R>(K, fl, bar, out);
+    fl.mu = (R)acc.mu(HC);
+    fl.D = (R)acc.D(HC);
+    const double tmu = acc.dmu(TA, HC), tph = acc.dphi(TA, HC), tp = acc.dp(TA, HC);
+    fl.gmx = A == 0 ? (R)0.0 : (R)tmu;
+    fl.gmy = A == 0 ? (R)tmu : (R)0.0;
+    fl.gfx = A == 0 ? (R)0.0 : (R)tph;
+    fl.gfy = A == 0 ? (R)tph : (R)0.0;
+    fl.gpx = A == 0 ? (R)0.0 : (R)tp;
+    fl.gpy = A == 0 ? (R)tp : (R)0.0;
+    face_dist<R, U>(K, fl, bar, out);
+    #pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int i = q % 9;
       const int en = A == 0 ? ex_of(i) : ey_of(i);
@@ -352,60 +410,91 @@ DFN void face_full(const Consts &K, const Work &w, int k, int t, R out[18]) {
     }
     return;
   }
-  const i64 L = CID(cl), Rr = CID(cr);
+  const typename Acc::H HL = acc.cell(CX(cl), CY(cl)), HR = acc.cell(CX(cr), CY(cr));
   FaceW fw;
   fw.wl = ax.fwl[k];
   fw.wr = ax.fwr[k];
   fw.inv = ax.finv[k];
+  #pragma unroll
   for (int q = 0; q < 18; ++q) {
     const int i = q % 9;
     const int en = A == 0 ? ex_of(i) : ey_of(i);
-    const double *Aq = w.barp + q * K.plane;
-    const R AL = (R)Aq[L], AR = (R)Aq[Rr];
+    const R AL = (R)acc.A(q, HL), AR = (R)acc.A(q, HR);
     R val, sn, st;
     if (K.recon == 1 && en > 0) {
-      const R gx = (R)pgx(K, Aq, CX(cl), CY(cl)), gy = (R)pgy(K, Aq, CX(cl), CY(cl));
+      const R gx = (R)acc.pgrad(0, q, HL), gy = (R)acc.pgrad(1, q, HL);
       const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
       val = AL + (R)ax.foffl[k] * Gn;
       sn = Gn;
       st = Gt;
     } else if (K.recon == 1 && en < 0) {
-      const R gx = (R)pgx(K, Aq, CX(cr), CY(cr)), gy = (R)pgy(K, Aq, CX(cr), CY(cr));
+      const R gx = (R)acc.pgrad(0, q, HR), gy = (R)acc.pgrad(1, q, HR);
       const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
       val = AR + (R)ax.foffr[k] * Gn;
       sn = Gn;
       st = Gt;
     } else {
-      const R GtL = (R)(A == 0 ? pgy(K, Aq, CX(cl), CY(cl)) : pgx(K, Aq, CX(cl), CY(cl)));
-      const R GtR = (R)(A == 0 ? pgy(K, Aq, CX(cr), CY(cr)) : pgx(K, Aq, CX(cr), CY(cr)));
+      const R GtL = (R)acc.pgrad(TA, q, HL);
+      const R GtR = (R)acc.pgrad(TA, q, HR);
       val = (R)fw.wl * AL + (R)fw.wr * AR;
       sn = (AR - AL) * (R)fw.inv;
       st = (R)fw.wl * GtL + (R)fw.wr * GtR;
     }
     const R sgx = A == 0 ? sn : st, sgy = A == 0 ? st : sn;
-    bar[q] = val - h * ((R)K.xi0[i] * sgx + (R)K.xi1[i] * sgy);
+    bar[q] = val - h * (U ? edot<R>(i, sgx, sgy) : (R)K.xi0[i] * sgx + (R)K.xi1[i] * sgy);
   }
-  const double *Tmu = A == 0 ? w.dmuy : w.dmux;
-  const double *Tph = A == 0 ? w.dphy : w.dphx;
-  const double *Tp = A == 0 ? w.dpy : w.dpx;
   double v, tmp, gn, gt;
-  face_field(fw, w.mu[L], w.mu[Rr], Tmu[L], Tmu[Rr], v, gn, gt);
+  face_field(fw, acc.mu(HL), acc.mu(HR), acc.dmu(TA, HL), acc.dmu(TA, HR), v, gn, gt);
   fl.mu = (R)v;
   fl.gmx = (R)(A == 0 ? gn : gt);
   fl.gmy = (R)(A == 0 ? gt : gn);
-  face_field(fw, w.D[L], w.D[Rr], w.D[L], w.D[Rr], v, tmp, tmp);
+  face_field(fw, acc.D(HL), acc.D(HR), 0.0, 0.0, v, tmp, tmp);
   fl.D = (R)v;
-  face_field(fw, w.phi[L], w.phi[Rr], Tph[L], Tph[Rr], tmp, gn, gt);
+  face_field(fw, acc.phi(HL), acc.phi(HR), acc.dphi(TA, HL), acc.dphi(TA, HR), tmp, gn, gt);
   fl.gfx = (R)(A == 0 ? gn : gt);
   fl.gfy = (R)(A == 0 ? gt : gn);
-  face_field(fw, w.p[L], w.p[Rr], Tp[L], Tp[Rr], tmp, gn, gt);
+  face_field(fw, acc.p(HL), acc.p(HR), acc.dp(TA, HL), acc.dp(TA, HR), tmp, gn, gt);
   fl.gpx = (R)(A == 0 ? gn : gt);
   fl.gpy = (R)(A == 0 ? gt : gn);
-  face_dist<R>(K, fl, bar, out);
-#undef CID
+  face_dist<R, U>(K, fl, bar, out);
 #undef CX
 #undef CY
 }
+
+// Accessor over the staged global arrays.  A cell handle is its linear
+// index and coordinates; derivatives use the App. B weights of the axis.
+struct GAcc {
+  const Consts *K;
+  const Work *w;
+  struct H {
+    int x, y;
+    i64 c, lo[2], hi[2];
+  };
+  DFN H cell(int x, int y) const {
+    H h;
+    h.x = x;
+    h.y = y;
+    h.c = (i64)y * K->ld + x;
+    h.lo[0] = (i64)y * K->ld + K->ax[0].lo[x];
+    h.hi[0] = (i64)y * K->ld + K->ax[0].hi[x];
+    h.lo[1] = (i64)K->ax[1].lo[y] * K->ld + x;
+    h.hi[1] = (i64)K->ax[1].hi[y] * K->ld + x;
+    return h;
+  }
+  DFN double A(int q, const H &h) const { return w->barp[q * K->plane + h.c]; }
+  DFN double pgrad(int a, int q, const H &h) const {
+    const double *wt = K->ax[a].pg + 3 * (a == 0 ? h.x : h.y);
+    const double *Aq = w->barp + q * K->plane;
+    return wt[0] * Aq[h.lo[a]] + wt[1] * Aq[h.c] + wt[2] * Aq[h.hi[a]];
+  }
+  DFN double mu(const H &h) const { return w->mu[h.c]; }
+  DFN double D(const H &h) const { return w->D[h.c]; }
+  DFN double phi(const H &h) const { return w->phi[h.c]; }
+  DFN double p(const H &h) const { return w->p[h.c]; }
+  DFN double dmu(int a, const H &h) const { return (a == 0 ? w->dmux : w->dmuy)[h.c]; }
+  DFN double dphi(int a, const H &h) const { return (a == 0 ? w->dphx : w->dphy)[h.c]; }
+  DFN double dp(int a, const H &h) const { return (a == 0 ? w->dpx : w->dpy)[h.c]; }
+};
 
 template <class R = double>
 struct FXFace {
@@ -413,7 +502,9 @@ struct FXFace {
   Work w;
   DFN void operator()(int k, int j) const {
     R out[18];
-    face_full<0, R>(K, w, k, j, out);
+    const GAcc acc{&K, &w};
+    face_core<0, R>(K, acc, k, j, out);
+    #pragma unroll
     for (int q = 0; q < 18; ++q) w.facex[q * K.xplane + (i64)j * K.nfx + k] = (double)out[q];
   }
 };
@@ -423,7 +514,9 @@ struct FYFace {
   Work w;
   DFN void operator()(int i, int k) const {
     R out[18];
-    face_full<1, R>(K, w, k, i, out);
+    const GAcc acc{&K, &w};
+    face_core<1, R>(K, acc, k, i, out);
+    #pragma unroll
     for (int q = 0; q < 18; ++q) w.facey[q * K.yplane + (i64)k * K.ld + i] = (double)out[q];
   }
 };
@@ -440,6 +533,7 @@ struct FUpdate {
     const int ie = (K.ax[0].bc == 0 && i == K.nx - 1) ? 0 : i + 1;
     const int jn = (K.ax[1].bc == 0 && j == K.ny - 1) ? 0 : j + 1;
     const R rx = (R)K.ax[0].rdt[i], ry = (R)K.ax[1].rdt[j];
+    #pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int d = q % 9;
       const R bp = (R)w.barp[q * K.plane + c];
@@ -498,6 +592,7 @@ struct FInit2 {
     Mac<double> m;
     cell_mac(K, w, c, m);
     const double uu = m.ux * m.ux + m.uy * m.uy;
+    #pragma unroll
     for (int i2 = 0; i2 < 9; ++i2) {
       double feq, geq, ff, fg;
       point_eq1(K, m, uu, i2, feq, geq, ff, fg);
@@ -540,6 +635,7 @@ DFN void monitor_terms(const Consts &K, const Work &w, const T *st, int i, int j
   out[2] = (psi + 0.5 * K.kappa * g2) * V;
   out[3] = u2;  // max of u2, sqrt at the end
   double bad = 0.0;
+  #pragma unroll
   for (int q = 0; q < 18; ++q) {
     const double v = (double)st[q * K.plane + c];
     if (!(v - v == 0.0)) bad += 1.0;

@@ -1,15 +1,373 @@
-// dugks2p_fused.hpp -- fused one-kernel time step (placeholder until written).
+// dugks2p_fused.hpp -- the step as three launches:
+//   1. FPhiSums: phi = sum g~ and the f~ sums (one thread per cell);
+//   2. FMacF:    mu, D, F, u, p (one thread per cell; mu of the four
+//                neighbours recomputed from phi);
+//   3. tile kernel: for a 14 x 14 tile, Step 2 (bar+) on the tile and a
+//                one-cell ring into LDS, Steps 3-4 at every face of the tile
+//                (each face once), flux exchange through LDS, Steps 5-6.
+// The populations are read once per step from HBM (ring cells from L2) and
+// written once.  Arithmetic is the same code as the staged stages, so FP64
+// results are bitwise identical to them.
+//
+// The tile work is written as phases separated by workgroup barriers; each
+// phase takes the thread index and a per-thread state, so the host build can
+// run the phases thread by thread with the same barrier semantics.
 #pragma once
+
 #include "dugks2p_dev.hpp"
 
 namespace dg {
-struct FusedPlan {
-  int ok;
+
+enum { TT = 14, W1 = TT + 2, W2 = TT + 4, NTHR = W1 * W1 };  // 256 threads
+
+// x-face flux slots: directions with e_x != 0 (1, 3, 5, 6, 7, 8); y-face:
+// e_y != 0 (2, 4, 5, 6, 7, 8).  -1 = no flux across that face.
+DFN int xslot(int i) { return i == 1 ? 0 : (i == 3 ? 1 : (i >= 5 ? i - 3 : -1)); }
+DFN int yslot(int i) { return i == 2 ? 0 : (i == 4 ? 1 : (i >= 5 ? i - 3 : -1)); }
+
+// phi, s0 = sum f~, jx, jy = sum xi f~ (the sums of eq. phi and eq. u, P).
+template <class T, bool U = false>
+struct FPhiSums {
+  Consts K;
+  Work w;
+  const T *st;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    double acc = 0.0;
+    #pragma unroll
+    for (int q = 9; q < 18; ++q) acc += (double)st[q * K.plane + c];
+    w.phi[c] = acc;
+    double f[9];
+    #pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = (double)st[q * K.plane + c];
+    double s0 = 0.0, jx = 0.0, jy = 0.0;
+    #pragma unroll
+    for (int q = 0; q < 9; ++q) s0 += f[q];
+    #pragma unroll
+    for (int q = 0; q < 9; ++q) jx += K.xi0[q] * f[q];
+    #pragma unroll
+    for (int q = 0; q < 9; ++q) jy += K.xi1[q] * f[q];
+    w.s0[c] = s0;
+    w.jx[c] = jx;
+    w.jy[c] = jy;
+  }
 };
-inline FusedPlan make_fused_plan(const Consts &, int) { return FusedPlan{0}; }
-template <class T>
-inline void fused_step(const FusedPlan &, const Consts &, const T *, T *, hipStream_t,
-                       hipError_t &err) {
-  err = hipErrorNotSupported;
+
+// mu, grad mu, D, F, eq. u and eq. P at a cell.
+struct FMacF {
+  Consts K;
+  Work w;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    const Axis &X = K.ax[0], &Y = K.ax[1];
+    const double mc = mu_at(K, w.phi, i, j);
+    const double mxl = mu_at(K, w.phi, X.lo[i], j), mxh = mu_at(K, w.phi, X.hi[i], j);
+    const double myl = mu_at(K, w.phi, i, Y.lo[j]), myh = mu_at(K, w.phi, i, Y.hi[j]);
+    const double *a1 = X.d1 + 3 * i, *a2 = X.d2 + 3 * i, *b1 = Y.d1 + 3 * j, *b2 = Y.d2 + 3 * j;
+    const double dmux = a1[0] * mxl + a1[1] * mc + a1[2] * mxh;
+    const double dmuy = b1[0] * myl + b1[1] * mc + b1[2] * myh;
+    const double lapmu = (a2[0] * mxl + a2[1] * mc + a2[2] * mxh) +
+                         (b2[0] * myl + b2[1] * mc + b2[2] * myh);
+    const double D = K.mobility * lapmu;
+    const double ph = w.phi[c];
+    const double rh = rho_of<double>(K, ph);
+    const double Fx = -ph * dmux + (rh - K.rho_ref) * K.gx;
+    const double Fy = -ph * dmuy + (rh - K.rho_ref) * K.gy;
+    const double icr = 1.0 / (K.cs2 * rh);
+    const double ux = (w.jx[c] + K.hdtcs2 * Fx) * icr;
+    const double uy = (w.jy[c] + K.hdtcs2 * Fy) * icr;
+    const double grx = K.drho * stx(K, X.d1, w.phi, i, j);
+    const double gry = K.drho * sty(K, Y.d1, w.phi, i, j);
+    w.mu[c] = mc;
+    w.D[c] = D;
+    w.Fx[c] = Fx;
+    w.Fy[c] = Fy;
+    w.ux[c] = ux;
+    w.uy[c] = uy;
+    w.p[c] = w.s0[c] + K.hdtcs2 * (ux * grx + uy * gry - K.gam * rh * D);
+  }
+};
+
+// LDS of one tile.  A (bar+ on the tile and its ring) is dead once the faces
+// are computed; the face fluxes then reuse its space.
+struct TileLds {
+  union {
+    double A[18][W1][W1];
+    struct {
+      double X[12][TT][TT + 1];
+      double Y[12][TT + 1][TT];
+    } f;
+  } u;
+  double phi[W2][W2], mu[W2][W2], p[W2][W2];
+};
+
+// Accessor of the face code over the tile's LDS (bar+, phi, mu, p) and the
+// global D.  Global cell (x, y) maps to the tile window, periodic images
+// folded back; a window position holding another image of the same cell
+// holds the same value.  A handle carries the LDS offsets of the cell and of
+// its stencil neighbours, computed once per face.
+struct LAcc {
+  const Consts *K;
+  const Work *w;
+  const TileLds *L;
+  int x0, y0;
+  struct H {
+    int x, y;
+    int o1, lo1[2], hi1[2];  // offsets in the bar+ window (W1 x W1)
+    int o2, lo2[2], hi2[2];  // offsets in the scalar window (W2 x W2)
+  };
+  DFN int win(int g, int o, int n, int wd) const {
+    int d = g - o;
+    if (d < 0) d += n;
+    else if (d >= wd) d -= n;
+#ifdef DUGKS2P_WINDOW_CHECK
+    if (d < 0 || d >= wd) __builtin_trap();
+#endif
+    return d;
+  }
+  DFN H cell(int x, int y) const {
+    const Axis &X = K->ax[0], &Y = K->ax[1];
+    H h;
+    h.x = x;
+    h.y = y;
+    const int ax1 = win(x, x0 - 1, K->nx, W1), ay1 = win(y, y0 - 1, K->ny, W1);
+    const int lx1 = win(X.lo[x], x0 - 1, K->nx, W1), hx1 = win(X.hi[x], x0 - 1, K->nx, W1);
+    const int ly1 = win(Y.lo[y], y0 - 1, K->ny, W1), hy1 = win(Y.hi[y], y0 - 1, K->ny, W1);
+    h.o1 = ay1 * W1 + ax1;
+    h.lo1[0] = ay1 * W1 + lx1;
+    h.hi1[0] = ay1 * W1 + hx1;
+    h.lo1[1] = ly1 * W1 + ax1;
+    h.hi1[1] = hy1 * W1 + ax1;
+    const int ax2 = win(x, x0 - 2, K->nx, W2);
+    const int ay2 = win(y, y0 - 2, K->ny, W2);
+    const int lx2 = win(X.lo[x], x0 - 2, K->nx, W2), hx2 = win(X.hi[x], x0 - 2, K->nx, W2);
+    const int ly2 = win(Y.lo[y], y0 - 2, K->ny, W2), hy2 = win(Y.hi[y], y0 - 2, K->ny, W2);
+    h.o2 = ay2 * W2 + ax2;
+    h.lo2[0] = ay2 * W2 + lx2;
+    h.hi2[0] = ay2 * W2 + hx2;
+    h.lo2[1] = ly2 * W2 + ax2;
+    h.hi2[1] = hy2 * W2 + ax2;
+    return h;
+  }
+  DFN const double *Aq(int q) const { return &L->u.A[q][0][0]; }
+  DFN double A(int q, const H &h) const { return Aq(q)[h.o1]; }
+  DFN double pgrad(int a, int q, const H &h) const {
+    const double *wt = K->ax[a].pg + 3 * (a == 0 ? h.x : h.y);
+    const double *aq = Aq(q);
+    return wt[0] * aq[h.lo1[a]] + wt[1] * aq[h.o1] + wt[2] * aq[h.hi1[a]];
+  }
+  DFN double d1(int a, const H &h, const double *f) const {
+    const double *wt = K->ax[a].d1 + 3 * (a == 0 ? h.x : h.y);
+    return wt[0] * f[h.lo2[a]] + wt[1] * f[h.o2] + wt[2] * f[h.hi2[a]];
+  }
+  DFN double mu(const H &h) const { return (&L->mu[0][0])[h.o2]; }
+  DFN double phi(const H &h) const { return (&L->phi[0][0])[h.o2]; }
+  DFN double p(const H &h) const { return (&L->p[0][0])[h.o2]; }
+  DFN double D(const H &h) const { return w->D[(i64)h.y * K->ld + h.x]; }
+  DFN double dmu(int a, const H &h) const { return d1(a, h, &L->mu[0][0]); }
+  DFN double dphi(int a, const H &h) const { return d1(a, h, &L->phi[0][0]); }
+  DFN double dp(int a, const H &h) const { return d1(a, h, &L->p[0][0]); }
+};
+
+DFN int wrapi(int g, int n) {
+  int r = g % n;
+  return r < 0 ? r + n : r;
 }
+
+// One 14 x 14 tile with origin (x0, y0).
+template <class T, class R, bool U = false>
+struct FusedTile {
+  const Consts &K;
+  const Work &w;
+  const T *src;
+  T *dst;
+  int x0, y0;
+  TileLds *L;
+
+  struct TS {
+    R fx[12], fy[12];
+    bool hx, hy;
+  };
+
+  // global index along an axis of window offset o, or -1 outside a wall domain
+  DFN int gcol(int g, int n, int bc) const {
+    if (bc == 0) return wrapi(g, n);
+    return (g >= 0 && g < n) ? g : -1;
+  }
+
+  // P0: phi, mu, p on the tile and a two-cell ring.
+  DFN void p0(int tid) const {
+    for (int e = tid; e < W2 * W2; e += NTHR) {
+      const int lx = e % W2, ly = e / W2;
+      const int gx = gcol(x0 - 2 + lx, K.nx, K.ax[0].bc);
+      const int gy = gcol(y0 - 2 + ly, K.ny, K.ax[1].bc);
+      if (gx < 0 || gy < 0) continue;
+      const i64 c = (i64)gy * K.ld + gx;
+      L->phi[ly][lx] = w.phi[c];
+      L->mu[ly][lx] = w.mu[c];
+      L->p[ly][lx] = w.p[c];
+    }
+  }
+
+  // P1: Step 2 on the tile and a one-cell ring; tilde+ kept for the tile.
+  DFN void p1(int tid, TS &ts) const {
+    const int lx = tid % W1, ly = tid / W1;
+    const int gx = gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
+    const int gy = gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
+    if (gx < 0 || gy < 0) return;
+    const i64 c = (i64)gy * K.ld + gx;
+    const LAcc acc{&K, &w, L, x0, y0};
+    const LAcc::H hc = acc.cell(gx, gy);
+    const double ph = acc.phi(hc);
+    const double rh = rho_of<double>(K, ph);
+    Mac<R> m;
+    m.phi = (R)ph;
+    m.rho = (R)rh;
+    m.ux = (R)w.ux[c];
+    m.uy = (R)w.uy[c];
+    m.p = (R)acc.p(hc);
+    m.mu = (R)acc.mu(hc);
+    m.grx = (R)(K.drho * acc.dphi(0, hc));
+    m.gry = (R)(K.drho * acc.dphi(1, hc));
+    m.D = (R)w.D[c];
+    m.Fx = (R)w.Fx[c];
+    m.Fy = (R)w.Fy[c];
+    m.gpx = (R)acc.dp(0, hc);
+    m.gpy = (R)acc.dp(1, hc);
+    m.icr = (R)1.0 / ((R)K.cs2 * m.rho);
+    const R tf = tauf_of<R>(K, (R)ph, (R)rh);
+    R til[18], out[18];
+    #pragma unroll
+    for (int q = 0; q < 18; ++q) til[q] = (R)src[q * K.plane + c];
+    cell_barp<R, U>(K, m, tf, til, out);
+    #pragma unroll
+    for (int q = 0; q < 18; ++q) L->u.A[q][ly][lx] = (double)out[q];
+    // tilde+ of the tile's own cells waits in the output buffer for P4
+    if (lx >= 1 && lx <= TT && ly >= 1 && ly <= TT && x0 + lx - 1 < K.nx && y0 + ly - 1 < K.ny)
+      #pragma unroll
+      for (int q = 0; q < 18; ++q)
+        dst[q * K.plane + c] = (T)((R)(4.0 / 3.0) * (R)(double)out[q] - (R)(1.0 / 3.0) * til[q]);
+  }
+
+  // P2: Steps 3-4 at the x-face west of tile column tx and the y-face south
+  // of tile row ty.
+  DFN void p2(int tid, TS &ts) const {
+    const int tx = tid % W1, ty = tid / W1;
+    const LAcc acc{&K, &w, L, x0, y0};
+    ts.hx = ts.hy = false;
+    R out[18];
+    const bool perx = K.ax[0].bc == 0, pery = K.ax[1].bc == 0;
+    if (tx <= TT && ty < TT) {
+      const int k = x0 + tx, t = y0 + ty;
+      if (t < K.ny && k <= K.nx) {
+        face_core<0, R, LAcc, U>(K, acc, (perx && k == K.nx) ? 0 : k, t, out);
+        #pragma unroll
+        for (int q = 0; q < 18; ++q) {
+          const int s = xslot(q % 9);
+          if (s >= 0) ts.fx[(q / 9) * 6 + s] = out[q];
+        }
+        ts.hx = true;
+      }
+    }
+    if (tx < TT && ty <= TT) {
+      const int k = y0 + ty, t = x0 + tx;
+      if (t < K.nx && k <= K.ny) {
+        face_core<1, R, LAcc, U>(K, acc, (pery && k == K.ny) ? 0 : k, t, out);
+        #pragma unroll
+        for (int q = 0; q < 18; ++q) {
+          const int s = yslot(q % 9);
+          if (s >= 0) ts.fy[(q / 9) * 6 + s] = out[q];
+        }
+        ts.hy = true;
+      }
+    }
+  }
+
+  // P3: face values into LDS (over the dead bar+).
+  DFN void p3(int tid, const TS &ts) const {
+    const int tx = tid % W1, ty = tid / W1;
+    if (ts.hx)
+      #pragma unroll
+      for (int s = 0; s < 12; ++s) L->u.f.X[s][ty][tx] = (double)ts.fx[s];
+    if (ts.hy)
+      #pragma unroll
+      for (int s = 0; s < 12; ++s) L->u.f.Y[s][ty][tx] = (double)ts.fy[s];
+  }
+
+  // P4: Steps 5-6 (eq. updatef) for the tile's cells.
+  DFN void p4(int tid, const TS &ts) const {
+    const int lx = tid % W1, ly = tid / W1;
+    if (lx < 1 || lx > TT || ly < 1 || ly > TT) return;
+    const int cx = lx - 1, cy = ly - 1;
+    const int gx = x0 + cx, gy = y0 + cy;
+    if (gx >= K.nx || gy >= K.ny) return;
+    const i64 c = (i64)gy * K.ld + gx;
+    const R rx = (R)K.ax[0].rdt[gx], ry = (R)K.ax[1].rdt[gy];
+    #pragma unroll
+    for (int q = 0; q < 18; ++q) {
+      const int d = q % 9, sx = xslot(d), sy = yslot(d);
+      R W = (R)0.0, E = (R)0.0, S = (R)0.0, N = (R)0.0;
+      if (sx >= 0) {
+        W = (R)L->u.f.X[(q / 9) * 6 + sx][cy][cx];
+        E = (R)L->u.f.X[(q / 9) * 6 + sx][cy][cx + 1];
+      }
+      if (sy >= 0) {
+        S = (R)L->u.f.Y[(q / 9) * 6 + sy][cy][cx];
+        N = (R)L->u.f.Y[(q / 9) * 6 + sy][cy + 1][cx];
+      }
+      const R tilp = (R)dst[q * K.plane + c];
+      if (U) {
+        // (rx * e_x) (E - W) with e_x in {-1, 0, 1}; a zero term leaves tilp
+        const R tx = sx >= 0 ? (ex_of(d) > 0 ? rx : -rx) * (E - W) : (R)0.0;
+        const R ty = sy >= 0 ? (ey_of(d) > 0 ? ry : -ry) * (N - S) : (R)0.0;
+        dst[q * K.plane + c] = (T)(tilp - tx - ty);
+      } else {
+        dst[q * K.plane + c] =
+            (T)(tilp - rx * (R)K.xi0[d] * (E - W) - ry * (R)K.xi1[d] * (N - S));
+      }
+    }
+  }
+};
+
+inline int tiles_x(const Consts &K) { return (K.nx + TT - 1) / TT; }
+inline int tiles_y(const Consts &K) { return (K.ny + TT - 1) / TT; }
+
+// Workgroups are dealt to the 8 XCDs round robin; give each XCD a contiguous
+// run of tiles so that neighbouring tiles share its L2.
+DFN int xcd_tile(int b, int n) {
+  const int xcd = b % 8, slot = b / 8;
+  const int q = n / 8, r = n % 8;
+  return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+#if defined(__HIPCC__)
+template <class T, class R, bool U>
+__global__ __launch_bounds__(NTHR) void k_fused_tile(Consts K, Work w, const T *src, T *dst,
+                                                     int ntx, int ntiles) {
+  __shared__ TileLds L;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  FusedTile<T, R, U> ft{K, w, src, dst, (tile % ntx) * TT, (tile / ntx) * TT, &L};
+  typename FusedTile<T, R, U>::TS ts;
+  const int tid = threadIdx.x;
+  ft.p0(tid);
+  __syncthreads();
+  ft.p1(tid, ts);
+  __syncthreads();
+  ft.p2(tid, ts);
+  __syncthreads();
+  ft.p3(tid, ts);
+  __syncthreads();
+  ft.p4(tid, ts);
+}
+#endif
+
+// One fused time step (Ex: grid(functor, n0, n1) and tiles<T, R>(...)).
+// U: unit lattice speed (RT = 1/3), chosen by the host.
+template <class Ex, class T, class R, bool U>
+void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const T *src, T *dst) {
+  ex.grid(FPhiSums<T, U>{K, w, src}, K.nx, K.ny);
+  ex.grid(FMacF{K, w}, K.nx, K.ny);
+  ex.template tiles<T, R, U>(K, w, src, dst);
+}
+
 }  // namespace dg

@@ -200,6 +200,7 @@ inline Consts make_consts(const dugks2p_params *P, AxisHost &ax, AxisHost &ay) {
   K.hh = 0.5 * K.h;
   K.cs2 = P->rt;
   const double c = sqrt(3.0 * P->rt);
+  K.unit = c == 1.0 ? 1 : 0;
   K.k1 = 1.0 / K.cs2;
   K.k2 = 1.0 / (2.0 * K.cs2 * K.cs2);
   K.k3 = 1.0 / (2.0 * K.cs2);
@@ -295,7 +296,7 @@ inline Layout make_layout(const Consts &K, const AxisHost &ax, const AxisHost &a
   off += align256(L.state_bytes);
   L.state[1] = off;
   off += align256(L.state_bytes);
-  L.nwork = 16;
+  L.nwork = 19;
   L.work = off;
   off += L.nwork * align256(sizeof(double) * (size_t)K.plane);
   if (staged) {
@@ -367,10 +368,11 @@ inline Axis bind_axis(const AxisHost &a, unsigned char *base) {
 inline Work bind_work(const Layout &L, const Consts &K, unsigned char *base) {
   Work w;
   memset(&w, 0, sizeof w);
-  double **f[16] = {&w.phi, &w.rho, &w.mu, &w.dphx, &w.dphy, &w.dmux, &w.dmuy, &w.D,
-                    &w.Fx,  &w.Fy,  &w.ux, &w.uy,   &w.p,    &w.dpx,  &w.dpy,  &w.tauf};
+  double **f[19] = {&w.phi, &w.rho, &w.mu, &w.dphx, &w.dphy, &w.dmux, &w.dmuy,
+                    &w.D,   &w.Fx,  &w.Fy, &w.ux,   &w.uy,   &w.p,    &w.dpx,
+                    &w.dpy, &w.tauf, &w.s0, &w.jx,  &w.jy};
   const size_t fb = align256(sizeof(double) * (size_t)K.plane);
-  for (int k = 0; k < 16; ++k) *f[k] = (double *)(base + L.work + k * fb);
+  for (int k = 0; k < 19; ++k) *f[k] = (double *)(base + L.work + k * fb);
   if (L.barp) {
     w.barp = (double *)(base + L.barp);
     w.facex = (double *)(base + L.facex);

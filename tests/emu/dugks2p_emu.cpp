@@ -10,6 +10,7 @@
 
 #include <vector>
 
+#include "../../paper_1802_02868_amd/csrc/dugks2p_fused.hpp"
 #include "../../paper_1802_02868_amd/csrc/dugks2p_host.hpp"
 
 using namespace dg;
@@ -20,6 +21,24 @@ struct CpuEx {
   void grid(const F &f, int n0, int n1) {
     for (int j = 0; j < n1; ++j)
       for (int i = 0; i < n0; ++i) f(i, j);
+  }
+  // Every workgroup of the tile kernel in turn; each phase runs for all 256
+  // threads before the next (the barrier between phases).
+  template <class T, class R, bool U>
+  void tiles(const Consts &K, const Work &w, const T *src, T *dst) {
+    const int ntx = tiles_x(K), nt = ntx * tiles_y(K);
+    std::vector<TileLds> L(1);
+    std::vector<typename FusedTile<T, R, U>::TS> ts(NTHR);
+    for (int b = 0; b < nt; ++b) {
+      const int tile = xcd_tile(b, nt);
+      memset((void *)L.data(), 0xff, sizeof(TileLds));  // NaN poison: stray reads show
+      FusedTile<T, R, U> ft{K, w, src, dst, (tile % ntx) * TT, (tile / ntx) * TT, L.data()};
+      for (int t = 0; t < NTHR; ++t) ft.p0(t);
+      for (int t = 0; t < NTHR; ++t) ft.p1(t, ts[t]);
+      for (int t = 0; t < NTHR; ++t) ft.p2(t, ts[t]);
+      for (int t = 0; t < NTHR; ++t) ft.p3(t, ts[t]);
+      for (int t = 0; t < NTHR; ++t) ft.p4(t, ts[t]);
+    }
   }
 };
 }  // namespace
@@ -33,6 +52,7 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
   build_axis(ax, P->nx, P->bc_x, P->x_faces);
   build_axis(ay, P->ny, P->bc_y, P->y_faces);
   Consts K = make_consts(P, ax, ay);
+  const bool fused = P->kernel == DUGKS2P_KERNEL_FUSED;
   Layout L = make_layout(K, ax, ay, DUGKS2P_FP64, true);
   std::vector<unsigned char> mem(L.total + 256, 0);
   unsigned char *base = (unsigned char *)(((uintptr_t)mem.data() + 255) & ~(uintptr_t)255);
@@ -49,7 +69,12 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
   seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
   int cur = 0;
   for (long long n = 0; n < nsteps; ++n) {
-    seq_staged_step(ex, K, w, st[cur], st[1 - cur]);
+    if (fused && K.unit)
+      seq_fused_step<CpuEx, double, double, true>(ex, K, w, st[cur], st[1 - cur]);
+    else if (fused)
+      seq_fused_step<CpuEx, double, double, false>(ex, K, w, st[cur], st[1 - cur]);
+    else
+      seq_staged_step(ex, K, w, st[cur], st[1 - cur]);
     cur = 1 - cur;
   }
   for (int q = 0; q < 18; ++q)

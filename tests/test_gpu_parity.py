@@ -115,3 +115,51 @@ def test_nonfinite_detected(D):
     out = sim.monitors(raise_nonfinite=False)
     assert out[4] == 1
     torch.cuda.synchronize()
+
+
+FUSED = {k: v for k, v in CASES.items() if "upwind" not in k}
+
+
+@pytest.mark.parametrize("name", sorted(FUSED))
+def test_fused_fp64_matches_oracle(D, oracle_mod, name):
+    make, steps = FUSED[name]
+    sim, _ = _compare(D, oracle_mod, make(), steps, D.KERNEL_FUSED, "fused")
+    assert sim.kernel_kind == D.KERNEL_FUSED
+
+
+def test_auto_kernel_choice(D):
+    sim = D.Simulation.from_case(W.drop_case(n=16, radius=4.0))
+    assert sim.kernel_kind == D.KERNEL_FUSED
+    sim = D.Simulation.from_case(W.drop_case(n=16, radius=4.0, recon=1))
+    assert sim.kernel_kind == D.KERNEL_STAGED
+
+
+def test_fused_equals_staged_bitwise_rt(D):
+    case = W.rt_case(64, ny=256)
+    a = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)
+    b = D.Simulation.from_case(case, kernel=D.KERNEL_STAGED)
+    a.step(100)
+    b.step(100)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+
+
+FP32_TOL = 1e-4
+
+
+@pytest.mark.parametrize("kernel", ["staged", "fused"])
+def test_fp32_state_within_tolerance(D, oracle_mod, kernel):
+    """FP32-state step against the FP64 oracle: phi and u within 1e-4
+    (relative max-norm)."""
+    case = W.rt_case(64, ny=256)
+    steps = 500
+    k = D.KERNEL_STAGED if kernel == "staged" else D.KERNEL_FUSED
+    sim = D.Simulation.from_case(case, precision=D.FP32_STATE, kernel=k)
+    sim.step(steps)
+    mom = {k2: v.cpu().numpy() for k2, v in sim.moments().items()}
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    m = o.moments()
+    errs = {f: relmax(mom[f], m[f]) for f in ("phi", "ux", "uy")}
+    print("fp32", kernel, {f: "%.2e" % e for f, e in errs.items()}, flush=True)
+    for f, e in errs.items():
+        assert e <= FP32_TOL, (f, e)

@@ -64,3 +64,38 @@ def test_staged_kernel_logic_bitwise_equal_to_oracle(oracle_mod, name):
     m = o.moments()
     for k, f in enumerate(("phi", "rho", "ux", "uy", "p")):
         assert np.array_equal(mac[k], m[f]), f
+
+
+FUSED_CASES = {
+    "drop": (lambda: W.drop_case(n=32, radius=8.0), 10),
+    "rt_walls_ragged": (lambda: W.rt_case(30, ny=50, amp_frac=0.2), 10),
+    "poiseuille_stretched": (lambda: W.poiseuille_case(nx=4, ny=32), 10),
+    "bubble_four_walls": (lambda: W.bubble_case(32, 48, eo=20.0, mo=1e-3), 10),
+    "single_cell": (lambda: W.drop_case(n=1, radius=0.3, noise=1e-3), 3),
+    "tile_plus_one": (lambda: W.drop_case(n=15, radius=4.0), 5),
+}
+
+
+@pytest.mark.parametrize("name", sorted(FUSED_CASES))
+def test_fused_kernel_logic_bitwise_equal_to_oracle(oracle_mod, name):
+    """Host run of the fused tile kernel (phases with barrier semantics, LDS
+    poisoned with NaN) against the oracle."""
+    make, steps = FUSED_CASES[name]
+    case = make()
+    pops, mac = _emu.run(case, steps, kernel=2)
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    assert np.array_equal(pops, o.pops())
+
+
+def test_general_lattice_speed_kernel_logic(oracle_mod):
+    """RT != 1/3 (c != 1) runs the general-direction code of both kernels."""
+    case = W.drop_case(n=20, radius=5.0)
+    case.params["rt"] = 0.3
+    case.params["c_max"] = 0.0
+    case.params["cfl"] = 0.4
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(8)
+    for kernel in (1, 2):
+        pops, _ = _emu.run(case, 8, kernel=kernel)
+        assert np.array_equal(pops, o.pops()), kernel
