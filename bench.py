@@ -110,7 +110,8 @@ def main():
     mlups = cells * args.steps / (ms / 1e3) / 1e6
     mon = sim.monitors(raise_nonfinite=False)
 
-    bytes_per_cell = 288 if prec == D.FP64 else 144
+    # populations read + written once: 18 doubles, or the 76-byte FP32 state
+    bytes_per_cell = 288 if prec == D.FP64 else 152
     fused = sim.kernel_kind == D.KERNEL_FUSED
     launches_per_step = 1 if fused else 7
     achieved = bytes_per_cell * cells / (ms_per_step / 1e3) / 1e9

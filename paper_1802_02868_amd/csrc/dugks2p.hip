@@ -47,10 +47,10 @@ struct GpuEx {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess && err == hipSuccess) err = e;
   }
-  template <class T, class R, bool U>
-  void tiles(const Consts &K, const Work &w, const T *src, T *dst) {
+  template <class IO, class R, bool U>
+  void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x(K), nt = ntx * tiles_y(K);
-    hipLaunchKernelGGL((k_fused_tile<T, R, U>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst, ntx,
+    hipLaunchKernelGGL((k_fused_tile<IO, R, U>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst, ntx,
                        nt);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess && err == hipSuccess) err = e;
@@ -60,9 +60,8 @@ struct GpuEx {
 // Monitor partial sums: one 64 x 4 block of cells per workgroup, fixed-order
 // tree in LDS, one partial per block.  A single-workgroup pass then adds the
 // partials in block order, so the result is deterministic.
-template <class T>
-__global__ __launch_bounds__(256) void k_mon_partial(Consts K, Work w, const T *st,
-                                                     double *part) {
+template <class IO>
+__global__ __launch_bounds__(256) void k_mon_partial(Consts K, Work w, IO st, double *part) {
   __shared__ double sh[5][256];
   const int t = threadIdx.y * 64 + threadIdx.x;
   const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
@@ -115,23 +114,26 @@ __global__ __launch_bounds__(256) void k_mon_final(const double *part, long long
     for (int m = 0; m < 5; ++m) out[m] = sh[m][0];
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_pops_out(Consts K, const T *st, double *dst) {
+// State <-> FP64 [18][ny][nx], one thread per cell.
+template <class IO>
+__global__ __launch_bounds__(256) void k_pops_out(Consts K, IO st, double *dst) {
   const i64 n = (i64)K.nx * K.ny;
-  for (i64 k = (i64)blockIdx.x * 256 + threadIdx.x; k < 18 * n; k += (i64)gridDim.x * 256) {
-    const i64 q = k / n, r = k - q * n;
+  for (i64 r = (i64)blockIdx.x * 256 + threadIdx.x; r < n; r += (i64)gridDim.x * 256) {
     const i64 j = r / K.nx, i = r - j * K.nx;
-    dst[k] = (double)st[q * K.plane + j * K.ld + i];
+    double v[18];
+    st.load(j * K.ld + i, v);
+    for (int q = 0; q < 18; ++q) dst[q * n + r] = v[q];
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_pops_in(Consts K, const double *src, T *st) {
+template <class IO>
+__global__ __launch_bounds__(256) void k_pops_in(Consts K, const double *src, IO st) {
   const i64 n = (i64)K.nx * K.ny;
-  for (i64 k = (i64)blockIdx.x * 256 + threadIdx.x; k < 18 * n; k += (i64)gridDim.x * 256) {
-    const i64 q = k / n, r = k - q * n;
+  for (i64 r = (i64)blockIdx.x * 256 + threadIdx.x; r < n; r += (i64)gridDim.x * 256) {
     const i64 j = r / K.nx, i = r - j * K.nx;
-    st[q * K.plane + j * K.ld + i] = (T)src[k];
+    double v[18];
+    for (int q = 0; q < 18; ++q) v[q] = src[q * n + r];
+    st.store(j * K.ld + i, v);
   }
 }
 
@@ -176,23 +178,31 @@ std::string prepare(const dugks2p_params *P, Prepared &pr) {
   if (!(pr.K.dt > 0.0) || !isfinite(pr.K.dt)) return "time step is not positive";
   if (P->kernel == DUGKS2P_KERNEL_FUSED && P->recon != DUGKS2P_RECON_CENTRAL)
     return "the fused kernel implements CENTRAL reconstruction only";
+  if (P->precision == DUGKS2P_FP32_STATE && use_staged(P))
+    return "the FP32-state form runs on the fused kernel (CENTRAL reconstruction)";
   pr.L = make_layout(pr.K, pr.ax, pr.ay, P->precision, use_staged(P));
   return std::string();
 }
 
-template <class T>
+// One time step on the handle's stream.
 int launch_step(dugks2p *h) {
   GpuEx ex{h->stream, hipSuccess};
-  const T *src = (const T *)h->state[h->cur];
-  T *dst = (T *)h->state[1 - h->cur];
-  if (h->kernel == DUGKS2P_KERNEL_STAGED)
-    seq_staged_step<GpuEx, T, T>(ex, h->K, h->w, src, dst);
-  else
-  {
+  if (h->precision == DUGKS2P_FP64 && h->kernel == DUGKS2P_KERNEL_STAGED) {
+    seq_staged_step<GpuEx, double, double>(ex, h->K, h->w, (const double *)h->state[h->cur],
+                                           (double *)h->state[1 - h->cur]);
+  } else if (h->precision == DUGKS2P_FP64) {
+    const IoF64 src = io_f64(h->state[h->cur], h->K), dst = io_f64(h->state[1 - h->cur], h->K);
     if (h->K.unit)
-      seq_fused_step<GpuEx, T, T, true>(ex, h->K, h->w, src, dst);
+      seq_fused_step<GpuEx, IoF64, double, true>(ex, h->K, h->w, src, dst);
     else
-      seq_fused_step<GpuEx, T, T, false>(ex, h->K, h->w, src, dst);
+      seq_fused_step<GpuEx, IoF64, double, false>(ex, h->K, h->w, src, dst);
+  } else {
+    const IoE32 src = io_e32(h->state[h->cur], h->K, h->L);
+    const IoE32 dst = io_e32(h->state[1 - h->cur], h->K, h->L);
+    if (h->K.unit)
+      seq_fused_step<GpuEx, IoE32, double, true>(ex, h->K, h->w, src, dst);
+    else
+      seq_fused_step<GpuEx, IoE32, double, false>(ex, h->K, h->w, src, dst);
   }
   if (ex.err != hipSuccess)
     return fail(DUGKS2P_EHIP, std::string("kernel launch: ") + hipGetErrorString(ex.err));
@@ -201,10 +211,13 @@ int launch_step(dugks2p *h) {
   return DUGKS2P_OK;
 }
 
-template <class T>
+// Cell fields of the current state into the work arrays.
 int launch_macros(dugks2p *h) {
   GpuEx ex{h->stream, hipSuccess};
-  seq_macros(ex, h->K, h->w, (const T *)h->state[h->cur]);
+  if (h->precision == DUGKS2P_FP64)
+    seq_moments(ex, h->K, h->w, io_f64(h->state[h->cur], h->K));
+  else
+    seq_moments(ex, h->K, h->w, io_e32(h->state[h->cur], h->K, h->L));
   if (ex.err != hipSuccess)
     return fail(DUGKS2P_EHIP, std::string("kernel launch: ") + hipGetErrorString(ex.err));
   return DUGKS2P_OK;
@@ -280,17 +293,17 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
     }
     GpuEx ex{h->stream, hipSuccess};
     if (P->precision == DUGKS2P_FP64)
-      seq_init(ex, h->K, h->w, phi0, ux0, uy0, p0, (double *)h->state[0]);
+      seq_init(ex, h->K, h->w, phi0, ux0, uy0, p0, io_f64(h->state[0], h->K));
     else
-      seq_init(ex, h->K, h->w, phi0, ux0, uy0, p0, (float *)h->state[0]);
+      seq_init(ex, h->K, h->w, phi0, ux0, uy0, p0, io_e32(h->state[0], h->K, h->L));
     if (ex.err != hipSuccess) {
       rc = fail(DUGKS2P_EHIP, std::string("init launch: ") + hipGetErrorString(ex.err));
       break;
     }
   } while (0);
   if (rc != DUGKS2P_OK) {
-    hipStreamSynchronize(h->stream);
-    if (h->own_ws) hipFree(h->ws);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->own_ws) (void)hipFree(h->ws);
     delete h;
     return rc;
   }
@@ -302,7 +315,7 @@ int dugks2p_step(dugks2p *h, int64_t nsteps) {
   if (!h) return fail(DUGKS2P_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(DUGKS2P_EINVAL, "nsteps must be >= 0");
   for (int64_t n = 0; n < nsteps; ++n) {
-    const int rc = h->precision == DUGKS2P_FP64 ? launch_step<double>(h) : launch_step<float>(h);
+    const int rc = launch_step(h);
     if (rc) return rc;
   }
   return DUGKS2P_OK;
@@ -310,7 +323,7 @@ int dugks2p_step(dugks2p *h, int64_t nsteps) {
 
 int dugks2p_moments(dugks2p *h, double *phi, double *rho, double *ux, double *uy, double *p) {
   if (!h) return fail(DUGKS2P_EINVAL, "handle is NULL");
-  const int rc = h->precision == DUGKS2P_FP64 ? launch_macros<double>(h) : launch_macros<float>(h);
+  const int rc = launch_macros(h);
   if (rc) return rc;
   GpuEx ex{h->stream, hipSuccess};
   ex.grid(FMoments{h->K, h->w, phi, rho, ux, uy, p}, h->K.nx, h->K.ny);
@@ -321,17 +334,17 @@ int dugks2p_moments(dugks2p *h, double *phi, double *rho, double *ux, double *uy
 
 int dugks2p_monitors(dugks2p *h, double out[6]) {
   if (!h || !out) return fail(DUGKS2P_EINVAL, "NULL argument");
-  int rc = h->precision == DUGKS2P_FP64 ? launch_macros<double>(h) : launch_macros<float>(h);
+  const int rc = launch_macros(h);
   if (rc) return rc;
   const dim3 b(64, 4), g((h->K.nx + 63) / 64, (h->K.ny + 3) / 4);
   const long long nb = (long long)g.x * g.y;
   if (nb > (long long)h->L.mon_blocks) return fail(DUGKS2P_EHIP, "monitor partial buffer too small");
   if (h->precision == DUGKS2P_FP64)
-    hipLaunchKernelGGL(k_mon_partial<double>, g, b, 0, h->stream, h->K, h->w,
-                       (const double *)h->state[h->cur], h->mon_part);
+    hipLaunchKernelGGL(k_mon_partial<IoF64>, g, b, 0, h->stream, h->K, h->w,
+                       io_f64(h->state[h->cur], h->K), h->mon_part);
   else
-    hipLaunchKernelGGL(k_mon_partial<float>, g, b, 0, h->stream, h->K, h->w,
-                       (const float *)h->state[h->cur], h->mon_part);
+    hipLaunchKernelGGL(k_mon_partial<IoE32>, g, b, 0, h->stream, h->K, h->w,
+                       io_e32(h->state[h->cur], h->K, h->L), h->mon_part);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(k_mon_final, dim3(1), dim3(256), 0, h->stream, h->mon_part, nb, h->mon_out);
   HIPCHK(hipGetLastError());
@@ -351,11 +364,11 @@ int dugks2p_monitors(dugks2p *h, double out[6]) {
 int dugks2p_get_populations(dugks2p *h, double *dst) {
   if (!h || !dst) return fail(DUGKS2P_EINVAL, "NULL argument");
   if (h->precision == DUGKS2P_FP64)
-    hipLaunchKernelGGL(k_pops_out<double>, dim3(1024), dim3(256), 0, h->stream, h->K,
-                       (const double *)h->state[h->cur], dst);
+    hipLaunchKernelGGL(k_pops_out<IoF64>, dim3(1024), dim3(256), 0, h->stream, h->K,
+                       io_f64(h->state[h->cur], h->K), dst);
   else
-    hipLaunchKernelGGL(k_pops_out<float>, dim3(1024), dim3(256), 0, h->stream, h->K,
-                       (const float *)h->state[h->cur], dst);
+    hipLaunchKernelGGL(k_pops_out<IoE32>, dim3(1024), dim3(256), 0, h->stream, h->K,
+                       io_e32(h->state[h->cur], h->K, h->L), dst);
   HIPCHK(hipGetLastError());
   return DUGKS2P_OK;
 }
@@ -363,11 +376,11 @@ int dugks2p_get_populations(dugks2p *h, double *dst) {
 int dugks2p_set_populations(dugks2p *h, const double *src) {
   if (!h || !src) return fail(DUGKS2P_EINVAL, "NULL argument");
   if (h->precision == DUGKS2P_FP64)
-    hipLaunchKernelGGL(k_pops_in<double>, dim3(1024), dim3(256), 0, h->stream, h->K, src,
-                       (double *)h->state[h->cur]);
+    hipLaunchKernelGGL(k_pops_in<IoF64>, dim3(1024), dim3(256), 0, h->stream, h->K, src,
+                       io_f64(h->state[h->cur], h->K));
   else
-    hipLaunchKernelGGL(k_pops_in<float>, dim3(1024), dim3(256), 0, h->stream, h->K, src,
-                       (float *)h->state[h->cur]);
+    hipLaunchKernelGGL(k_pops_in<IoE32>, dim3(1024), dim3(256), 0, h->stream, h->K, src,
+                       io_e32(h->state[h->cur], h->K, h->L));
   HIPCHK(hipGetLastError());
   return DUGKS2P_OK;
 }
@@ -394,8 +407,8 @@ int dugks2p_kernel(const dugks2p *h) { return h ? h->kernel : DUGKS2P_EINVAL; }
 
 int dugks2p_destroy(dugks2p *h) {
   if (!h) return DUGKS2P_OK;
-  hipStreamSynchronize(h->stream);
-  if (h->own_ws) hipFree(h->ws);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->own_ws) (void)hipFree(h->ws);
   delete h;
   return DUGKS2P_OK;
 }

@@ -161,6 +161,76 @@ struct Work {
 };
 
 // ---------------------------------------------------------------------------
+// State storage.  Populations are handled as 18 doubles per cell
+// (q = 0..8 f~, 9..17 g~); an IO policy maps them to memory.
+// ---------------------------------------------------------------------------
+
+// FP64 state: 18 planes of doubles.
+struct IoF64 {
+  double *p;
+  i64 plane;
+  DFN void load(i64 c, double v[18]) const {
+#pragma unroll
+    for (int q = 0; q < 18; ++q) v[q] = p[q * plane + c];
+  }
+  DFN void store(i64 c, const double v[18]) const {
+#pragma unroll
+    for (int q = 0; q < 18; ++q) p[q * plane + c] = v[q];
+  }
+  DFN void load_f(i64 c, double f[9]) const {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = p[q * plane + c];
+  }
+  // eq. phi: phi = sum_i g~_i, ascending i
+  DFN double phi(i64 c) const {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 9; q < 18; ++q) a += p[q * plane + c];
+    return a;
+  }
+};
+
+// FP32 state with an FP64 order-parameter channel: f~ as 9 floats, the cell
+// order parameter phi = sum g~ as one double, and g~_i - w_i phi (i = 1..8)
+// as floats (the i = 0 deviation is minus the sum of the others).  Storing
+// phi exactly keeps the rounding of g~ out of phi and hence out of the
+// chemical potential and the surface force.  76 bytes per cell.
+struct IoE32 {
+  float *f;    // 17 planes: f~_0..8, then g~_i - w_i phi for i = 1..8
+  double *ph;  // 1 plane: phi
+  i64 plane;
+  DFN void load(i64 c, double v[18]) const {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) v[q] = (double)f[q * plane + c];
+    double d[9], s = 0.0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      d[i] = (double)f[(8 + i) * plane + c];
+      s += d[i];
+    }
+    d[0] = -s;
+    const double phi = ph[c];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[9 + i] = w9_lit(i) * phi + d[i];
+  }
+  DFN void store(i64 c, const double v[18]) const {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q * plane + c] = (float)v[q];
+    double phi = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) phi += v[9 + i];
+    ph[c] = phi;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) f[(8 + i) * plane + c] = (float)(v[9 + i] - w9_lit(i) * phi);
+  }
+  DFN void load_f(i64 c, double fo[9]) const {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fo[q] = (double)f[q * plane + c];
+  }
+  DFN double phi(i64 c) const { return ph[c]; }
+};
+
+// ---------------------------------------------------------------------------
 // Staged step: one functor per stage, one call per cell or face.
 // ---------------------------------------------------------------------------
 
@@ -173,7 +243,7 @@ struct FPhi {
   DFN void operator()(int i, int j) const {
     const i64 c = (i64)j * K.ld + i;
     double acc = 0.0;
-    #pragma unroll
+#pragma unroll
     for (int q = 9; q < 18; ++q) acc += (double)st[q * K.plane + c];
     w.phi[c] = acc;
     w.rho[c] = rho_of<double>(K, acc);
@@ -219,13 +289,13 @@ struct FMacro {
     w.Fy[c] = Fy;
     double s0 = 0.0, jx = 0.0, jy = 0.0;
     double f[9];
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 9; ++q) f[q] = (double)st[q * K.plane + c];
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 9; ++q) s0 += f[q];
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 9; ++q) jx += K.xi0[q] * f[q];
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 9; ++q) jy += K.xi1[q] * f[q];
     const double icr = 1.0 / (K.cs2 * rh);
     const double ux = (jx + K.hdtcs2 * Fx) * icr;
@@ -263,7 +333,7 @@ DFN void cell_barp(const Consts &K, const Mac<R> &m, R tf, const R til[18], R ou
   const R den = (R)1.0 / ((R)2.0 * tf + (R)K.dt);
   const R fca = ((R)2.0 * tf - (R)K.h) * den, fcb = (R)3.0 * (R)K.h * den,
           fcc = (R)3.0 * tf * (R)K.h * den;
-  #pragma unroll
+#pragma unroll
   for (int i2 = 0; i2 < 9; ++i2) {
     R feq, geq, ff, fg;
     point_eq1<R, U>(K, m, uu, i2, feq, geq, ff, fg);
@@ -288,10 +358,10 @@ struct FCell {
     Mac<R> m;
     cell_mac(K, w, c, m);
     R til[18], out[18];
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 18; ++q) til[q] = (R)st[q * K.plane + c];
     cell_barp<R>(K, m, tf, til, out);
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 18; ++q) w.barp[q * K.plane + c] = (double)out[q];
   }
 };
@@ -319,7 +389,7 @@ template <class R, bool U = false>
 DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R out[18]) {
   Mac<R> m;
   R phib = (R)0.0;
-  #pragma unroll
+#pragma unroll
   for (int i = 0; i < 9; ++i) phib += bar[9 + i];
   m.phi = phib;
   m.rho = rho_of<R>(K, phib);
@@ -333,11 +403,11 @@ DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R 
   m.Fy = -phib * fl.gmy + (m.rho - (R)K.rho_ref) * (R)K.gy;
   m.icr = (R)1.0 / ((R)K.cs2 * m.rho);
   R s0 = (R)0.0, jx = (R)0.0, jy = (R)0.0;
-  #pragma unroll
+#pragma unroll
   for (int i = 0; i < 9; ++i) s0 += bar[i];
-  #pragma unroll
+#pragma unroll
   for (int i = 0; i < 9; ++i) jx += (R)K.xi0[i] * bar[i];
-  #pragma unroll
+#pragma unroll
   for (int i = 0; i < 9; ++i) jy += (R)K.xi1[i] * bar[i];
   m.ux = (jx + (R)K.hhcs2 * m.Fx) * m.icr;
   m.uy = (jy + (R)K.hhcs2 * m.Fy) * m.icr;
@@ -346,7 +416,7 @@ DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R 
   const R tf = tauf_of<R>(K, phib, m.rho);
   const R den = (R)1.0 / ((R)2.0 * tf + (R)K.h);
   const R fk1 = (R)2.0 * tf * den, fk2 = (R)K.h * den, fk3 = tf * (R)K.h * den;
-  #pragma unroll
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
     R feq, geq, ff, fg;
     point_eq1<R, U>(K, m, uu, i, feq, geq, ff, fg);
@@ -374,7 +444,7 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
     const double off = cl < 0 ? ax.foffr[k] : ax.foffl[k];
     const int nout = cl < 0 ? -1 : 1;
     const typename Acc::H HC = acc.cell(CX(cc), CY(cc));
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int i = q % 9;
       const int en = A == 0 ? ex_of(i) : ey_of(i);
@@ -386,7 +456,7 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
       const R sgx = A == 0 ? Gn : Gt, sgy = A == 0 ? Gt : Gn;
       bar[q] = val - h * (U ? edot<R>(i, sgx, sgy) : (R)K.xi0[i] * sgx + (R)K.xi1[i] * sgy);
     }
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int i = q % 9;
       const int en = A == 0 ? ex_of(i) : ey_of(i);
@@ -402,7 +472,7 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
     fl.gpx = A == 0 ? (R)0.0 : (R)tp;
     fl.gpy = A == 0 ? (R)tp : (R)0.0;
     face_dist<R, U>(K, fl, bar, out);
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int i = q % 9;
       const int en = A == 0 ? ex_of(i) : ey_of(i);
@@ -415,7 +485,7 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
   fw.wl = ax.fwl[k];
   fw.wr = ax.fwr[k];
   fw.inv = ax.finv[k];
-  #pragma unroll
+#pragma unroll
   for (int q = 0; q < 18; ++q) {
     const int i = q % 9;
     const int en = A == 0 ? ex_of(i) : ey_of(i);
@@ -504,7 +574,7 @@ struct FXFace {
     R out[18];
     const GAcc acc{&K, &w};
     face_core<0, R>(K, acc, k, j, out);
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 18; ++q) w.facex[q * K.xplane + (i64)j * K.nfx + k] = (double)out[q];
   }
 };
@@ -516,7 +586,7 @@ struct FYFace {
     R out[18];
     const GAcc acc{&K, &w};
     face_core<1, R>(K, acc, k, i, out);
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 18; ++q) w.facey[q * K.yplane + (i64)k * K.ld + i] = (double)out[q];
   }
 };
@@ -533,7 +603,7 @@ struct FUpdate {
     const int ie = (K.ax[0].bc == 0 && i == K.nx - 1) ? 0 : i + 1;
     const int jn = (K.ax[1].bc == 0 && j == K.ny - 1) ? 0 : j + 1;
     const R rx = (R)K.ax[0].rdt[i], ry = (R)K.ax[1].rdt[j];
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int d = q % 9;
       const R bp = (R)w.barp[q * K.plane + c];
@@ -582,23 +652,25 @@ struct FInit1 {
   }
 };
 
-template <class T>
+template <class IO>
 struct FInit2 {
   Consts K;
   Work w;
-  T *dst;
+  IO dst;
   DFN void operator()(int i, int j) const {
     const i64 c = (i64)j * K.ld + i;
     Mac<double> m;
     cell_mac(K, w, c, m);
     const double uu = m.ux * m.ux + m.uy * m.uy;
-    #pragma unroll
+    double v[18];
+#pragma unroll
     for (int i2 = 0; i2 < 9; ++i2) {
       double feq, geq, ff, fg;
       point_eq1(K, m, uu, i2, feq, geq, ff, fg);
-      dst[i2 * K.plane + c] = (T)(feq - K.hdt * ff);
-      dst[(9 + i2) * K.plane + c] = (T)(geq - K.hdt * fg);
+      v[i2] = feq - K.hdt * ff;
+      v[9 + i2] = geq - K.hdt * fg;
     }
+    dst.store(c, v);
   }
 };
 
@@ -612,7 +684,7 @@ struct FMoments {
   DFN void operator()(int i, int j) const {
     const i64 c = (i64)j * K.ld + i, o = (i64)j * K.nx + i;
     if (phi) phi[o] = w.phi[c];
-    if (rho) rho[o] = w.rho[c];
+    if (rho) rho[o] = rho_of<double>(K, w.phi[c]);
     if (ux) ux[o] = w.ux[c];
     if (uy) uy[o] = w.uy[c];
     if (p) p[o] = w.p[c];
@@ -621,25 +693,26 @@ struct FMoments {
 
 // Per-cell monitor terms: phi |V|, rho |u|^2 |V| / 2, free-energy density
 // (eqs. doublewell, freeenergyfunction) times |V|, |u|, non-finite count.
-template <class T>
-DFN void monitor_terms(const Consts &K, const Work &w, const T *st, int i, int j, double out[5]) {
+template <class IO>
+DFN void monitor_terms(const Consts &K, const Work &w, const IO &io, int i, int j, double out[5]) {
   const i64 c = (i64)j * K.ld + i;
   const double V = K.ax[0].w[i] * K.ax[1].w[j];
   const double ph = w.phi[c];
+  const double rh = rho_of<double>(K, ph);
   const double u2 = w.ux[c] * w.ux[c] + w.uy[c] * w.uy[c];
   const double a1 = ph - K.phi_a, b1 = ph - K.phi_b;
   const double psi = K.beta * a1 * a1 * b1 * b1;
-  const double g2 = w.dphx[c] * w.dphx[c] + w.dphy[c] * w.dphy[c];
+  const double gx = stx(K, K.ax[0].d1, w.phi, i, j), gy = sty(K, K.ax[1].d1, w.phi, i, j);
+  const double g2 = gx * gx + gy * gy;
   out[0] = ph * V;
-  out[1] = 0.5 * w.rho[c] * u2 * V;
+  out[1] = 0.5 * rh * u2 * V;
   out[2] = (psi + 0.5 * K.kappa * g2) * V;
   out[3] = u2;  // max of u2, sqrt at the end
-  double bad = 0.0;
-  #pragma unroll
-  for (int q = 0; q < 18; ++q) {
-    const double v = (double)st[q * K.plane + c];
-    if (!(v - v == 0.0)) bad += 1.0;
-  }
+  double v[18], bad = 0.0;
+  io.load(c, v);
+#pragma unroll
+  for (int q = 0; q < 18; ++q)
+    if (!(v[q] - v[q] == 0.0)) bad += 1.0;
   out[4] = bad;
 }
 

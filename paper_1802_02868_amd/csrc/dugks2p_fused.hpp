@@ -26,27 +26,20 @@ DFN int xslot(int i) { return i == 1 ? 0 : (i == 3 ? 1 : (i >= 5 ? i - 3 : -1));
 DFN int yslot(int i) { return i == 2 ? 0 : (i == 4 ? 1 : (i >= 5 ? i - 3 : -1)); }
 
 // phi, s0 = sum f~, jx, jy = sum xi f~ (the sums of eq. phi and eq. u, P).
-template <class T, bool U = false>
+template <class IO, bool U = false>
 struct FPhiSums {
   Consts K;
   Work w;
-  const T *st;
+  IO st;
   DFN void operator()(int i, int j) const {
     const i64 c = (i64)j * K.ld + i;
-    double acc = 0.0;
-    #pragma unroll
-    for (int q = 9; q < 18; ++q) acc += (double)st[q * K.plane + c];
-    w.phi[c] = acc;
+    w.phi[c] = st.phi(c);
     double f[9];
-    #pragma unroll
-    for (int q = 0; q < 9; ++q) f[q] = (double)st[q * K.plane + c];
-    double s0 = 0.0, jx = 0.0, jy = 0.0;
-    #pragma unroll
+    st.load_f(c, f);
+    double s0 = 0.0, jx, jy;
+#pragma unroll
     for (int q = 0; q < 9; ++q) s0 += f[q];
-    #pragma unroll
-    for (int q = 0; q < 9; ++q) jx += K.xi0[q] * f[q];
-    #pragma unroll
-    for (int q = 0; q < 9; ++q) jy += K.xi1[q] * f[q];
+    xi_sums<double, U>(K, f, jx, jy);
     w.s0[c] = s0;
     w.jx[c] = jx;
     w.jy[c] = jy;
@@ -175,12 +168,12 @@ DFN int wrapi(int g, int n) {
 }
 
 // One 14 x 14 tile with origin (x0, y0).
-template <class T, class R, bool U = false>
+template <class IO, class R, bool U = false>
 struct FusedTile {
   const Consts &K;
   const Work &w;
-  const T *src;
-  T *dst;
+  IO src;
+  IO dst;
   int x0, y0;
   TileLds *L;
 
@@ -237,16 +230,20 @@ struct FusedTile {
     m.icr = (R)1.0 / ((R)K.cs2 * m.rho);
     const R tf = tauf_of<R>(K, (R)ph, (R)rh);
     R til[18], out[18];
-    #pragma unroll
-    for (int q = 0; q < 18; ++q) til[q] = (R)src[q * K.plane + c];
+    double tv[18];
+    src.load(c, tv);
+#pragma unroll
+    for (int q = 0; q < 18; ++q) til[q] = (R)tv[q];
     cell_barp<R, U>(K, m, tf, til, out);
-    #pragma unroll
+#pragma unroll
     for (int q = 0; q < 18; ++q) L->u.A[q][ly][lx] = (double)out[q];
     // tilde+ of the tile's own cells waits in the output buffer for P4
-    if (lx >= 1 && lx <= TT && ly >= 1 && ly <= TT && x0 + lx - 1 < K.nx && y0 + ly - 1 < K.ny)
-      #pragma unroll
+    if (lx >= 1 && lx <= TT && ly >= 1 && ly <= TT && x0 + lx - 1 < K.nx && y0 + ly - 1 < K.ny) {
+#pragma unroll
       for (int q = 0; q < 18; ++q)
-        dst[q * K.plane + c] = (T)((R)(4.0 / 3.0) * (R)(double)out[q] - (R)(1.0 / 3.0) * til[q]);
+        tv[q] = (double)((R)(4.0 / 3.0) * (R)(double)out[q] - (R)(1.0 / 3.0) * til[q]);
+      dst.store(c, tv);
+    }
   }
 
   // P2: Steps 3-4 at the x-face west of tile column tx and the y-face south
@@ -261,7 +258,7 @@ struct FusedTile {
       const int k = x0 + tx, t = y0 + ty;
       if (t < K.ny && k <= K.nx) {
         face_core<0, R, LAcc, U>(K, acc, (perx && k == K.nx) ? 0 : k, t, out);
-        #pragma unroll
+#pragma unroll
         for (int q = 0; q < 18; ++q) {
           const int s = xslot(q % 9);
           if (s >= 0) ts.fx[(q / 9) * 6 + s] = out[q];
@@ -273,7 +270,7 @@ struct FusedTile {
       const int k = y0 + ty, t = x0 + tx;
       if (t < K.nx && k <= K.ny) {
         face_core<1, R, LAcc, U>(K, acc, (pery && k == K.ny) ? 0 : k, t, out);
-        #pragma unroll
+#pragma unroll
         for (int q = 0; q < 18; ++q) {
           const int s = yslot(q % 9);
           if (s >= 0) ts.fy[(q / 9) * 6 + s] = out[q];
@@ -287,10 +284,10 @@ struct FusedTile {
   DFN void p3(int tid, const TS &ts) const {
     const int tx = tid % W1, ty = tid / W1;
     if (ts.hx)
-      #pragma unroll
+#pragma unroll
       for (int s = 0; s < 12; ++s) L->u.f.X[s][ty][tx] = (double)ts.fx[s];
     if (ts.hy)
-      #pragma unroll
+#pragma unroll
       for (int s = 0; s < 12; ++s) L->u.f.Y[s][ty][tx] = (double)ts.fy[s];
   }
 
@@ -303,7 +300,9 @@ struct FusedTile {
     if (gx >= K.nx || gy >= K.ny) return;
     const i64 c = (i64)gy * K.ld + gx;
     const R rx = (R)K.ax[0].rdt[gx], ry = (R)K.ax[1].rdt[gy];
-    #pragma unroll
+    double tv[18];
+    dst.load(c, tv);
+#pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int d = q % 9, sx = xslot(d), sy = yslot(d);
       R W = (R)0.0, E = (R)0.0, S = (R)0.0, N = (R)0.0;
@@ -315,17 +314,17 @@ struct FusedTile {
         S = (R)L->u.f.Y[(q / 9) * 6 + sy][cy][cx];
         N = (R)L->u.f.Y[(q / 9) * 6 + sy][cy + 1][cx];
       }
-      const R tilp = (R)dst[q * K.plane + c];
+      const R tilp = (R)tv[q];
       if (U) {
         // (rx * e_x) (E - W) with e_x in {-1, 0, 1}; a zero term leaves tilp
         const R tx = sx >= 0 ? (ex_of(d) > 0 ? rx : -rx) * (E - W) : (R)0.0;
         const R ty = sy >= 0 ? (ey_of(d) > 0 ? ry : -ry) * (N - S) : (R)0.0;
-        dst[q * K.plane + c] = (T)(tilp - tx - ty);
+        tv[q] = (double)(tilp - tx - ty);
       } else {
-        dst[q * K.plane + c] =
-            (T)(tilp - rx * (R)K.xi0[d] * (E - W) - ry * (R)K.xi1[d] * (N - S));
+        tv[q] = (double)(tilp - rx * (R)K.xi0[d] * (E - W) - ry * (R)K.xi1[d] * (N - S));
       }
     }
+    dst.store(c, tv);
   }
 };
 
@@ -341,13 +340,13 @@ DFN int xcd_tile(int b, int n) {
 }
 
 #if defined(__HIPCC__)
-template <class T, class R, bool U>
-__global__ __launch_bounds__(NTHR) void k_fused_tile(Consts K, Work w, const T *src, T *dst,
-                                                     int ntx, int ntiles) {
+template <class IO, class R, bool U>
+__global__ __launch_bounds__(NTHR) void k_fused_tile(Consts K, Work w, IO src, IO dst, int ntx,
+                                                     int ntiles) {
   __shared__ TileLds L;
   const int tile = xcd_tile(blockIdx.x, ntiles);
-  FusedTile<T, R, U> ft{K, w, src, dst, (tile % ntx) * TT, (tile / ntx) * TT, &L};
-  typename FusedTile<T, R, U>::TS ts;
+  FusedTile<IO, R, U> ft{K, w, src, dst, (tile % ntx) * TT, (tile / ntx) * TT, &L};
+  typename FusedTile<IO, R, U>::TS ts;
   const int tid = threadIdx.x;
   ft.p0(tid);
   __syncthreads();
@@ -363,11 +362,19 @@ __global__ __launch_bounds__(NTHR) void k_fused_tile(Consts K, Work w, const T *
 
 // One fused time step (Ex: grid(functor, n0, n1) and tiles<T, R>(...)).
 // U: unit lattice speed (RT = 1/3), chosen by the host.
-template <class Ex, class T, class R, bool U>
-void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const T *src, T *dst) {
-  ex.grid(FPhiSums<T, U>{K, w, src}, K.nx, K.ny);
+template <class Ex, class IO, class R, bool U>
+void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const IO &src, const IO &dst) {
+  ex.grid(FPhiSums<IO, U>{K, w, src}, K.nx, K.ny);
   ex.grid(FMacF{K, w}, K.nx, K.ny);
-  ex.template tiles<T, R, U>(K, w, src, dst);
+  ex.template tiles<IO, R, U>(K, w, src, dst);
+}
+
+// Cell fields of the current state for moments and monitors (phi, mu, D, F,
+// u, p in the work arrays).
+template <class Ex, class IO>
+void seq_moments(Ex &ex, const Consts &K, const Work &w, const IO &src) {
+  ex.grid(FPhiSums<IO, false>{K, w, src}, K.nx, K.ny);
+  ex.grid(FMacF{K, w}, K.nx, K.ny);
 }
 
 }  // namespace dg

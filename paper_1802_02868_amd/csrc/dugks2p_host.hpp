@@ -267,6 +267,7 @@ struct Layout {
   size_t mon;        // monitor partials
   size_t total;
   size_t state_bytes;
+  size_t f32_planes;  // byte offset of the FP64 phi plane in an FP32 state
   int nwork;
   size_t mon_blocks;
 };
@@ -290,8 +291,11 @@ inline Layout make_layout(const Consts &K, const AxisHost &ax, const AxisHost &a
   off += align256(axis_table_bytes(ax));
   L.tables[1] = off;
   off += align256(axis_table_bytes(ay));
-  const size_t tsize = precision == DUGKS2P_FP64 ? sizeof(double) : sizeof(float);
-  L.state_bytes = 18 * (size_t)K.plane * tsize;
+  // FP64: 18 double planes.  FP32 state: 17 float planes + 1 double plane
+  // (layout of IoE32).
+  L.f32_planes = align256(17 * sizeof(float) * (size_t)K.plane);
+  L.state_bytes = precision == DUGKS2P_FP64 ? 18 * sizeof(double) * (size_t)K.plane
+                                            : L.f32_planes + sizeof(double) * (size_t)K.plane;
   L.state[0] = off;
   off += align256(L.state_bytes);
   L.state[1] = off;
@@ -384,18 +388,23 @@ inline Work bind_work(const Layout &L, const Consts &K, unsigned char *base) {
 // ---------------------------------------------------------------------------
 // Stage sequences (Ex provides grid(functor, n0, n1)).
 // ---------------------------------------------------------------------------
-template <class Ex, class T>
+template <class Ex, class IO>
 void seq_init(Ex &ex, const Consts &K, const Work &w, const double *phi0, const double *ux0,
-              const double *uy0, const double *p0, T *dst) {
+              const double *uy0, const double *p0, const IO &dst) {
   ex.grid(FInit0{K, w, phi0, ux0, uy0, p0}, K.nx, K.ny);
   ex.grid(FMu{K, w}, K.nx, K.ny);
   ex.grid(FInit1{K, w}, K.nx, K.ny);
-  ex.grid(FInit2<T>{K, w, dst}, K.nx, K.ny);
+  ex.grid(FInit2<IO>{K, w, dst}, K.nx, K.ny);
 }
 
-// Cell macroscopic fields of the current state (Step 7).
+inline IoF64 io_f64(void *state, const Consts &K) { return IoF64{(double *)state, K.plane}; }
+inline IoE32 io_e32(void *state, const Consts &K, const Layout &L) {
+  return IoE32{(float *)state, (double *)((unsigned char *)state + L.f32_planes), K.plane};
+}
+
+// Cell macroscopic fields of the current state (Step 7), staged form.
 template <class Ex, class T>
-void seq_macros(Ex &ex, const Consts &K, const Work &w, const T *src) {
+void seq_staged_macros(Ex &ex, const Consts &K, const Work &w, const T *src) {
   ex.grid(FPhi<T>{K, w, src}, K.nx, K.ny);
   ex.grid(FMu{K, w}, K.nx, K.ny);
   ex.grid(FMacro<T>{K, w, src}, K.nx, K.ny);
@@ -405,7 +414,7 @@ void seq_macros(Ex &ex, const Consts &K, const Work &w, const T *src) {
 // R: arithmetic type of Steps 2-6 (double; float for the FP32-state form).
 template <class Ex, class T, class R = double>
 void seq_staged_step(Ex &ex, const Consts &K, const Work &w, const T *src, T *dst) {
-  seq_macros(ex, K, w, src);
+  seq_staged_macros(ex, K, w, src);
   ex.grid(FCell<T, R>{K, w, src}, K.nx, K.ny);
   ex.grid(FXFace<R>{K, w}, K.nfx, K.ny);
   ex.grid(FYFace<R>{K, w}, K.nx, K.nfy);

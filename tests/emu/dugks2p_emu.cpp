@@ -24,15 +24,15 @@ struct CpuEx {
   }
   // Every workgroup of the tile kernel in turn; each phase runs for all 256
   // threads before the next (the barrier between phases).
-  template <class T, class R, bool U>
-  void tiles(const Consts &K, const Work &w, const T *src, T *dst) {
+  template <class IO, class R, bool U>
+  void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x(K), nt = ntx * tiles_y(K);
     std::vector<TileLds> L(1);
-    std::vector<typename FusedTile<T, R, U>::TS> ts(NTHR);
+    std::vector<typename FusedTile<IO, R, U>::TS> ts(NTHR);
     for (int b = 0; b < nt; ++b) {
       const int tile = xcd_tile(b, nt);
       memset((void *)L.data(), 0xff, sizeof(TileLds));  // NaN poison: stray reads show
-      FusedTile<T, R, U> ft{K, w, src, dst, (tile % ntx) * TT, (tile / ntx) * TT, L.data()};
+      FusedTile<IO, R, U> ft{K, w, src, dst, (tile % ntx) * TT, (tile / ntx) * TT, L.data()};
       for (int t = 0; t < NTHR; ++t) ft.p0(t);
       for (int t = 0; t < NTHR; ++t) ft.p1(t, ts[t]);
       for (int t = 0; t < NTHR; ++t) ft.p2(t, ts[t]);
@@ -42,6 +42,18 @@ struct CpuEx {
   }
 };
 }  // namespace
+
+template <class IO>
+static void run_steps(CpuEx &ex, const Consts &K, const Work &w, IO st[2], int &cur, bool fused,
+                      long long nsteps) {
+  for (long long n = 0; n < nsteps; ++n) {
+    if (fused && K.unit)
+      seq_fused_step<CpuEx, IO, double, true>(ex, K, w, st[cur], st[1 - cur]);
+    else if (fused)
+      seq_fused_step<CpuEx, IO, double, false>(ex, K, w, st[cur], st[1 - cur]);
+    cur = 1 - cur;
+  }
+}
 
 extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double *ux0,
                        const double *uy0, const double *p0, long long nsteps, double *pops,
@@ -53,7 +65,9 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
   build_axis(ay, P->ny, P->bc_y, P->y_faces);
   Consts K = make_consts(P, ax, ay);
   const bool fused = P->kernel == DUGKS2P_KERNEL_FUSED;
-  Layout L = make_layout(K, ax, ay, DUGKS2P_FP64, true);
+  const bool f32 = P->precision == DUGKS2P_FP32_STATE;
+  if (f32 && !fused) return -2;
+  Layout L = make_layout(K, ax, ay, P->precision, true);
   std::vector<unsigned char> mem(L.total + 256, 0);
   unsigned char *base = (unsigned char *)(((uintptr_t)mem.data() + 255) & ~(uintptr_t)255);
   std::vector<unsigned char> tb;
@@ -64,30 +78,44 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
   K.ax[0] = bind_axis(ax, base + L.tables[0]);
   K.ax[1] = bind_axis(ay, base + L.tables[1]);
   Work w = bind_work(L, K, base);
-  double *st[2] = {(double *)(base + L.state[0]), (double *)(base + L.state[1])};
   CpuEx ex;
-  seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
   int cur = 0;
-  for (long long n = 0; n < nsteps; ++n) {
-    if (fused && K.unit)
-      seq_fused_step<CpuEx, double, double, true>(ex, K, w, st[cur], st[1 - cur]);
-    else if (fused)
-      seq_fused_step<CpuEx, double, double, false>(ex, K, w, st[cur], st[1 - cur]);
-    else
-      seq_staged_step(ex, K, w, st[cur], st[1 - cur]);
-    cur = 1 - cur;
-  }
-  for (int q = 0; q < 18; ++q)
+  double v[18];
+  if (!f32) {
+    IoF64 st[2] = {io_f64(base + L.state[0], K), io_f64(base + L.state[1], K)};
+    seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
+    if (fused) {
+      run_steps(ex, K, w, st, cur, true, nsteps);
+    } else {
+      for (long long n = 0; n < nsteps; ++n) {
+        seq_staged_step(ex, K, w, (const double *)st[cur].p, st[1 - cur].p);
+        cur = 1 - cur;
+      }
+    }
     for (int j = 0; j < K.ny; ++j)
-      for (int i = 0; i < K.nx; ++i)
-        pops[((size_t)q * K.ny + j) * K.nx + i] = st[cur][q * K.plane + (i64)j * K.ld + i];
+      for (int i = 0; i < K.nx; ++i) {
+        st[cur].load((i64)j * K.ld + i, v);
+        for (int q = 0; q < 18; ++q) pops[((size_t)q * K.ny + j) * K.nx + i] = v[q];
+      }
+    if (macros) seq_moments(ex, K, w, st[cur]);
+  } else {
+    IoE32 st[2] = {io_e32(base + L.state[0], K, L), io_e32(base + L.state[1], K, L)};
+    seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
+    run_steps(ex, K, w, st, cur, true, nsteps);
+    for (int j = 0; j < K.ny; ++j)
+      for (int i = 0; i < K.nx; ++i) {
+        st[cur].load((i64)j * K.ld + i, v);
+        for (int q = 0; q < 18; ++q) pops[((size_t)q * K.ny + j) * K.nx + i] = v[q];
+      }
+    if (macros) seq_moments(ex, K, w, st[cur]);
+  }
   if (macros) {
-    seq_macros(ex, K, w, st[cur]);
-    const double *src[5] = {w.phi, w.rho, w.ux, w.uy, w.p};
-    for (int f = 0; f < 5; ++f)
-      for (int j = 0; j < K.ny; ++j)
-        for (int i = 0; i < K.nx; ++i)
-          macros[((size_t)f * K.ny + j) * K.nx + i] = src[f][(i64)j * K.ld + i];
+    for (int j = 0; j < K.ny; ++j)
+      for (int i = 0; i < K.nx; ++i) {
+        const i64 c = (i64)j * K.ld + i;
+        const double vals[5] = {w.phi[c], rho_of<double>(K, w.phi[c]), w.ux[c], w.uy[c], w.p[c]};
+        for (int f = 0; f < 5; ++f) macros[((size_t)f * K.ny + j) * K.nx + i] = vals[f];
+      }
   }
   return 0;
 }

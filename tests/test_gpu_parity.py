@@ -146,20 +146,41 @@ def test_fused_equals_staged_bitwise_rt(D):
 FP32_TOL = 1e-4
 
 
-@pytest.mark.parametrize("kernel", ["staged", "fused"])
-def test_fp32_state_within_tolerance(D, oracle_mod, kernel):
+def test_fp32_state_within_tolerance(D, oracle_mod):
     """FP32-state step against the FP64 oracle: phi and u within 1e-4
     (relative max-norm)."""
     case = W.rt_case(64, ny=256)
     steps = 500
-    k = D.KERNEL_STAGED if kernel == "staged" else D.KERNEL_FUSED
-    sim = D.Simulation.from_case(case, precision=D.FP32_STATE, kernel=k)
+    sim = D.Simulation.from_case(case, precision=D.FP32_STATE)
+    assert sim.kernel_kind == D.KERNEL_FUSED
     sim.step(steps)
     mom = {k2: v.cpu().numpy() for k2, v in sim.moments().items()}
     o = oracle_mod.Oracle.from_case(case)
     o.step(steps)
     m = o.moments()
     errs = {f: relmax(mom[f], m[f]) for f in ("phi", "ux", "uy")}
-    print("fp32", kernel, {f: "%.2e" % e for f, e in errs.items()}, flush=True)
+    print("fp32-state", {f: "%.2e" % e for f, e in errs.items()}, flush=True)
     for f, e in errs.items():
         assert e <= FP32_TOL, (f, e)
+
+
+def test_fp32_state_staged_is_rejected(D):
+    case = W.drop_case(n=16, radius=4.0)
+    with pytest.raises(D.DugksError) as e:
+        D.Simulation.from_case(case, precision=D.FP32_STATE, kernel=D.KERNEL_STAGED)
+    assert e.value.code == D.EINVAL
+
+
+def test_fp32_state_checkpoint_and_populations(D):
+    case = W.drop_case(n=32, radius=8.0)
+    a = D.Simulation.from_case(case, precision=D.FP32_STATE)
+    a.step(30)
+    ref = a.populations().cpu().numpy()
+    b = D.Simulation.from_case(case, precision=D.FP32_STATE)
+    b.step(10)
+    snap = b.get_state().clone()
+    b.step(3)
+    b.set_state(snap)
+    b.step(20)
+    assert np.array_equal(b.populations().cpu().numpy(), ref)
+    assert b.monitors()[4] == 0

@@ -99,3 +99,18 @@ def test_general_lattice_speed_kernel_logic(oracle_mod):
     for kernel in (1, 2):
         pops, _ = _emu.run(case, 8, kernel=kernel)
         assert np.array_equal(pops, o.pops()), kernel
+
+
+def test_fp32_state_kernel_logic_within_tolerance(oracle_mod):
+    """FP32 state (f~ as floats, phi as FP64, g~ as float deviations) keeps
+    phi and u within 1e-4 of the FP64 oracle."""
+    for case, steps in [(W.rt_case(32, ny=128, amp_frac=0.2), 300),
+                        (W.drop_case(n=32, radius=8.0), 400)]:
+        case.params["precision"] = 1
+        pops, mac = _emu.run(case, steps, kernel=2)
+        o = oracle_mod.Oracle.from_case(case)
+        o.step(steps)
+        m = o.moments()
+        for k, f in ((0, "phi"), (2, "ux"), (3, "uy")):
+            err = np.abs(mac[k] - m[f]).max() / np.abs(m[f]).max()
+            assert err < 1e-4, (case.name, f, err)
