@@ -56,6 +56,52 @@ def cpu_baseline(case, seconds=10.0):
                 n, case.name, case.nx, case.ny)}
 
 
+def batched_vs_plain(steps, precision):
+    """48 rising bubbles of uneven size: one batched handle (graph replays)
+    against a loop of single handles, in both loop orders."""
+    import torch
+    from paper_1802_02868_amd import dugks2p as D
+    from paper_1802_02868_amd import workloads as W
+    cases = W.bubble_batch(48)
+    cells = sum(c.nx * c.ny for c in cases)
+    b = D.BatchSimulation(cases, precision=precision)
+    b.step(8)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / 1e3
+    mon = [b.monitors(i, raise_nonfinite=False)[4] for i in range(len(cases))]
+    b.close()
+    sims = [D.Simulation.from_case(c, precision=precision, kernel=D.KERNEL_FUSED) for c in cases]
+    for s_ in sims:
+        s_.step(1)
+    torch.cuda.synchronize()
+    best = None
+    for order in ("step-outer", "instance-outer"):
+        e0.record(sims[0].stream)
+        if order == "step-outer":
+            for _ in range(steps):
+                for s_ in sims:
+                    s_.step(1)
+        else:
+            for s_ in sims:
+                s_.step(steps)
+        e1.record(sims[0].stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        if best is None or t < best[1]:
+            best = (order, t)
+    return {"instances": len(cases), "cells": cells, "steps": steps,
+            "batched_mlups": round(cells * steps / t_batch / 1e6, 1),
+            "plain_loop_mlups": round(cells * steps / best[1] / 1e6, 1),
+            "plain_loop_order": best[0], "speedup": round(best[1] / t_batch, 3),
+            "nonfinite_instances": int(sum(1 for m in mon if m > 0)),
+            "precision": "fp64" if precision == D.FP64 else "fp32-state"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +111,8 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
     ap.add_argument("--kernel", choices=("auto", "staged", "fused"), default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (counter calibration)")
@@ -140,6 +188,8 @@ def main():
         "wall_s": round(wall, 3),
         "monitor_nonfinite": int(mon[4]),
     }
+    if not args.no_batched:
+        out["batched"] = batched_vs_plain(args.batched_steps, D.FP32_STATE)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

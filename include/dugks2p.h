@@ -155,6 +155,30 @@ int dugks2p_destroy(dugks2p *h);
 
 const char *dugks2p_last_error(void);
 
+/* ---- Batched form ------------------------------------------------------
+ * n independent simulations of arbitrary, uneven sizes advanced together:
+ * each time step is three launches over the concatenated work of all
+ * instances (a flattened list of (instance, cell block) and (instance,
+ * 14x14 tile) entries), and runs of steps are captured once into HIP graphs
+ * and replayed.  Each instance evolves exactly as a single handle with the
+ * same parameters would (bit for bit).  All instances must share the
+ * precision and use CENTRAL reconstruction (the fused kernel).
+ *   params[n]: per-instance parameters (workspace fields ignored);
+ *   phi0[n], ux0[n], uy0[n], p0[n]: device FP64 initial fields, each
+ *   [ny_i][nx_i] for instance i.  The batch owns one device allocation. */
+typedef struct dugks2p_batch dugks2p_batch;
+int dugks2p_batch_create(int32_t n, const dugks2p_params *params, const double *const *phi0,
+                         const double *const *ux0, const double *const *uy0,
+                         const double *const *p0, void *hip_stream, dugks2p_batch **out);
+int dugks2p_batch_step(dugks2p_batch *b, int64_t nsteps);
+/* Per-instance access, same contracts as the single-handle calls. */
+int dugks2p_batch_moments(dugks2p_batch *b, int32_t i, double *phi, double *rho, double *ux,
+                          double *uy, double *p);
+int dugks2p_batch_monitors(dugks2p_batch *b, int32_t i, double out[6]);
+int dugks2p_batch_get_populations(dugks2p_batch *b, int32_t i, double *dst);
+int64_t dugks2p_batch_cells(const dugks2p_batch *b);
+int dugks2p_batch_destroy(dugks2p_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -416,3 +416,4 @@ int dugks2p_destroy(dugks2p *h) {
 const char *dugks2p_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+#include "dugks2p_batch.inc"

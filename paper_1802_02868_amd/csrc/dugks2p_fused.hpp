@@ -26,59 +26,64 @@ DFN int xslot(int i) { return i == 1 ? 0 : (i == 3 ? 1 : (i >= 5 ? i - 3 : -1));
 DFN int yslot(int i) { return i == 2 ? 0 : (i == 4 ? 1 : (i >= 5 ? i - 3 : -1)); }
 
 // phi, s0 = sum f~, jx, jy = sum xi f~ (the sums of eq. phi and eq. u, P).
+template <class IO, bool U>
+DFN void phi_sums_at(const Consts &K, const Work &w, const IO &st, int i, int j) {
+  const i64 c = (i64)j * K.ld + i;
+  w.phi[c] = st.phi(c);
+  double f[9];
+  st.load_f(c, f);
+  double s0 = 0.0, jx, jy;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) s0 += f[q];
+  xi_sums<double, U>(K, f, jx, jy);
+  w.s0[c] = s0;
+  w.jx[c] = jx;
+  w.jy[c] = jy;
+}
+
 template <class IO, bool U = false>
 struct FPhiSums {
   Consts K;
   Work w;
   IO st;
-  DFN void operator()(int i, int j) const {
-    const i64 c = (i64)j * K.ld + i;
-    w.phi[c] = st.phi(c);
-    double f[9];
-    st.load_f(c, f);
-    double s0 = 0.0, jx, jy;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) s0 += f[q];
-    xi_sums<double, U>(K, f, jx, jy);
-    w.s0[c] = s0;
-    w.jx[c] = jx;
-    w.jy[c] = jy;
-  }
+  DFN void operator()(int i, int j) const { phi_sums_at<IO, U>(K, w, st, i, j); }
 };
 
 // mu, grad mu, D, F, eq. u and eq. P at a cell.
+DFN void macros_at(const Consts &K, const Work &w, int i, int j) {
+  const i64 c = (i64)j * K.ld + i;
+  const Axis &X = K.ax[0], &Y = K.ax[1];
+  const double mc = mu_at(K, w.phi, i, j);
+  const double mxl = mu_at(K, w.phi, X.lo[i], j), mxh = mu_at(K, w.phi, X.hi[i], j);
+  const double myl = mu_at(K, w.phi, i, Y.lo[j]), myh = mu_at(K, w.phi, i, Y.hi[j]);
+  const double *a1 = X.d1 + 3 * i, *a2 = X.d2 + 3 * i, *b1 = Y.d1 + 3 * j, *b2 = Y.d2 + 3 * j;
+  const double dmux = a1[0] * mxl + a1[1] * mc + a1[2] * mxh;
+  const double dmuy = b1[0] * myl + b1[1] * mc + b1[2] * myh;
+  const double lapmu =
+      (a2[0] * mxl + a2[1] * mc + a2[2] * mxh) + (b2[0] * myl + b2[1] * mc + b2[2] * myh);
+  const double D = K.mobility * lapmu;
+  const double ph = w.phi[c];
+  const double rh = rho_of<double>(K, ph);
+  const double Fx = -ph * dmux + (rh - K.rho_ref) * K.gx;
+  const double Fy = -ph * dmuy + (rh - K.rho_ref) * K.gy;
+  const double icr = 1.0 / (K.cs2 * rh);
+  const double ux = (w.jx[c] + K.hdtcs2 * Fx) * icr;
+  const double uy = (w.jy[c] + K.hdtcs2 * Fy) * icr;
+  const double grx = K.drho * stx(K, X.d1, w.phi, i, j);
+  const double gry = K.drho * sty(K, Y.d1, w.phi, i, j);
+  w.mu[c] = mc;
+  w.D[c] = D;
+  w.Fx[c] = Fx;
+  w.Fy[c] = Fy;
+  w.ux[c] = ux;
+  w.uy[c] = uy;
+  w.p[c] = w.s0[c] + K.hdtcs2 * (ux * grx + uy * gry - K.gam * rh * D);
+}
+
 struct FMacF {
   Consts K;
   Work w;
-  DFN void operator()(int i, int j) const {
-    const i64 c = (i64)j * K.ld + i;
-    const Axis &X = K.ax[0], &Y = K.ax[1];
-    const double mc = mu_at(K, w.phi, i, j);
-    const double mxl = mu_at(K, w.phi, X.lo[i], j), mxh = mu_at(K, w.phi, X.hi[i], j);
-    const double myl = mu_at(K, w.phi, i, Y.lo[j]), myh = mu_at(K, w.phi, i, Y.hi[j]);
-    const double *a1 = X.d1 + 3 * i, *a2 = X.d2 + 3 * i, *b1 = Y.d1 + 3 * j, *b2 = Y.d2 + 3 * j;
-    const double dmux = a1[0] * mxl + a1[1] * mc + a1[2] * mxh;
-    const double dmuy = b1[0] * myl + b1[1] * mc + b1[2] * myh;
-    const double lapmu = (a2[0] * mxl + a2[1] * mc + a2[2] * mxh) +
-                         (b2[0] * myl + b2[1] * mc + b2[2] * myh);
-    const double D = K.mobility * lapmu;
-    const double ph = w.phi[c];
-    const double rh = rho_of<double>(K, ph);
-    const double Fx = -ph * dmux + (rh - K.rho_ref) * K.gx;
-    const double Fy = -ph * dmuy + (rh - K.rho_ref) * K.gy;
-    const double icr = 1.0 / (K.cs2 * rh);
-    const double ux = (w.jx[c] + K.hdtcs2 * Fx) * icr;
-    const double uy = (w.jy[c] + K.hdtcs2 * Fy) * icr;
-    const double grx = K.drho * stx(K, X.d1, w.phi, i, j);
-    const double gry = K.drho * sty(K, Y.d1, w.phi, i, j);
-    w.mu[c] = mc;
-    w.D[c] = D;
-    w.Fx[c] = Fx;
-    w.Fy[c] = Fy;
-    w.ux[c] = ux;
-    w.uy[c] = uy;
-    w.p[c] = w.s0[c] + K.hdtcs2 * (ux * grx + uy * gry - K.gam * rh * D);
-  }
+  DFN void operator()(int i, int j) const { macros_at(K, w, i, j); }
 };
 
 // LDS of one tile.  A (bar+ on the tile and its ring) is dead once the faces

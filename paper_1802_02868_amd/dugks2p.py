@@ -64,6 +64,21 @@ def _load():
     L.dugks2p_destroy.argtypes = [vp]
     L.dugks2p_last_error.restype = ctypes.c_char_p
     L.dugks2p_last_error.argtypes = []
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    L.dugks2p_batch_create.restype = ctypes.c_int
+    L.dugks2p_batch_create.argtypes = [ctypes.c_int32, P(Params), PP, PP, PP, PP, vp, P(vp)]
+    L.dugks2p_batch_step.restype = ctypes.c_int
+    L.dugks2p_batch_step.argtypes = [vp, ctypes.c_int64]
+    L.dugks2p_batch_moments.restype = ctypes.c_int
+    L.dugks2p_batch_moments.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp]
+    L.dugks2p_batch_monitors.restype = ctypes.c_int
+    L.dugks2p_batch_monitors.argtypes = [vp, ctypes.c_int32, P(d)]
+    L.dugks2p_batch_get_populations.restype = ctypes.c_int
+    L.dugks2p_batch_get_populations.argtypes = [vp, ctypes.c_int32, vp]
+    L.dugks2p_batch_cells.restype = ctypes.c_int64
+    L.dugks2p_batch_cells.argtypes = [vp]
+    L.dugks2p_batch_destroy.restype = ctypes.c_int
+    L.dugks2p_batch_destroy.argtypes = [vp]
     return L
 
 
@@ -72,7 +87,10 @@ lib = _load()
 EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2p_moments",
             "dugks2p_monitors", "dugks2p_get_populations", "dugks2p_set_populations",
             "dugks2p_state_bytes", "dugks2p_get_state", "dugks2p_set_state", "dugks2p_dt",
-            "dugks2p_step_count", "dugks2p_kernel", "dugks2p_destroy", "dugks2p_last_error")
+            "dugks2p_step_count", "dugks2p_kernel", "dugks2p_destroy", "dugks2p_last_error",
+            "dugks2p_batch_create", "dugks2p_batch_step", "dugks2p_batch_moments",
+            "dugks2p_batch_monitors", "dugks2p_batch_get_populations", "dugks2p_batch_cells",
+            "dugks2p_batch_destroy")
 
 
 def _check(rc):
@@ -203,3 +221,68 @@ class Simulation:
     def set_state(self, buf):
         _check(lib.dugks2p_set_state(self._h, buf.data_ptr()))
         self.stream.synchronize()
+
+
+class BatchSimulation:
+    """Independent simulations of uneven sizes advanced together (batched
+    launches replayed from HIP graphs).  `cases`: objects with params,
+    x_faces, y_faces, phi0, ux0, uy0, p0 (see workloads.Case)."""
+
+    def __init__(self, cases, precision=FP64, stream=None):
+        import torch
+        self.torch = torch
+        self.cases = list(cases)
+        self.n = len(self.cases)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (Params * self.n)()
+        self._keep = []
+        for i, c in enumerate(self.cases):
+            P = make_params(c.params, c.x_faces, c.y_faces, precision, KERNEL_FUSED)
+            self._keep.append(P._keep)
+            arr[i] = P
+        fields = []
+        ptrs = [(ctypes.c_void_p * self.n)() for _ in range(4)]
+        for i, c in enumerate(self.cases):
+            for k, a in enumerate((c.phi0, c.ux0, c.uy0, c.p0)):
+                t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
+                fields.append(t)
+                ptrs[k][i] = t.data_ptr()
+        h = ctypes.c_void_p()
+        _check(lib.dugks2p_batch_create(self.n, arr, *ptrs, ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(h)))
+        self._h = h
+        self.stream.synchronize()
+        del fields
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.dugks2p_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def cells(self):
+        return int(lib.dugks2p_batch_cells(self._h))
+
+    def step(self, n=1):
+        _check(lib.dugks2p_batch_step(self._h, int(n)))
+
+    def populations(self, i):
+        c = self.cases[i]
+        t = self.torch
+        out = t.empty((18, c.ny, c.nx), dtype=t.float64, device=self.device)
+        _check(lib.dugks2p_batch_get_populations(self._h, int(i), out.data_ptr()))
+        return out
+
+    def monitors(self, i, raise_nonfinite=True):
+        out = (ctypes.c_double * 6)()
+        rc = lib.dugks2p_batch_monitors(self._h, int(i), out)
+        if rc != OK and (raise_nonfinite or rc != ENONFINITE):
+            _check(rc)
+        return np.array(out[:])

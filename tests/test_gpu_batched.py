@@ -1,0 +1,48 @@
+"""Batched form on an MI355X: every instance of a batch evolves bit for bit
+as a single handle with the same parameters (including step counts that are
+not a multiple of the graph length)."""
+import numpy as np
+import pytest
+
+from paper_1802_02868_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_02868_amd import dugks2p
+    return dugks2p
+
+
+def _cases():
+    return [W.bubble_case(32, 64, eo=20.0, mo=1e-3), W.drop_case(n=40, radius=10.0),
+            W.rt_case(30, ny=70, amp_frac=0.2), W.bubble_case(48, 80, eo=60.0, mo=1e-4),
+            W.poiseuille_case(nx=4, ny=32)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_instances_bitwise_equal_single(D, prec):
+    p = D.FP64 if prec == "fp64" else D.FP32_STATE
+    cases = _cases()
+    b = D.BatchSimulation(cases, precision=p)
+    assert b.cells == sum(c.nx * c.ny for c in cases)
+    b.step(13)   # one 8-step graph + 5 single steps
+    b.step(19)   # graphs from the other buffer parity
+    for i, c in enumerate(cases):
+        print("batch", prec, i, c.name, flush=True)
+        s = D.Simulation.from_case(c, precision=p, kernel=D.KERNEL_FUSED)
+        s.step(32)
+        assert np.array_equal(b.populations(i).cpu().numpy(), s.populations().cpu().numpy()), i
+        assert b.monitors(i)[5] == 32
+
+
+def test_batch_rejects_mixed_precision(D):
+    c = W.drop_case(n=16, radius=4.0)
+    c2 = W.drop_case(n=16, radius=4.0)
+    c2.params = dict(c2.params, precision=1)
+    with pytest.raises(D.DugksError):
+        D.BatchSimulation([c, c2])
