@@ -102,6 +102,52 @@ def batched_vs_plain(steps, precision):
             "precision": "fp64" if precision == D.FP64 else "fp32-state"}
 
 
+def adjoint_cost(case, steps, every):
+    """Forward rollout (fused FP64 steps, populations kept every `every`
+    steps) against the reverse sweep (library adjoint: per segment the
+    staged recomputation into the tape, then the reverse stages), for
+    J = <lam, final populations>."""
+    import torch
+    from paper_1802_02868_amd import dugks2p as D
+    s = torch.cuda.current_stream()
+    sim = D.Simulation.from_case(case, precision=D.FP64, kernel=D.KERNEL_FUSED)
+    adj = D.Adjoint(case.params, case.x_faces, case.y_faces, max_segment=every)
+    lam0 = torch.randn((18, case.ny, case.nx), dtype=torch.float64, device="cuda",
+                       generator=torch.Generator(device="cuda").manual_seed(5))
+    pg = torch.zeros(3, dtype=torch.float64, device="cuda")
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    sim.step(2)
+    torch.cuda.synchronize()
+    e[0].record(s)
+    ck = []
+    done = 0
+    while done < steps:
+        ck.append(sim.populations())
+        n = min(every, steps - done)
+        sim.step(n)
+        done += n
+    e[1].record(s)
+    lam = lam0
+    for k in range(len(ck) - 1, -1, -1):
+        lam = adj.segment(ck[k], min(every, steps - k * every), lam, pg)
+    e[2].record(s)
+    torch.cuda.synchronize()
+    t_fwd = e[0].elapsed_time(e[1]) / 1e3
+    t_bwd = e[1].elapsed_time(e[2]) / 1e3
+    cells = case.nx * case.ny
+    finite = bool(torch.isfinite(lam).all()) and bool(torch.isfinite(pg).all())
+    adj.close()
+    sim.close()
+    return {"workload": "%s (%dx%d), %d steps, checkpoints every %d" % (
+                case.name, case.nx, case.ny, steps, every),
+            "forward_ms_per_step": round(t_fwd / steps * 1e3, 4),
+            "backward_ms_per_step": round(t_bwd / steps * 1e3, 4),
+            "backward_over_forward": round(t_bwd / t_fwd, 3),
+            "forward_mlups": round(cells * steps / t_fwd / 1e6, 1),
+            "adjoint_mlups": round(cells * steps / t_bwd / 1e6, 1),
+            "finite": finite}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +159,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (counter calibration)")
@@ -190,6 +238,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_vs_plain(args.batched_steps, D.FP32_STATE)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_cost(case, args.adjoint_steps, 50)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -179,6 +179,50 @@ int dugks2p_batch_get_populations(dugks2p_batch *b, int32_t i, double *dst);
 int64_t dugks2p_batch_cells(const dugks2p_batch *b);
 int dugks2p_batch_destroy(dugks2p_batch *b);
 
+
+/* ---- Adjoint form ------------------------------------------------------
+ * Reverse-mode derivative (vector-Jacobian product) of a rollout of the
+ * FP64 scheme: Step 1 (initialisation from phi0, eq. auxf) followed by
+ * time steps (Steps 2-7 of Sec. 2.2), each step differentiated exactly as
+ * the forward computes it (CENTRAL reconstruction, phi_clamp off).  For a
+ * scalar J of the final populations, with lam = dJ/d(populations) given,
+ * the calls return dJ/d(phi0) and dJ/d(kappa, gx, gy) (kappa at fixed
+ * beta; gx, gy of the body force).  The caller keeps checkpoints of the
+ * forward populations (dugks2p_get_populations) every m <= max_segment
+ * steps and walks the segments backwards; within a segment the library
+ * recomputes the steps from the checkpoint and keeps their intermediates
+ * (a tape of 52 FP64 values per cell and step) in its workspace.
+ * Population-shaped arrays are device FP64 [18][ny][nx]; param_grad is
+ * device FP64 [3] = (kappa, gx, gy) and is accumulated into (+=).  The
+ * reductions are deterministic; results do not depend on scheduling. */
+typedef struct dugks2p_adj dugks2p_adj;
+
+/* Device bytes the adjoint needs for these parameters and segment length
+ * (0 if invalid: the adjoint needs precision FP64, CENTRAL, phi_clamp 0,
+ * 1 <= max_segment <= 100000). */
+size_t dugks2p_adjoint_workspace_bytes(const dugks2p_params *params, int32_t max_segment);
+
+/* New adjoint object (params.workspace, if given, must hold
+ * dugks2p_adjoint_workspace_bytes bytes, 256-byte aligned). */
+int dugks2p_adjoint_create(const dugks2p_params *params, int32_t max_segment, void *hip_stream,
+                           dugks2p_adj **out);
+
+/* One segment backwards: pops0 = populations at the segment start,
+ * 0 <= nsteps <= max_segment steps, lam_end = adjoint of the populations
+ * after them; writes lam_begin = adjoint of pops0 (lam_begin may equal
+ * lam_end) and adds the segment's kappa / gx / gy partials to param_grad. */
+int dugks2p_adjoint_segment(dugks2p_adj *a, const double *pops0, int32_t nsteps,
+                            const double *lam_end, double *lam_begin, double *param_grad);
+
+/* Adjoint of Step 1: lam0 = adjoint of the initial populations; phi0, ux0,
+ * uy0, p0 as given to dugks2p_create ([ny][nx]); writes phi0_grad
+ * ([ny][nx]) and adds the kappa / gx / gy partials to param_grad. */
+int dugks2p_adjoint_initial(dugks2p_adj *a, const double *phi0, const double *ux0,
+                            const double *uy0, const double *p0, const double *lam0,
+                            double *phi0_grad, double *param_grad);
+
+int dugks2p_adjoint_destroy(dugks2p_adj *a);
+
 #ifdef __cplusplus
 }
 #endif

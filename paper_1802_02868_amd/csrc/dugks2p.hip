@@ -417,3 +417,4 @@ const char *dugks2p_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
 #include "dugks2p_batch.inc"
+#include "dugks2p_adjoint.inc"

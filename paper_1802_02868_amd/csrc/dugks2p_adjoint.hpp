@@ -1,0 +1,849 @@
+// dugks2p_adjoint.hpp -- hand-written reverse mode (vector-Jacobian product)
+// of one FP64 DUGKS time step and of the initialisation, in gather form.
+//
+// Forward quantities are recomputed from the staged forward arrays of the
+// same step (phi, rho, mu, grad phi, grad mu, D, F, u, p, grad p, bar+).  The
+// reverse sweep mirrors the forward stages:
+//   face stage  -> per-face slots (adjoints sent to the two cells of a face)
+//   gather      -> per-cell sums of the slots of the cell's four faces
+//   Step 2      -> adjoint of the cell transforms (eqs. relations1/2)
+//   macros      -> adjoint of eqs. u, P and of F, D
+//   mu          -> adjoint of eq. chemicalpotential
+//   phi         -> adjoint of eq. phi, eq. oderrho and the phi stencils
+// Stencil transposes are gathers (a cell sums what its stencil readers
+// received), so no floating-point atomics are used and the result does not
+// depend on thread scheduling.  CENTRAL reconstruction, phi_clamp off.
+#pragma once
+
+#include "dugks2p_host.hpp"
+
+namespace dg {
+
+// ---------------------------------------------------------------------------
+// Pointwise adjoints.
+// ---------------------------------------------------------------------------
+
+// Adjoint of point_eq1 (eqs. feq, geq, su, Hi, F, G) for direction i:
+// accumulates into mb (same fields as Mac) and uub (d/d u^2).
+DFN void point_eq1_vjp(const Consts &K, const Mac<double> &m, double uu, int i, double feqb,
+                       double geqb, double ffb, double fgb, Mac<double> &mb, double &uub) {
+  const double cs2 = K.cs2;
+  const double wi = K.w9[i], xx = K.xi0[i], xy = K.xi1[i];
+  const double eu = xx * m.ux + xy * m.uy;
+  const double si = wi * (eu * K.k1 + eu * eu * K.k2 - uu * K.k3);
+  const double G = wi + si;
+  const double cx = xx - m.ux, cy = xy - m.uy;
+  const double A1 = m.Fx * G + si * cs2 * m.grx, A2 = m.Fy * G + si * cs2 * m.gry;
+  const double Q = cx * (m.Fx - m.gpx) + cy * (m.Fy - m.gpy);
+  double sib = 0.0, Gb = 0.0, cxb = 0.0, cyb = 0.0;
+  // feq = wi p + cs2 rho si
+  mb.p += wi * feqb;
+  mb.rho += cs2 * si * feqb;
+  sib += cs2 * m.rho * feqb;
+  // geq = Hi + phi si
+  mb.phi += si * geqb;
+  sib += m.phi * geqb;
+  if (i == 0) {
+    mb.phi += geqb;
+    mb.mu += -K.ch0 * geqb;
+  } else {
+    mb.mu += K.chi[i] * geqb;
+  }
+  // ff = cx A1 + cy A2 - wics2 rho gam D
+  cxb += A1 * ffb;
+  cyb += A2 * ffb;
+  const double A1b = cx * ffb, A2b = cy * ffb;
+  mb.rho += -K.wics2[i] * K.gam * m.D * ffb;
+  mb.D += -K.wics2[i] * m.rho * K.gam * ffb;
+  mb.Fx += G * A1b;
+  Gb += m.Fx * A1b;
+  sib += cs2 * m.grx * A1b;
+  mb.grx += si * cs2 * A1b;
+  mb.Fy += G * A2b;
+  Gb += m.Fy * A2b;
+  sib += cs2 * m.gry * A2b;
+  mb.gry += si * cs2 * A2b;
+  // fg = phi icr Q G
+  mb.phi += m.icr * Q * G * fgb;
+  mb.icr += m.phi * Q * G * fgb;
+  const double Qb = m.phi * m.icr * G * fgb;
+  Gb += m.phi * m.icr * Q * fgb;
+  cxb += (m.Fx - m.gpx) * Qb;
+  mb.Fx += cx * Qb;
+  mb.gpx += -cx * Qb;
+  cyb += (m.Fy - m.gpy) * Qb;
+  mb.Fy += cy * Qb;
+  mb.gpy += -cy * Qb;
+  // G = wi + si ; cx = xx - ux ; cy = xy - uy
+  sib += Gb;
+  mb.ux += -cxb;
+  mb.uy += -cyb;
+  // si = wi (eu k1 + eu^2 k2 - uu k3)
+  const double eub = wi * (K.k1 + 2.0 * eu * K.k2) * sib;
+  uub += -wi * K.k3 * sib;
+  mb.ux += xx * eub;
+  mb.uy += xy * eub;
+}
+
+DFN void mac_zero(Mac<double> &m) {
+  m.phi = m.rho = m.ux = m.uy = m.p = m.mu = m.grx = m.gry = m.D = m.Fx = m.Fy = m.gpx =
+      m.gpy = m.icr = 0.0;
+}
+
+// d tau_f / d phi and d tau_f / d rho of eqs. kineticandmobility, mixvis.
+DFN void tauf_grad(const Consts &K, double phi, double rho, double &dphi, double &drho) {
+  if (K.tau_f > 0.0) {
+    dphi = drho = 0.0;
+    return;
+  }
+  const double den = (phi - K.phi_b) * K.mu_b + (K.phi_a - phi) * K.mu_a;
+  const double mud = K.mumu / den;
+  const double tf = mud / (rho * K.cs2);
+  dphi = -mud / den * (K.mu_b - K.mu_a) / (rho * K.cs2);
+  drho = -tf / rho;
+}
+
+// Adjoint of cell_barp (Step 2): out_bar (18) -> til_bar (18), mb, tf_bar.
+DFN void cell_barp_vjp(const Consts &K, const Mac<double> &m, double tf, const double til[18],
+                       const double ob[18], double tilb[18], Mac<double> &mb, double &tfb) {
+  const double uu = m.ux * m.ux + m.uy * m.uy;
+  const double den = 1.0 / (2.0 * tf + K.dt);
+  const double fca = (2.0 * tf - K.h) * den, fcb = 3.0 * K.h * den, fcc = 3.0 * tf * K.h * den;
+  double fcab = 0.0, fcbb = 0.0, fccb = 0.0, uub = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    double feq, geq, ff, fg;
+    point_eq1<double>(K, m, uu, i, feq, geq, ff, fg);
+    tilb[i] = fca * ob[i];
+    fcab += til[i] * ob[i];
+    fcbb += feq * ob[i];
+    fccb += ff * ob[i];
+    tilb[9 + i] = K.gca * ob[9 + i];
+    point_eq1_vjp(K, m, uu, i, fcb * ob[i], K.gcb * ob[9 + i], fcc * ob[i], K.gcc * ob[9 + i],
+                  mb, uub);
+  }
+  mb.ux += 2.0 * m.ux * uub;
+  mb.uy += 2.0 * m.uy * uub;
+  const double denb = (2.0 * tf - K.h) * fcab + 3.0 * K.h * fcbb + 3.0 * tf * K.h * fccb;
+  tfb += 2.0 * den * fcab + 3.0 * K.h * den * fccb - 2.0 * den * den * denb;
+}
+
+// Adjoint of face_dist (Step 4 at a face): out_bar (18) -> bar_bar (18),
+// face-field adjoints fb and the body-force partials (gxb, gyb).
+DFN void face_dist_vjp(const Consts &K, const FaceFields<double> &fl, const double bar[18],
+                       const double ob[18], double barb[18], FaceFields<double> &fb,
+                       double &gxb, double &gyb) {
+  // forward recomputation (face_dist)
+  Mac<double> m;
+  double phib = 0.0;
+  for (int i = 0; i < 9; ++i) phib += bar[9 + i];
+  m.phi = phib;
+  m.rho = rho_of<double>(K, phib);
+  m.mu = fl.mu;
+  m.D = fl.D;
+  m.grx = K.drho * fl.gfx;
+  m.gry = K.drho * fl.gfy;
+  m.gpx = fl.gpx;
+  m.gpy = fl.gpy;
+  m.Fx = -phib * fl.gmx + (m.rho - K.rho_ref) * K.gx;
+  m.Fy = -phib * fl.gmy + (m.rho - K.rho_ref) * K.gy;
+  m.icr = 1.0 / (K.cs2 * m.rho);
+  double s0 = 0.0, jx = 0.0, jy = 0.0;
+  for (int i = 0; i < 9; ++i) s0 += bar[i];
+  for (int i = 0; i < 9; ++i) jx += K.xi0[i] * bar[i];
+  for (int i = 0; i < 9; ++i) jy += K.xi1[i] * bar[i];
+  m.ux = (jx + K.hhcs2 * m.Fx) * m.icr;
+  m.uy = (jy + K.hhcs2 * m.Fy) * m.icr;
+  m.p = s0 + K.hhcs2 * (m.ux * m.grx + m.uy * m.gry - K.gam * m.rho * m.D);
+  const double uu = m.ux * m.ux + m.uy * m.uy;
+  const double tf = tauf_of<double>(K, phib, m.rho);
+  const double den = 1.0 / (2.0 * tf + K.h);
+  const double fk1 = 2.0 * tf * den, fk2 = K.h * den, fk3 = tf * K.h * den;
+  // reverse
+  Mac<double> mb;
+  mac_zero(mb);
+  double uub = 0.0, fk1b = 0.0, fk2b = 0.0, fk3b = 0.0;
+  for (int i = 0; i < 18; ++i) barb[i] = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    double feq, geq, ff, fg;
+    point_eq1<double>(K, m, uu, i, feq, geq, ff, fg);
+    barb[i] += fk1 * ob[i];
+    fk1b += bar[i] * ob[i];
+    fk2b += feq * ob[i];
+    fk3b += ff * ob[i];
+    barb[9 + i] += K.gk1 * ob[9 + i];
+    point_eq1_vjp(K, m, uu, i, fk2 * ob[i], K.gk2 * ob[9 + i], fk3 * ob[i], K.gk3 * ob[9 + i],
+                  mb, uub);
+  }
+  // fk1 = 2 tf den, fk2 = h den, fk3 = tf h den, den = 1/(2 tf + h)
+  const double denb = 2.0 * tf * fk1b + K.h * fk2b + tf * K.h * fk3b;
+  double tfb = 2.0 * den * fk1b + K.h * den * fk3b - 2.0 * den * den * denb;
+  double phibb = 0.0, rhob = mb.rho;
+  double dtp, dtr;
+  tauf_grad(K, phib, m.rho, dtp, dtr);
+  phibb += dtp * tfb;
+  rhob += dtr * tfb;
+  mb.ux += 2.0 * m.ux * uub;
+  mb.uy += 2.0 * m.uy * uub;
+  // p = s0 + hhcs2 (ux grx + uy gry - gam rho D)
+  const double pb = mb.p;
+  double s0b = pb;
+  mb.ux += K.hhcs2 * m.grx * pb;
+  mb.grx += K.hhcs2 * m.ux * pb;
+  mb.uy += K.hhcs2 * m.gry * pb;
+  mb.gry += K.hhcs2 * m.uy * pb;
+  rhob += -K.hhcs2 * K.gam * m.D * pb;
+  mb.D += -K.hhcs2 * K.gam * m.rho * pb;
+  // ux = (jx + hhcs2 Fx) icr
+  const double jxb = m.icr * mb.ux, jyb = m.icr * mb.uy;
+  mb.Fx += K.hhcs2 * m.icr * mb.ux;
+  mb.Fy += K.hhcs2 * m.icr * mb.uy;
+  mb.icr += (jx + K.hhcs2 * m.Fx) * mb.ux + (jy + K.hhcs2 * m.Fy) * mb.uy;
+  for (int i = 0; i < 9; ++i) barb[i] += s0b + K.xi0[i] * jxb + K.xi1[i] * jyb;
+  // icr = 1/(cs2 rho)
+  rhob += -K.cs2 * m.icr * m.icr * mb.icr;
+  // F = -phib gm + (rho - rho_ref) g
+  phibb += -fl.gmx * mb.Fx - fl.gmy * mb.Fy;
+  fb.gmx += -phib * mb.Fx;
+  fb.gmy += -phib * mb.Fy;
+  rhob += K.gx * mb.Fx + K.gy * mb.Fy;
+  gxb += (m.rho - K.rho_ref) * mb.Fx;
+  gyb += (m.rho - K.rho_ref) * mb.Fy;
+  fb.gfx += K.drho * mb.grx;
+  fb.gfy += K.drho * mb.gry;
+  fb.gpx += mb.gpx;
+  fb.gpy += mb.gpy;
+  fb.mu += mb.mu;
+  fb.D += mb.D;
+  phibb += mb.phi + K.drho * rhob;
+  for (int i = 0; i < 9; ++i) barb[9 + i] += phibb;
+}
+
+// ---------------------------------------------------------------------------
+// Work arrays of the reverse sweep.
+// ---------------------------------------------------------------------------
+enum {
+  FB_MU, FB_D, FB_PHI, FB_P, FB_DMUX, FB_DMUY, FB_DPHX, FB_DPHY, FB_DPX, FB_DPY, FB_RHO, FB_FX,
+  FB_FY, FB_UX, FB_UY, FB_S0, FB_JX, FB_JY, FB_LAPMU, FB_LAPPHI, FB_KAP, FB_GX, FB_GY, NFB
+};
+// Per-face record of the face stage: adjoint of the 18 reconstructed face
+// values bar (after folding the bounce-back copies), of the 8 face fields and
+// the body-force partials of the face.
+enum {
+  FS_B = 0, FS_MU = 18, FS_D, FS_GMX, FS_GMY, FS_GFX, FS_GFY, FS_GPX, FS_GPY, FS_GX, FS_GY, NFS
+};
+
+struct AdjWork {
+  const double *lam;  // 18 planes: adjoint of the state after the step
+  double *out;        // 18 planes: adjoint of the state before the step
+  double *xs, *ys;    // face records: NFS planes of xplane / yplane
+  double *ab, *gxb, *gyb;  // per cell: bar+ adjoint and its gradient adjoints (18 planes each)
+  double *fb;         // NFB planes of per-cell field adjoints and parameter partials
+  double *pacc;       // 3 planes: per-cell sums over steps of the kappa, gx, gy partials
+};
+
+// Transpose of a three-point stencil along axis ax at cell (i, j): the sum,
+// over the cells whose stencil reads (i, j), of weight times their adjoint.
+DFN double stencil_T(const Consts &K, int ax, const double *wt3, const double *B, int i, int j) {
+  const Axis &X = K.ax[ax];
+  const int c = ax == 0 ? i : j;
+  const int cand[3] = {X.lo[c], c, X.hi[c]};
+  double acc = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    bool dup = false;
+    for (int b = 0; b < a; ++b) dup |= cand[b] == cand[a];
+    if (dup) continue;
+    const int cp = cand[a];
+    const int tgt[3] = {X.lo[cp], cp, X.hi[cp]};
+    const double *w = wt3 + 3 * cp;
+    const i64 id = ax == 0 ? (i64)j * K.ld + cp : (i64)cp * K.ld + i;
+    for (int s = 0; s < 3; ++s)
+      if (tgt[s] == c) acc += w[s] * B[id];
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse stages.
+// ---------------------------------------------------------------------------
+
+// Face stage: adjoint of the face distributions from the update (eq.
+// updatef), then of Step 4 (eq. original-function) and of the bounce-back;
+// the adjoint of bar and of the face fields go to the face record.
+template <int A>
+struct FAdjFace {
+  Consts K;
+  Work w;
+  AdjWork a;
+  DFN void operator()(int p0, int p1) const {
+    const int k = A == 0 ? p0 : p1, t = A == 0 ? p1 : p0;
+    const Axis &ax = K.ax[A];
+    const int cl = ax.fl[k], cr = ax.fr[k];
+    const GAcc acc{&K, &w};
+    const int TA = 1 - A;
+    const i64 fid = A == 0 ? (i64)t * K.nfx + k : (i64)k * K.ld + t;
+    const i64 fpl = A == 0 ? K.xplane : K.yplane;
+    double *rec = (A == 0 ? a.xs : a.ys) + fid;
+#define CX(ia) (A == 0 ? (ia) : t)
+#define CY(ia) (A == 0 ? t : (ia))
+    // the face value enters the update of cell L with -r_L xi_n and of
+    // cell R with +r_R xi_n
+    double ob[18];
+    for (int q = 0; q < 18; ++q) {
+      const int i = q % 9;
+      const double xn = A == 0 ? K.xi0[i] : K.xi1[i];
+      double v = 0.0;
+      if (cl >= 0) v += -(ax.rdt[cl] * xn) * a.lam[q * K.plane + (i64)CY(cl) * K.ld + CX(cl)];
+      if (cr >= 0) v += (ax.rdt[cr] * xn) * a.lam[q * K.plane + (i64)CY(cr) * K.ld + CX(cr)];
+      ob[q] = v;
+    }
+    const double h = K.h;
+    double bar[18], barb[18];
+    FaceFields<double> fl, fb;
+    fb.mu = fb.D = fb.gmx = fb.gmy = fb.gfx = fb.gfy = fb.gpx = fb.gpy = 0.0;
+    double gxb = 0.0, gyb = 0.0;
+    if (cl < 0 || cr < 0) {
+      const int cc = cl < 0 ? cr : cl;
+      const double off = cl < 0 ? ax.foffr[k] : ax.foffl[k];
+      const int nout = cl < 0 ? -1 : 1;
+      const GAcc::H HC = acc.cell(CX(cc), CY(cc));
+      for (int q = 0; q < 18; ++q) {
+        const int i = q % 9;
+        const int en = A == 0 ? ex_of(i) : ey_of(i);
+        if (en * nout < 0) continue;
+        const double Gn = acc.pgrad(A, q, HC), Gt = acc.pgrad(TA, q, HC);
+        const double val = acc.A(q, HC) + off * Gn;
+        const double sgx = A == 0 ? Gn : Gt, sgy = A == 0 ? Gt : Gn;
+        bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
+      }
+      for (int q = 0; q < 18; ++q) {
+        const int i = q % 9;
+        const int en = A == 0 ? ex_of(i) : ey_of(i);
+        if (en * nout < 0) bar[q] = bar[q - i + opp_of(i)];
+      }
+      fl.mu = acc.mu(HC);
+      fl.D = acc.D(HC);
+      const double tmu = acc.dmu(TA, HC), tph = acc.dphi(TA, HC), tp = acc.dp(TA, HC);
+      fl.gmx = A == 0 ? 0.0 : tmu;
+      fl.gmy = A == 0 ? tmu : 0.0;
+      fl.gfx = A == 0 ? 0.0 : tph;
+      fl.gfy = A == 0 ? tph : 0.0;
+      fl.gpx = A == 0 ? 0.0 : tp;
+      fl.gpy = A == 0 ? tp : 0.0;
+      // reverse of: copy of the outgoing face values onto the entering ones
+      for (int q = 0; q < 18; ++q) {
+        const int i = q % 9;
+        const int en = A == 0 ? ex_of(i) : ey_of(i);
+        if (en * nout < 0) {
+          ob[q - i + opp_of(i)] += ob[q];
+          ob[q] = 0.0;
+        }
+      }
+      face_dist_vjp(K, fl, bar, ob, barb, fb, gxb, gyb);
+      for (int q = 0; q < 18; ++q) {
+        const int i = q % 9;
+        const int en = A == 0 ? ex_of(i) : ey_of(i);
+        if (en * nout < 0) {
+          barb[q - i + opp_of(i)] += barb[q];
+          barb[q] = 0.0;
+        }
+      }
+    } else {
+      const GAcc::H HL = acc.cell(CX(cl), CY(cl)), HR = acc.cell(CX(cr), CY(cr));
+      const FaceW fw{ax.fwl[k], ax.fwr[k], ax.finv[k]};
+      for (int q = 0; q < 18; ++q) {
+        const int i = q % 9;
+        const double AL = acc.A(q, HL), AR = acc.A(q, HR);
+        const double val = fw.wl * AL + fw.wr * AR;
+        const double sn = (AR - AL) * fw.inv;
+        const double st = fw.wl * acc.pgrad(TA, q, HL) + fw.wr * acc.pgrad(TA, q, HR);
+        const double sgx = A == 0 ? sn : st, sgy = A == 0 ? st : sn;
+        bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
+      }
+      double v, tmp, gn, gt;
+      face_field(fw, acc.mu(HL), acc.mu(HR), acc.dmu(TA, HL), acc.dmu(TA, HR), v, gn, gt);
+      fl.mu = v;
+      fl.gmx = A == 0 ? gn : gt;
+      fl.gmy = A == 0 ? gt : gn;
+      face_field(fw, acc.D(HL), acc.D(HR), 0.0, 0.0, v, tmp, tmp);
+      fl.D = v;
+      face_field(fw, acc.phi(HL), acc.phi(HR), acc.dphi(TA, HL), acc.dphi(TA, HR), tmp, gn, gt);
+      fl.gfx = A == 0 ? gn : gt;
+      fl.gfy = A == 0 ? gt : gn;
+      face_field(fw, acc.p(HL), acc.p(HR), acc.dp(TA, HL), acc.dp(TA, HR), tmp, gn, gt);
+      fl.gpx = A == 0 ? gn : gt;
+      fl.gpy = A == 0 ? gt : gn;
+      face_dist_vjp(K, fl, bar, ob, barb, fb, gxb, gyb);
+    }
+    for (int q = 0; q < 18; ++q) rec[(FS_B + q) * fpl] = barb[q];
+    rec[FS_MU * fpl] = fb.mu;
+    rec[FS_D * fpl] = fb.D;
+    rec[FS_GMX * fpl] = fb.gmx;
+    rec[FS_GMY * fpl] = fb.gmy;
+    rec[FS_GFX * fpl] = fb.gfx;
+    rec[FS_GFY * fpl] = fb.gfy;
+    rec[FS_GPX * fpl] = fb.gpx;
+    rec[FS_GPY * fpl] = fb.gpy;
+    rec[FS_GX * fpl] = gxb;
+    rec[FS_GY * fpl] = gyb;
+#undef CX
+#undef CY
+  }
+};
+
+// Contribution of one face record of axis A to the adjoint of the cell that
+// lies on side s (0: low side L, 1: high side R) of face k.  Reverse of the
+// face reconstruction of bar (eq. original-function with the central face
+// operator, or the one-sided wall expansion) and of the face fields.
+template <int A>
+DFN void gather_face(const Consts &K, const double *rec, i64 fpl, int k, int s, double ab[18],
+                     double gb[2][18], double fv[12]) {
+  const Axis &ax = K.ax[A];
+  const int TA = 1 - A;
+  const bool wall = ax.fl[k] < 0 || ax.fr[k] < 0;
+  const double h = K.h;
+  double wgt, sg, off;
+  if (wall) {
+    wgt = 1.0;
+    sg = 0.0;
+    off = ax.fl[k] < 0 ? ax.foffr[k] : ax.foffl[k];
+  } else {
+    wgt = s == 0 ? ax.fwl[k] : ax.fwr[k];
+    sg = (s == 0 ? -1.0 : 1.0) * ax.finv[k];
+    off = 0.0;
+  }
+  for (int q = 0; q < 18; ++q) {
+    const int i = q % 9;
+    const double bb = rec[(FS_B + q) * fpl];
+    const double xn = A == 0 ? K.xi0[i] : K.xi1[i], xt = A == 0 ? K.xi1[i] : K.xi0[i];
+    if (wall) {
+      // bar = A + off Gn - h (xn Gn + xt Gt)
+      ab[q] += bb;
+      gb[A][q] += (off - h * xn) * bb;
+      gb[TA][q] += -h * xt * bb;
+    } else {
+      // bar = wl AL + wr AR - h (xn (AR - AL) inv + xt (wl GtL + wr GtR))
+      ab[q] += wgt * bb + sg * (-h * xn * bb);
+      gb[TA][q] += wgt * (-h * xt * bb);
+    }
+  }
+  const double mub = rec[FS_MU * fpl], Db = rec[FS_D * fpl];
+  const double mun = rec[(A == 0 ? FS_GMX : FS_GMY) * fpl], mut = rec[(A == 0 ? FS_GMY : FS_GMX) * fpl];
+  const double phn = rec[(A == 0 ? FS_GFX : FS_GFY) * fpl], pht = rec[(A == 0 ? FS_GFY : FS_GFX) * fpl];
+  const double pn = rec[(A == 0 ? FS_GPX : FS_GPY) * fpl], pt = rec[(A == 0 ? FS_GPY : FS_GPX) * fpl];
+  // fv: mu, D, phi, p, dmu[2], dphi[2], dp[2]
+  fv[0] += wgt * mub + sg * mun;
+  fv[1] += wgt * Db;
+  fv[2] += sg * phn;
+  fv[3] += sg * pn;
+  fv[4 + TA] += wgt * mut;
+  fv[6 + TA] += wgt * pht;
+  fv[8 + TA] += wgt * pt;
+  // the face's body-force partials are counted once, on side L (or the fluid side)
+  if (wall || s == 0) {
+    fv[10] += rec[FS_GX * fpl];
+    fv[11] += rec[FS_GY * fpl];
+  }
+}
+
+// Gather: a cell is side R of its W and S faces and side L of its E and N
+// faces (a wall face has only the fluid side).
+struct FAdjGather {
+  Consts K;
+  AdjWork a;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i, P = K.plane;
+    const int ie = (K.ax[0].bc == 0 && i == K.nx - 1) ? 0 : i + 1;
+    const int jn = (K.ax[1].bc == 0 && j == K.ny - 1) ? 0 : j + 1;
+    double ab[18], gb[2][18], fv[12];
+    for (int q = 0; q < 18; ++q) {
+      ab[q] = (4.0 / 3.0) * a.lam[q * P + c];
+      gb[0][q] = gb[1][q] = 0.0;
+    }
+    for (int e = 0; e < 12; ++e) fv[e] = 0.0;
+    gather_face<0>(K, a.xs + (i64)j * K.nfx + i, K.xplane, i, 1, ab, gb, fv);
+    gather_face<0>(K, a.xs + (i64)j * K.nfx + ie, K.xplane, ie, 0, ab, gb, fv);
+    gather_face<1>(K, a.ys + (i64)j * K.ld + i, K.yplane, j, 1, ab, gb, fv);
+    gather_face<1>(K, a.ys + (i64)jn * K.ld + i, K.yplane, jn, 0, ab, gb, fv);
+    for (int q = 0; q < 18; ++q) {
+      a.ab[q * P + c] = ab[q];
+      a.gxb[q * P + c] = gb[0][q];
+      a.gyb[q * P + c] = gb[1][q];
+    }
+    double *fb = a.fb;
+    for (int f = 0; f < NFB; ++f) fb[f * P + c] = 0.0;
+    fb[FB_MU * P + c] = fv[0];
+    fb[FB_D * P + c] = fv[1];
+    fb[FB_PHI * P + c] = fv[2];
+    fb[FB_P * P + c] = fv[3];
+    fb[FB_DMUX * P + c] = fv[4];
+    fb[FB_DMUY * P + c] = fv[5];
+    fb[FB_DPHX * P + c] = fv[6];
+    fb[FB_DPHY * P + c] = fv[7];
+    fb[FB_DPX * P + c] = fv[8];
+    fb[FB_DPY * P + c] = fv[9];
+    fb[FB_GX * P + c] = fv[10];
+    fb[FB_GY * P + c] = fv[11];
+  }
+};
+
+// Adjoint of the population gradients and of Step 2 at a cell.
+struct FAdjCell {
+  Consts K;
+  Work w;
+  AdjWork a;
+  const double *st;  // state before the step (FP64)
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    double ob[18], til[18], tilb[18];
+    for (int q = 0; q < 18; ++q) {
+      ob[q] = a.ab[q * K.plane + c] + stencil_T(K, 0, K.ax[0].pg, a.gxb + q * K.plane, i, j) +
+              stencil_T(K, 1, K.ax[1].pg, a.gyb + q * K.plane, i, j);
+      til[q] = st[q * K.plane + c];
+    }
+    Mac<double> m, mb;
+    cell_mac(K, w, c, m);
+    mac_zero(mb);
+    const double tf = w.tauf[c];
+    double tfb = 0.0;
+    cell_barp_vjp(K, m, tf, til, ob, tilb, mb, tfb);
+    // tilde+ = 4/3 bar+ - 1/3 tilde: the 4/3 part is in ab; here -1/3
+    for (int q = 0; q < 18; ++q) a.out[q * K.plane + c] = tilb[q] - (1.0 / 3.0) * a.lam[q * K.plane + c];
+    double dtp, dtr;
+    tauf_grad(K, m.phi, m.rho, dtp, dtr);
+    double *fb = a.fb;
+    const i64 P = K.plane;
+    fb[FB_PHI * P + c] += mb.phi + dtp * tfb;
+    fb[FB_RHO * P + c] += mb.rho + dtr * tfb - K.cs2 * m.icr * m.icr * mb.icr;
+    fb[FB_UX * P + c] += mb.ux;
+    fb[FB_UY * P + c] += mb.uy;
+    fb[FB_P * P + c] += mb.p;
+    fb[FB_MU * P + c] += mb.mu;
+    fb[FB_DPHX * P + c] += K.drho * mb.grx;
+    fb[FB_DPHY * P + c] += K.drho * mb.gry;
+    fb[FB_D * P + c] += mb.D;
+    fb[FB_FX * P + c] += mb.Fx;
+    fb[FB_FY * P + c] += mb.Fy;
+    fb[FB_DPX * P + c] += mb.gpx;
+    fb[FB_DPY * P + c] += mb.gpy;
+  }
+};
+
+// Adjoint of the cell macros (eqs. u, P; F; D): p adjoint completed by the
+// transpose of its gradient stencil.  init = 1: Step 1 form (u, p given).
+struct FAdjMacro {
+  Consts K;
+  Work w;
+  AdjWork a;
+  int init;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i, P = K.plane;
+    double *fb = a.fb;
+    const double ph = w.phi[c], rh = w.rho[c];
+    const double dmux = w.dmux[c], dmuy = w.dmuy[c], D = w.D[c];
+    double Fxb = fb[FB_FX * P + c], Fyb = fb[FB_FY * P + c], Db = fb[FB_D * P + c];
+    double rhob = 0.0, phib = 0.0;
+    if (!init) {
+      const double pb = fb[FB_P * P + c] + stencil_T(K, 0, K.ax[0].d1, fb + FB_DPX * P, i, j) +
+                        stencil_T(K, 1, K.ax[1].d1, fb + FB_DPY * P, i, j);
+      const double ux = w.ux[c], uy = w.uy[c];
+      const double grx = K.drho * w.dphx[c], gry = K.drho * w.dphy[c];
+      double uxb = fb[FB_UX * P + c] + K.hdtcs2 * grx * pb;
+      double uyb = fb[FB_UY * P + c] + K.hdtcs2 * gry * pb;
+      fb[FB_DPHX * P + c] += K.drho * K.hdtcs2 * ux * pb;
+      fb[FB_DPHY * P + c] += K.drho * K.hdtcs2 * uy * pb;
+      rhob += -K.hdtcs2 * K.gam * D * pb;
+      Db += -K.hdtcs2 * K.gam * rh * pb;
+      fb[FB_S0 * P + c] = pb;
+      const double icr = 1.0 / (K.cs2 * rh);
+      const double Fx = -ph * dmux + (rh - K.rho_ref) * K.gx;
+      const double Fy = -ph * dmuy + (rh - K.rho_ref) * K.gy;
+      // recover jx, jy from u: jx = ux / icr - hdtcs2 Fx
+      const double jx = ux * (K.cs2 * rh) - K.hdtcs2 * Fx, jy = uy * (K.cs2 * rh) - K.hdtcs2 * Fy;
+      fb[FB_JX * P + c] = icr * uxb;
+      fb[FB_JY * P + c] = icr * uyb;
+      Fxb += K.hdtcs2 * icr * uxb;
+      Fyb += K.hdtcs2 * icr * uyb;
+      const double icrb = (jx + K.hdtcs2 * Fx) * uxb + (jy + K.hdtcs2 * Fy) * uyb;
+      rhob += -K.cs2 * icr * icr * icrb;
+    } else {
+      fb[FB_S0 * P + c] = fb[FB_JX * P + c] = fb[FB_JY * P + c] = 0.0;
+    }
+    // F = -phi grad mu + (rho - rho_ref) g
+    phib += -dmux * Fxb - dmuy * Fyb;
+    fb[FB_DMUX * P + c] += -ph * Fxb;
+    fb[FB_DMUY * P + c] += -ph * Fyb;
+    rhob += K.gx * Fxb + K.gy * Fyb;
+    fb[FB_GX * P + c] += (rh - K.rho_ref) * Fxb;
+    fb[FB_GY * P + c] += (rh - K.rho_ref) * Fyb;
+    // D = lambda lap mu
+    fb[FB_LAPMU * P + c] = K.mobility * Db;
+    fb[FB_PHI * P + c] += phib;
+    fb[FB_RHO * P + c] += rhob;
+  }
+};
+
+// Adjoint of eq. chemicalpotential: mu adjoint completed by the transposes
+// of grad mu and lap mu; kappa partial.
+struct FAdjMu {
+  Consts K;
+  Work w;
+  AdjWork a;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i, P = K.plane;
+    double *fb = a.fb;
+    const double mub = fb[FB_MU * P + c] + stencil_T(K, 0, K.ax[0].d1, fb + FB_DMUX * P, i, j) +
+                       stencil_T(K, 1, K.ax[1].d1, fb + FB_DMUY * P, i, j) +
+                       stencil_T(K, 0, K.ax[0].d2, fb + FB_LAPMU * P, i, j) +
+                       stencil_T(K, 1, K.ax[1].d2, fb + FB_LAPMU * P, i, j);
+    const double ph = w.phi[c];
+    const double a1 = ph - K.phi_a, b1 = ph - K.phi_b, m1 = ph - K.phimid;
+    const double lap = stx(K, K.ax[0].d2, w.phi, i, j) + sty(K, K.ax[1].d2, w.phi, i, j);
+    fb[FB_PHI * P + c] += K.c4b * (b1 * m1 + a1 * m1 + a1 * b1) * mub;
+    fb[FB_LAPPHI * P + c] = -K.kappa * mub;
+    fb[FB_KAP * P + c] = -lap * mub;
+  }
+};
+
+// Adjoint of eq. phi and eq. oderrho with the transposes of grad phi and
+// lap phi.  Writes the adjoint of the populations (step) or of phi0 (init).
+struct FAdjPhi {
+  Consts K;
+  AdjWork a;
+  double *phi0b;  // Step 1 form: adjoint of phi0 ([ny][nx]); NULL for a step
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i, P = K.plane;
+    const double *fb = a.fb;
+    const double phb = fb[FB_PHI * P + c] + K.drho * fb[FB_RHO * P + c] +
+                       stencil_T(K, 0, K.ax[0].d1, fb + FB_DPHX * P, i, j) +
+                       stencil_T(K, 1, K.ax[1].d1, fb + FB_DPHY * P, i, j) +
+                       stencil_T(K, 0, K.ax[0].d2, fb + FB_LAPPHI * P, i, j) +
+                       stencil_T(K, 1, K.ax[1].d2, fb + FB_LAPPHI * P, i, j);
+    a.pacc[c] += fb[FB_KAP * P + c];
+    a.pacc[P + c] += fb[FB_GX * P + c];
+    a.pacc[2 * P + c] += fb[FB_GY * P + c];
+    if (phi0b) {
+      phi0b[(i64)j * K.nx + i] = phb;
+      return;
+    }
+    const double s0b = fb[FB_S0 * P + c], jxb = fb[FB_JX * P + c], jyb = fb[FB_JY * P + c];
+    for (int q = 0; q < 9; ++q)
+      a.out[q * P + c] += s0b + K.xi0[q] * jxb + K.xi1[q] * jyb;
+    for (int q = 9; q < 18; ++q) a.out[q * P + c] += phb;
+  }
+};
+
+// Step 1 adjoint at a cell: tilde = eq - (dt/2) F with u, p given.
+struct FAdjInit {
+  Consts K;
+  Work w;
+  AdjWork a;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i, P = K.plane;
+    Mac<double> m, mb;
+    cell_mac(K, w, c, m);
+    mac_zero(mb);
+    const double uu = m.ux * m.ux + m.uy * m.uy;
+    double uub = 0.0;
+    for (int q = 0; q < 9; ++q)
+      point_eq1_vjp(K, m, uu, q, a.lam[q * P + c], a.lam[(9 + q) * P + c],
+                    -K.hdt * a.lam[q * P + c], -K.hdt * a.lam[(9 + q) * P + c], mb, uub);
+    double *fb = a.fb;
+    for (int f = 0; f < NFB; ++f) fb[f * P + c] = 0.0;
+    fb[FB_PHI * P + c] = mb.phi;
+    fb[FB_RHO * P + c] = mb.rho - K.cs2 * m.icr * m.icr * mb.icr;
+    fb[FB_MU * P + c] = mb.mu;
+    fb[FB_DPHX * P + c] = K.drho * mb.grx;
+    fb[FB_DPHY * P + c] = K.drho * mb.gry;
+    fb[FB_D * P + c] = mb.D;
+    fb[FB_FX * P + c] = mb.Fx;
+    fb[FB_FY * P + c] = mb.Fy;
+  }
+};
+
+// Sequences.  The forward arrays (staged stages up to Step 2) of the step
+// must be in w; lam = adjoint after the step, out = adjoint before it.
+template <class Ex>
+void seq_adjoint_step(Ex &ex, const Consts &K, const Work &w, const AdjWork &a,
+                      const double *st) {
+  ex.grid(FAdjFace<0>{K, w, a}, K.nfx, K.ny);
+  ex.grid(FAdjFace<1>{K, w, a}, K.nx, K.nfy);
+  ex.grid(FAdjGather{K, a}, K.nx, K.ny);
+  ex.grid(FAdjCell{K, w, a, st}, K.nx, K.ny);
+  ex.grid(FAdjMacro{K, w, a, 0}, K.nx, K.ny);
+  ex.grid(FAdjMu{K, w, a}, K.nx, K.ny);
+  ex.grid(FAdjPhi{K, a, nullptr}, K.nx, K.ny);
+}
+
+// Step 1 adjoint: forward init fields must be in w; lam = adjoint of the
+// initial state; phi0b receives the adjoint of phi0.
+template <class Ex>
+void seq_adjoint_init(Ex &ex, const Consts &K, const Work &w, const AdjWork &a, double *phi0b) {
+  ex.grid(FAdjInit{K, w, a}, K.nx, K.ny);
+  ex.grid(FAdjMacro{K, w, a, 1}, K.nx, K.ny);
+  ex.grid(FAdjMu{K, w, a}, K.nx, K.ny);
+  ex.grid(FAdjPhi{K, a, phi0b}, K.nx, K.ny);
+}
+
+// ---------------------------------------------------------------------------
+// Reverse sweep over a segment of steps, with the forward tape.
+// ---------------------------------------------------------------------------
+
+// Rows without padding: every adjoint-side array has the layout
+// [plane][ny][nx] of the population export.
+inline void pack_rows(Consts &K) {
+  K.ld = K.nx;
+  K.plane = (i64)K.ny * K.nx;
+  K.yplane = (i64)K.nfy * K.nx;
+}
+
+// Per step of a segment the tape holds the 16 cell fields of the staged
+// step and bar+ (18 planes); the population state of every step but the
+// first is kept too.
+enum { TAPE_FIELDS = 16 };
+
+struct AdjLayout {
+  size_t tables[2];
+  size_t field_bytes;  // one cell plane, padded
+  size_t slot_bytes;   // one tape slot: 16 fields + bar+
+  size_t state_bytes;  // 18 planes
+  size_t states, tape, dummy, facex, facey, lam[2], xs, ys, ab, gxb, gyb, fb, pacc;
+  size_t total;
+  int mseg;
+};
+
+inline AdjLayout make_adj_layout(const Consts &K, const AxisHost &ax, const AxisHost &ay,
+                                 int mseg) {
+  AdjLayout L;
+  const size_t P = (size_t)K.plane;
+  size_t off = 0;
+  L.mseg = mseg;
+  L.tables[0] = off;
+  off += align256(axis_table_bytes(ax));
+  L.tables[1] = off;
+  off += align256(axis_table_bytes(ay));
+  L.field_bytes = align256(sizeof(double) * P);
+  L.state_bytes = align256(18 * sizeof(double) * P);
+  L.slot_bytes = TAPE_FIELDS * L.field_bytes + L.state_bytes;
+  L.states = off;
+  off += (size_t)mseg * L.state_bytes;
+  L.tape = off;
+  off += (size_t)mseg * L.slot_bytes;
+  L.dummy = off;
+  off += 3 * L.field_bytes;
+  L.facex = off;
+  off += align256(18 * sizeof(double) * (size_t)K.xplane);
+  L.facey = off;
+  off += align256(18 * sizeof(double) * (size_t)K.yplane);
+  for (int b = 0; b < 2; ++b) {
+    L.lam[b] = off;
+    off += L.state_bytes;
+  }
+  L.xs = off;
+  off += align256(NFS * sizeof(double) * (size_t)K.xplane);
+  L.ys = off;
+  off += align256(NFS * sizeof(double) * (size_t)K.yplane);
+  L.ab = off;
+  off += L.state_bytes;
+  L.gxb = off;
+  off += L.state_bytes;
+  L.gyb = off;
+  off += L.state_bytes;
+  L.fb = off;
+  off += align256(NFB * sizeof(double) * P);
+  L.pacc = off;
+  off += align256(3 * sizeof(double) * P);
+  L.total = off;
+  return L;
+}
+
+struct AdjBufs {
+  AdjLayout L;
+  unsigned char *base;
+  double *state(int n) const { return (double *)(base + L.states + (size_t)n * L.state_bytes); }
+  Work tape(int n) const {
+    unsigned char *s = base + L.tape + (size_t)n * L.slot_bytes;
+    Work w;
+    double **f[TAPE_FIELDS] = {&w.phi, &w.rho, &w.mu, &w.dphx, &w.dphy, &w.dmux, &w.dmuy, &w.D,
+                               &w.Fx,  &w.Fy,  &w.ux, &w.uy,   &w.p,    &w.dpx,  &w.dpy,  &w.tauf};
+    for (int k = 0; k < TAPE_FIELDS; ++k) *f[k] = (double *)(s + k * L.field_bytes);
+    w.barp = (double *)(s + TAPE_FIELDS * L.field_bytes);
+    w.s0 = (double *)(base + L.dummy);
+    w.jx = (double *)(base + L.dummy + L.field_bytes);
+    w.jy = (double *)(base + L.dummy + 2 * L.field_bytes);
+    w.facex = (double *)(base + L.facex);
+    w.facey = (double *)(base + L.facey);
+    return w;
+  }
+  double *lam(int b) const { return (double *)(base + L.lam[b]); }
+  AdjWork adj(int in) const {
+    AdjWork a;
+    a.lam = lam(in);
+    a.out = lam(1 - in);
+    a.xs = (double *)(base + L.xs);
+    a.ys = (double *)(base + L.ys);
+    a.ab = (double *)(base + L.ab);
+    a.gxb = (double *)(base + L.gxb);
+    a.gyb = (double *)(base + L.gyb);
+    a.fb = (double *)(base + L.fb);
+    a.pacc = (double *)(base + L.pacc);
+    return a;
+  }
+};
+
+// dst[q][c] = src[q][c] (or 0 if src is NULL) for q < nq, packed planes.
+struct FCopyPlanes {
+  Consts K;
+  const double *src;
+  double *dst;
+  int nq;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    for (int q = 0; q < nq; ++q) dst[q * K.plane + c] = src ? src[q * K.plane + c] : 0.0;
+  }
+};
+
+// Reverse sweep of one segment: recompute nsteps steps from pops0 (the
+// state at the segment start) into the tape, then carry the adjoint of the
+// state after the segment (lam_end) back to its start (lam_begin).  The
+// per-cell kappa / g partials of the segment are left in pacc.
+template <class Ex>
+void seq_adjoint_segment(Ex &ex, const Consts &K, const AdjBufs &B, const double *pops0,
+                         int nsteps, const double *lam_end, double *lam_begin) {
+  const AdjWork a0 = B.adj(0);
+  ex.grid(FCopyPlanes{K, nullptr, a0.pacc, 3}, K.nx, K.ny);
+  ex.grid(FCopyPlanes{K, lam_end, B.lam(0), 18}, K.nx, K.ny);
+  for (int n = 0; n < nsteps; ++n) {
+    const Work w = B.tape(n);
+    const double *src = n == 0 ? pops0 : B.state(n);
+    if (n + 1 < nsteps) {
+      seq_staged_step(ex, K, w, src, B.state(n + 1));
+    } else {
+      seq_staged_macros(ex, K, w, src);
+      ex.grid(FCell<double, double>{K, w, src}, K.nx, K.ny);
+    }
+  }
+  int cur = 0;
+  for (int n = nsteps - 1; n >= 0; --n) {
+    seq_adjoint_step(ex, K, B.tape(n), B.adj(cur), n == 0 ? pops0 : B.state(n));
+    cur = 1 - cur;
+  }
+  ex.grid(FCopyPlanes{K, B.lam(cur), lam_begin, 18}, K.nx, K.ny);
+}
+
+// Adjoint of Step 1: recompute the initial cell fields from phi0, u0, p0,
+// then carry lam0 (adjoint of the initial populations) to phi0_grad.
+template <class Ex>
+void seq_adjoint_initial(Ex &ex, const Consts &K, const AdjBufs &B, const double *phi0,
+                         const double *ux0, const double *uy0, const double *p0,
+                         const double *lam0, double *phi0_grad) {
+  const Work w = B.tape(0);
+  const AdjWork a = B.adj(0);
+  ex.grid(FCopyPlanes{K, nullptr, a.pacc, 3}, K.nx, K.ny);
+  ex.grid(FCopyPlanes{K, lam0, B.lam(0), 18}, K.nx, K.ny);
+  ex.grid(FInit0{K, w, phi0, ux0, uy0, p0}, K.nx, K.ny);
+  ex.grid(FMu{K, w}, K.nx, K.ny);
+  ex.grid(FInit1{K, w}, K.nx, K.ny);
+  seq_adjoint_init(ex, K, w, a, phi0_grad);
+}
+
+}  // namespace dg

@@ -79,6 +79,16 @@ def _load():
     L.dugks2p_batch_cells.argtypes = [vp]
     L.dugks2p_batch_destroy.restype = ctypes.c_int
     L.dugks2p_batch_destroy.argtypes = [vp]
+    L.dugks2p_adjoint_workspace_bytes.restype = ctypes.c_size_t
+    L.dugks2p_adjoint_workspace_bytes.argtypes = [P(Params), ctypes.c_int32]
+    L.dugks2p_adjoint_create.restype = ctypes.c_int
+    L.dugks2p_adjoint_create.argtypes = [P(Params), ctypes.c_int32, vp, P(vp)]
+    L.dugks2p_adjoint_segment.restype = ctypes.c_int
+    L.dugks2p_adjoint_segment.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
+    L.dugks2p_adjoint_initial.restype = ctypes.c_int
+    L.dugks2p_adjoint_initial.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.dugks2p_adjoint_destroy.restype = ctypes.c_int
+    L.dugks2p_adjoint_destroy.argtypes = [vp]
     return L
 
 
@@ -90,7 +100,8 @@ EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2
             "dugks2p_step_count", "dugks2p_kernel", "dugks2p_destroy", "dugks2p_last_error",
             "dugks2p_batch_create", "dugks2p_batch_step", "dugks2p_batch_moments",
             "dugks2p_batch_monitors", "dugks2p_batch_get_populations", "dugks2p_batch_cells",
-            "dugks2p_batch_destroy")
+            "dugks2p_batch_destroy", "dugks2p_adjoint_workspace_bytes", "dugks2p_adjoint_create",
+            "dugks2p_adjoint_segment", "dugks2p_adjoint_initial", "dugks2p_adjoint_destroy")
 
 
 def _check(rc):
@@ -286,3 +297,76 @@ class BatchSimulation:
         if rc != OK and (raise_nonfinite or rc != ENONFINITE):
             _check(rc)
         return np.array(out[:])
+
+
+class Adjoint:
+    """Reverse sweep of FP64 rollouts (include/dugks2p.h, "Adjoint form").
+
+    Population-shaped tensors are torch float64 CUDA [18, ny, nx]; the
+    parameter gradient is a float64 CUDA tensor [3] = d/d(kappa, gx, gy),
+    accumulated in place."""
+
+    def __init__(self, params: dict, x_faces, y_faces, max_segment=50, stream=None):
+        import torch
+        self.torch = torch
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        self.max_segment = int(max_segment)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        P = make_params(params, x_faces, y_faces, FP64, KERNEL_STAGED)
+        nb = int(lib.dugks2p_adjoint_workspace_bytes(ctypes.byref(P), self.max_segment))
+        self._ws = None
+        if nb:
+            self._ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            P.workspace = (self._ws.data_ptr() + 255) & ~255
+            P.workspace_bytes = nb
+        h = ctypes.c_void_p()
+        _check(lib.dugks2p_adjoint_create(ctypes.byref(P), self.max_segment,
+                                          ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.dugks2p_adjoint_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _pops(self, a):
+        a = a.to(device=self.device, dtype=self.torch.float64).contiguous()
+        if tuple(a.shape) != (18, self.ny, self.nx):
+            raise ValueError("population shape %s != (18, %d, %d)" % (tuple(a.shape), self.ny,
+                                                                        self.nx))
+        return a
+
+    def _field(self, a):
+        t = self.torch
+        if isinstance(a, np.ndarray):
+            a = t.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        a = a.to(device=self.device, dtype=t.float64).contiguous()
+        if tuple(a.shape) != (self.ny, self.nx):
+            raise ValueError("field shape %s != (%d, %d)" % (tuple(a.shape), self.ny, self.nx))
+        return a
+
+    def segment(self, pops0, nsteps, lam_end, param_grad, out=None):
+        """Adjoint at the segment start from the adjoint after nsteps steps."""
+        pops0, lam_end = self._pops(pops0), self._pops(lam_end)
+        out = self.torch.empty_like(lam_end) if out is None else out
+        _check(lib.dugks2p_adjoint_segment(self._h, pops0.data_ptr(), int(nsteps),
+                                           lam_end.data_ptr(), out.data_ptr(),
+                                           param_grad.data_ptr()))
+        return out
+
+    def initial(self, phi0, ux0, uy0, p0, lam0, param_grad):
+        """Adjoint of the initialisation: returns dJ/d(phi0)."""
+        f = [self._field(a) for a in (phi0, ux0, uy0, p0)]
+        lam0 = self._pops(lam0)
+        out = self.torch.empty((self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+        _check(lib.dugks2p_adjoint_initial(self._h, *[a.data_ptr() for a in f], lam0.data_ptr(),
+                                           out.data_ptr(), param_grad.data_ptr()))
+        return out

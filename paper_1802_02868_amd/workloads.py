@@ -194,7 +194,7 @@ def rt_case(nx=256, ny=None, atwood=0.5, re=3000.0, pe=1000.0, sigma=5e-5, width
                     gx=0.0, gy=-g, rho_ref=rho_b, recon=recon)
     z = np.zeros_like(phi)
     return Case("rt%dx%d" % (nx, ny), p, xf, yf, phi, z.copy(), z.copy(), z.copy(), steps,
-                dict(g=g, nu=nu, lam=lam))
+                dict(g=g, nu=nu, lam=lam, width=width))
 
 
 def bubble_case(nx, ny, eo, mo, rho_l=1.0, rho_g=0.1, visc_ratio=100.0, width=4.0,
@@ -218,6 +218,34 @@ def bubble_case(nx, ny, eo, mo, rho_l=1.0, rho_g=0.1, visc_ratio=100.0, width=4.
     z = np.zeros_like(phi)
     return Case("bubble%dx%d" % (nx, ny), p, xf, yf, phi, z.copy(), z.copy(), z.copy(),
                 steps, dict(g=g, sigma=sigma, nu_l=nu_l, eo=eo, mo=mo))
+
+
+def rt_mode_amplitudes(nx, nmodes=64, seed=2024, sigma_frac=1e-3):
+    """Seeded amplitudes a_1..a_nmodes ~ N(0, (sigma_frac nx)^2) of the
+    interface modes of the differentiable Rayleigh-Taylor rollout."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return sigma_frac * nx * rng.standard_normal(nmodes)
+
+
+def rt_interface_phi0(amps, case):
+    """Order parameter of a Rayleigh-Taylor interface at
+    y_I(x) = ny/2 + sum_k a_k cos(2 pi k x / nx), k = 1..len(amps), with the
+    tanh profile of the case's width (heavy fluid A above).  Accepts a numpy
+    array or a torch tensor of amplitudes and returns the same kind (torch:
+    differentiable, on the amplitudes' device)."""
+    nx, ny = case.nx, case.ny
+    width = case.meta.get("width", 4.0)
+    xc, yc = centres(case.x_faces), centres(case.y_faces)
+    k = np.arange(1, len(amps) + 1, dtype=np.float64)
+    basis = np.cos(2.0 * np.pi * np.outer(k, xc) / nx)  # [modes, nx]
+    if isinstance(amps, np.ndarray):
+        yi = ny / 2.0 + amps @ basis
+        return np.ascontiguousarray(tanh_profile(yc[:, None] - yi[None, :], width))
+    import torch
+    B = torch.as_tensor(basis, dtype=torch.float64, device=amps.device)
+    Y = torch.as_tensor(yc, dtype=torch.float64, device=amps.device)
+    yi = ny / 2.0 + amps @ B
+    return (0.5 + 0.5 * torch.tanh(2.0 * (Y[:, None] - yi[None, :]) / width)).contiguous()
 
 
 BUBBLE_SIZES = ((128, 256), (160, 320), (192, 384), (256, 512))

@@ -12,7 +12,7 @@ CSRC = os.path.join(os.path.dirname(HERE), "paper_1802_02868_amd", "csrc")
 
 
 def build():
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-Wall",
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-Wall", "-Wno-unknown-pragmas",
            "-o", LIB + ".tmp", SRC]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
@@ -51,3 +51,21 @@ def run(case, steps, kernel=1):
                        pops.ctypes.data_as(dp), mac.ctypes.data_as(dp))
     assert rc == 0
     return pops, mac
+
+
+def adjoint(case, steps, mseg, lam):
+    """Rollout adjoint in the host build: returns (pops_T, phi0_grad, grad3)
+    for J = <lam, pops_T>, grad3 = dJ/d(kappa, gx, gy)."""
+    from paper_1802_02868_amd.dugks2p_params import make_params  # noqa: E402
+    P = make_params(case.params, case.x_faces, case.y_faces, kernel=1)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(18, case.ny, case.nx)
+    pops = np.empty((18, case.ny, case.nx))
+    g0 = np.empty((case.ny, case.nx))
+    g3 = np.empty(3)
+    fl = [np.ascontiguousarray(a, dtype=np.float64) for a in (case.phi0, case.ux0, case.uy0, case.p0)]
+    rc = lib().emu_adjoint(ctypes.byref(P), *[a.ctypes.data_as(dp) for a in fl],
+                           ctypes.c_longlong(steps), ctypes.c_int(mseg), lam.ctypes.data_as(dp),
+                           pops.ctypes.data_as(dp), g0.ctypes.data_as(dp), g3.ctypes.data_as(dp))
+    assert rc == 0
+    return pops, g0, g3

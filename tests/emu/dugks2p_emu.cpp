@@ -12,6 +12,7 @@
 
 #include "../../paper_1802_02868_amd/csrc/dugks2p_fused.hpp"
 #include "../../paper_1802_02868_amd/csrc/dugks2p_host.hpp"
+#include "../../paper_1802_02868_amd/csrc/dugks2p_adjoint.hpp"
 
 using namespace dg;
 
@@ -117,5 +118,67 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
         for (int f = 0; f < 5; ++f) macros[((size_t)f * K.ny + j) * K.nx + i] = vals[f];
       }
   }
+  return 0;
+}
+
+// Adjoint of a rollout in the host build: initialise, run nsteps staged
+// steps keeping a checkpoint every mseg steps, then sweep back segment by
+// segment and through Step 1.  lam_T: adjoint of the final populations
+// ([18][ny][nx]); outputs the final populations, the adjoint of phi0 and the
+// kappa / gx / gy gradients (grad3).
+extern "C" int emu_adjoint(const dugks2p_params *P, const double *phi0, const double *ux0,
+                           const double *uy0, const double *p0, long long nsteps, int mseg,
+                           const double *lam_T, double *pops_T, double *phi0_grad,
+                           double *grad3) {
+  const std::string err = validate(P);
+  if (!err.empty() || mseg < 1) return -1;
+  AxisHost ax, ay;
+  build_axis(ax, P->nx, P->bc_x, P->x_faces);
+  build_axis(ay, P->ny, P->bc_y, P->y_faces);
+  Consts K = make_consts(P, ax, ay);
+  pack_rows(K);
+  const AdjLayout AL = make_adj_layout(K, ax, ay, mseg);
+  std::vector<unsigned char> mem(AL.total + 256, 0);
+  unsigned char *base = (unsigned char *)(((uintptr_t)mem.data() + 255) & ~(uintptr_t)255);
+  memset(base, 0xff, AL.total);  // NaN poison: reads of unwritten scratch show
+  std::vector<unsigned char> tb;
+  pack_axis(ax, tb);
+  memcpy(base + AL.tables[0], tb.data(), tb.size());
+  pack_axis(ay, tb);
+  memcpy(base + AL.tables[1], tb.data(), tb.size());
+  K.ax[0] = bind_axis(ax, base + AL.tables[0]);
+  K.ax[1] = bind_axis(ay, base + AL.tables[1]);
+  const AdjBufs B{AL, base};
+  CpuEx ex;
+  const size_t np = 18 * (size_t)K.plane;
+  std::vector<double> st[2] = {std::vector<double>(np), std::vector<double>(np)};
+  const Work w = B.tape(0);
+  seq_init(ex, K, w, phi0, ux0, uy0, p0, IoF64{st[0].data(), K.plane});
+  std::vector<std::vector<double>> ck;
+  int cur = 0;
+  for (long long n = 0; n < nsteps; ++n) {
+    if (n % mseg == 0) ck.push_back(st[cur]);
+    seq_staged_step(ex, K, w, (const double *)st[cur].data(), st[1 - cur].data());
+    cur = 1 - cur;
+  }
+  memcpy(pops_T, st[cur].data(), np * sizeof(double));
+  std::vector<double> lam(lam_T, lam_T + np);
+  const double *pacc = B.adj(0).pacc;
+  for (int m = 0; m < 3; ++m) grad3[m] = 0.0;
+  auto reduce = [&]() {
+    for (int m = 0; m < 3; ++m) {
+      double s = 0.0;
+      for (i64 c = 0; c < K.plane; ++c) s += pacc[m * K.plane + c];
+      grad3[m] += s;
+    }
+  };
+  for (long long k = (long long)ck.size() - 1; k >= 0; --k) {
+    const long long left = nsteps - k * mseg;
+    const int ns = (int)(left < mseg ? left : mseg);
+    seq_adjoint_segment(ex, K, B, ck[k].data(), ns, lam.data(), lam.data());
+    reduce();
+  }
+  seq_adjoint_initial(ex, K, B, phi0, ux0, uy0, p0, lam.data(), phi0_grad);
+  reduce();
   return 0;
 }

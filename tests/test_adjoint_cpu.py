@@ -1,0 +1,108 @@
+"""The adjoint form's kernel logic (host build) against central finite
+differences of the oracle's forward rollout.
+
+J = <lam, populations after the rollout> for a seeded lam; the host build of
+the HIP adjoint gives dJ/d(phi0) and dJ/d(kappa, gx, gy); the oracle (an
+independent FP64 forward) gives the same directional derivatives by
+central differences.  Central differences with an absolute step of 1e-6 are
+good to about 1e-9 relative here, so a missing term, a wrong sign or a
+transposed stencil shows as an O(1) relative error.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from tests import _emu
+from paper_1802_02868_amd import workloads as W
+
+
+def _oracle_pops(oracle_mod, case, steps, **over):
+    o = oracle_mod.Oracle.from_case(case, **over)
+    o.step(steps)
+    return o.pops()
+
+
+def _cases():
+    drop = W.drop_case(16, radius=5.0, width=3.0, noise=1e-3)
+    drop.params.update(gx=1e-4, gy=-2e-4, rho_ref=0.5)
+    rt = W.rt_case(8, 32)
+    rt.params.update(gx=3e-5)
+    pz = W.poiseuille_case(4, 32)
+    pz.params.update(gy=1e-5)
+    bub = W.bubble_case(16, 24, 30.0, 1e-3)
+    bub.params.update(phi_clamp=0, gx=2e-5)
+    ragged = W.rt_case(7, 13)
+    ragged.params.update(gx=1e-5)
+    return [(drop, 3, 2), (rt, 7, 3), (pz, 5, 5), (bub, 6, 4), (ragged, 4, 3)]
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("case,steps,mseg", CASES, ids=[c[0].name for c in CASES])
+def test_adjoint_matches_oracle_fd(oracle_mod, case, steps, mseg):
+    rng = np.random.default_rng(7)
+    lam = rng.standard_normal((18, case.ny, case.nx))
+    pops, g0, g3 = _emu.adjoint(case, steps, mseg, lam)
+    # the rollout itself is the oracle's, bit for bit
+    assert np.array_equal(pops, _oracle_pops(oracle_mod, case, steps))
+    eps = 1e-6
+    for _ in range(2):
+        d = rng.standard_normal((case.ny, case.nx))
+        fp = _oracle_pops(oracle_mod, dataclasses.replace(case, phi0=case.phi0 + eps * d), steps)
+        fm = _oracle_pops(oracle_mod, dataclasses.replace(case, phi0=case.phi0 - eps * d), steps)
+        fd = float(np.sum(lam * (fp - fm))) / (2 * eps)
+        ad = float(np.sum(g0 * d))
+        assert abs(ad - fd) <= 1e-7 * abs(fd), (ad, fd)
+    for k, name in enumerate(("kappa", "gx", "gy")):
+        v = case.params[name]
+        fp = _oracle_pops(oracle_mod, case, steps, **{name: v + eps})
+        fm = _oracle_pops(oracle_mod, case, steps, **{name: v - eps})
+        fd = float(np.sum(lam * (fp - fm))) / (2 * eps)
+        assert abs(g3[k] - fd) <= 1e-6 * abs(fd) + 1e-12, (name, g3[k], fd)
+
+
+def test_adjoint_init_only(oracle_mod):
+    """Zero steps: only the adjoint of Step 1 (eq. auxf with the equilibria)."""
+    case, _, _ = CASES[0]
+    rng = np.random.default_rng(3)
+    lam = rng.standard_normal((18, case.ny, case.nx))
+    _, g0, g3 = _emu.adjoint(case, 0, 4, lam)
+    d = rng.standard_normal((case.ny, case.nx))
+    eps = 1e-6
+    fp = _oracle_pops(oracle_mod, dataclasses.replace(case, phi0=case.phi0 + eps * d), 0)
+    fm = _oracle_pops(oracle_mod, dataclasses.replace(case, phi0=case.phi0 - eps * d), 0)
+    fd = float(np.sum(lam * (fp - fm))) / (2 * eps)
+    assert abs(float(np.sum(g0 * d)) - fd) <= 1e-8 * abs(fd)
+    for k, name in enumerate(("kappa", "gx", "gy")):
+        v = case.params[name]
+        fp = _oracle_pops(oracle_mod, case, 0, **{name: v + eps})
+        fm = _oracle_pops(oracle_mod, case, 0, **{name: v - eps})
+        fd = float(np.sum(lam * (fp - fm))) / (2 * eps)
+        assert abs(g3[k] - fd) <= 1e-7 * abs(fd) + 1e-12
+
+
+def test_adjoint_segment_length_invariant():
+    """Checkpoint spacing changes only where the forward is recomputed, so
+    the adjoint is the same bit for bit for any segment length."""
+    case, steps, _ = CASES[1]
+    lam = np.random.default_rng(11).standard_normal((18, case.ny, case.nx))
+    ref = _emu.adjoint(case, steps, steps, lam)
+    for m in (1, 2, 5):
+        got = _emu.adjoint(case, steps, m, lam)
+        assert np.array_equal(got[1], ref[1])
+        # parameter sums are added segment by segment: equal to rounding
+        assert np.allclose(got[2], ref[2], rtol=1e-13, atol=0)
+
+
+def test_adjoint_linear_in_lam():
+    case, steps, mseg = CASES[3]
+    rng = np.random.default_rng(5)
+    l1 = rng.standard_normal((18, case.ny, case.nx))
+    l2 = rng.standard_normal((18, case.ny, case.nx))
+    a = _emu.adjoint(case, steps, mseg, l1)
+    b = _emu.adjoint(case, steps, mseg, l2)
+    c = _emu.adjoint(case, steps, mseg, 2.0 * l1 - 3.0 * l2)
+    assert np.allclose(c[1], 2.0 * a[1] - 3.0 * b[1], rtol=1e-11, atol=1e-11 * np.abs(c[1]).max())
+    assert np.allclose(c[2], 2.0 * a[2] - 3.0 * b[2], rtol=1e-10)

@@ -1,0 +1,164 @@
+"""GPU adjoint form through the C ABI: against the host build of the same
+kernel logic, against central differences of the oracle through the
+torch.autograd.Function on a 64 x 256 Rayleigh-Taylor rollout with 64
+interface modes, and its argument contracts."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1802_02868_amd import workloads as W
+from tests import _emu
+from tests.test_adjoint_cpu import CASES
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_02868_amd import dugks2p
+    return dugks2p
+
+
+def _gpu_adjoint(D, case, steps, mseg, lam):
+    import torch
+    sim = D.Simulation.from_case(case, precision=D.FP64, kernel=D.KERNEL_AUTO)
+    ck = []
+    done = 0
+    while done < steps:
+        ck.append(sim.populations())
+        n = min(mseg, steps - done)
+        sim.step(n)
+        done += n
+    pops = sim.populations()
+    adj = D.Adjoint(case.params, case.x_faces, case.y_faces, max_segment=mseg)
+    pg = torch.zeros(3, dtype=torch.float64, device="cuda")
+    L = torch.from_numpy(lam).cuda()
+    for k in range(len(ck) - 1, -1, -1):
+        L = adj.segment(ck[k], min(mseg, steps - k * mseg), L, pg)
+    g0 = adj.initial(case.phi0, case.ux0, case.uy0, case.p0, L, pg)
+    torch.cuda.synchronize()
+    adj.close()
+    sim.close()
+    return pops.cpu().numpy(), g0.cpu().numpy(), pg.cpu().numpy()
+
+
+@pytest.mark.parametrize("case,steps,mseg", CASES, ids=[c[0].name for c in CASES])
+def test_gpu_adjoint_matches_host_build(D, case, steps, mseg):
+    print("adjoint vs host build:", case.name, steps, mseg, flush=True)
+    lam = np.random.default_rng(7).standard_normal((18, case.ny, case.nx))
+    pops, g0, g3 = _gpu_adjoint(D, case, steps, mseg, lam)
+    epops, eg0, eg3 = _emu.adjoint(case, steps, mseg, lam)
+    assert np.array_equal(pops, epops)
+    err = np.max(np.abs(g0 - eg0)) / np.max(np.abs(eg0))
+    print("  phi0 grad rel diff %.3e, bitwise %s" % (err, np.array_equal(g0, eg0)))
+    assert err <= 1e-12
+    assert np.allclose(g3, eg3, rtol=1e-11, atol=0)
+
+
+def test_gpu_adjoint_deterministic_and_inplace(D):
+    import torch
+    case, steps, mseg = CASES[1]
+    print("adjoint determinism:", case.name, flush=True)
+    lam = np.random.default_rng(9).standard_normal((18, case.ny, case.nx))
+    a = _gpu_adjoint(D, case, steps, mseg, lam)
+    b = _gpu_adjoint(D, case, steps, mseg, lam)
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    # lam_begin may alias lam_end; nsteps = 0 copies and adds nothing
+    sim = D.Simulation.from_case(case)
+    p0 = sim.populations()
+    adj = D.Adjoint(case.params, case.x_faces, case.y_faces, max_segment=4)
+    pg = torch.zeros(3, dtype=torch.float64, device="cuda")
+    L = torch.from_numpy(lam).cuda()
+    ref = adj.segment(p0, 3, L.clone(), pg.clone())
+    out = adj.segment(p0, 3, L, torch.zeros(3, dtype=torch.float64, device="cuda"), out=L)
+    assert torch.equal(out, ref)
+    L2 = torch.from_numpy(lam).cuda()
+    same = adj.segment(p0, 0, L2, pg)
+    assert torch.equal(same, L2) and float(pg.abs().sum()) == 0.0
+    torch.cuda.synchronize()
+    adj.close()
+    sim.close()
+
+
+def test_gpu_adjoint_contracts(D):
+    import torch
+    case = CASES[0][0]
+    bad = [dict(precision=D.FP32_STATE), dict(recon=D.RECON_UPWIND), dict(phi_clamp=1)]
+    for over in bad:
+        p = dict(case.params)
+        p.update(over)
+        with pytest.raises(D.DugksError) as e:
+            D.Adjoint(p, case.x_faces, case.y_faces, max_segment=4)
+        assert e.value.code == D.EINVAL
+    with pytest.raises(D.DugksError):
+        D.Adjoint(case.params, case.x_faces, case.y_faces, max_segment=0)
+    adj = D.Adjoint(case.params, case.x_faces, case.y_faces, max_segment=2)
+    z = torch.zeros((18, case.ny, case.nx), dtype=torch.float64, device="cuda")
+    pg = torch.zeros(3, dtype=torch.float64, device="cuda")
+    with pytest.raises(D.DugksError) as e:
+        adj.segment(z, 3, z, pg)
+    assert e.value.code == D.EINVAL
+    adj.close()
+
+
+def test_gpu_rollout_gradient_rt64x256(D, oracle_mod):
+    """dJ/d(a_1..a_64, kappa, g) of J = sum (phi(T) - phi_ref)^2 through the
+    autograd.Function (checkpoints every 50 steps, ragged last segment),
+    against central differences of the oracle in scaled coordinates
+    (a / sigma_a, kappa / kappa0, g / g0) along seeded unit directions."""
+    import torch
+    from paper_1802_02868_amd.rollout import rollout
+    case = W.rt_case(64)
+    steps, every = 120, 50
+    print("rollout gradient:", case.name, steps, every, flush=True)
+    a0 = W.rt_mode_amplitudes(64, 64, seed=2024)
+    sig = 1e-3 * 64
+    ref = W.rt_interface_phi0(W.rt_mode_amplitudes(64, 64, seed=77), case)
+    k0, g0 = case.params["kappa"], case.params["gy"]
+    a = torch.tensor(a0, dtype=torch.float64, device="cuda", requires_grad=True)
+    kap = torch.tensor(k0, dtype=torch.float64, device="cuda", requires_grad=True)
+    g = torch.tensor([case.params["gx"], g0], dtype=torch.float64, device="cuda",
+                     requires_grad=True)
+    pops = rollout(W.rt_interface_phi0(a, case), kap, g, case, steps, every)
+    R = torch.from_numpy(ref).cuda()
+    J = ((pops[9:].sum(0) - R) ** 2).sum()
+    J.backward()
+    ga, gk, gg = a.grad.cpu().numpy(), float(kap.grad), g.grad.cpu().numpy()
+    # scaled-coordinate gradient: (a / sig, kappa / k0, gx / |g0|, gy / |g0|)
+    grad_s = np.concatenate([ga * sig, [gk * k0], gg * abs(g0)])
+
+    def J_oracle_diff(theta_p, theta_m):
+        out = []
+        for th in (theta_p, theta_m):
+            amps = th[:64] * sig
+            c = dataclasses.replace(case, phi0=W.rt_interface_phi0(amps, case))
+            o = oracle_mod.Oracle.from_case(c, kappa=th[64] * k0, gx=th[65] * abs(g0),
+                                            gy=th[66] * abs(g0))
+            o.step(steps)
+            out.append(o.pops()[9:].sum(0))
+        pp, pm = out
+        return float(np.sum((pp - pm) * (pp + pm - 2.0 * ref)))
+
+    theta = np.concatenate([a0 / sig, [1.0], [case.params["gx"] / abs(g0), g0 / abs(g0)]])
+    rng = np.random.default_rng(31)
+    # a step of 1e-4 in scaled coordinates: the truncation error is then
+    # below 1e-8 relative and roundoff in the differences is still small
+    eps = 1e-4
+    for _ in range(4):
+        d = rng.standard_normal(theta.size)
+        d /= np.linalg.norm(d)
+        fd = J_oracle_diff(theta + eps * d, theta - eps * d) / (2 * eps)
+        ad = float(grad_s @ d)
+        print("  direction: ad %.10e fd %.10e" % (ad, fd), flush=True)
+        assert abs(ad - fd) <= 1e-6 * abs(fd)
+    # forward of the Function is the oracle's rollout bit for bit
+    c = dataclasses.replace(case, phi0=W.rt_interface_phi0(a0, case))
+    assert float(J) > 0.0
+    o = oracle_mod.Oracle.from_case(c)
+    o.step(steps)
+    phi_o = o.pops()[9:].sum(0)
+    assert np.max(np.abs(pops[9:].sum(0).detach().cpu().numpy() - phi_o)) <= 1e-13
