@@ -18,8 +18,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+
+# HBM bytes per launch of the fused FP64 step kernel on the Rayleigh-Taylor
+# 256 x 1024 workload, from FETCH_SIZE / WRITE_SIZE counters scaled by a
+# plain copy (profiles/fused_rt256x1024_fp64_traffic.md).  Valid only while
+# the kernel sources hash to the measured version.
+TRAFFIC = {"workload": "rt256x1024", "precision": "fp64", "src_sha": "531a6e7b4aeb788b",
+           "bytes_per_launch": 151.2e6}
+
 FP64_VEC_PEAK_TF = 78.6    # MI355X FP64 vector
 FP32_VEC_PEAK_TF = 157.3
+
+
+def kernel_src_sha():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1802_02868_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("dugks2p_dev.hpp", "dugks2p_fused.hpp"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def workload(name: str):
@@ -211,8 +229,13 @@ def main():
     fused = sim.kernel_kind == D.KERNEL_FUSED
     launches_per_step = 1 if fused else 7
     achieved = bytes_per_cell * cells / (ms_per_step / 1e3) / 1e9
+    traffic = None
+    if (fused and prec == D.FP64 and args.workload == TRAFFIC["workload"]
+            and kernel_src_sha() == TRAFFIC["src_sha"]):
+        traffic = TRAFFIC["bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM, counters)",
             "kernel": "dugks2p fused step" if fused else "staged step (7 kernels, summed)",
             "algorithmic_bytes_per_cell": bytes_per_cell,
             "launches_per_step": launches_per_step}

@@ -4,8 +4,8 @@
 // Forward quantities are recomputed from the staged forward arrays of the
 // same step (phi, rho, mu, grad phi, grad mu, D, F, u, p, grad p, bar+).  The
 // reverse sweep mirrors the forward stages:
-//   face stage  -> per-face slots (adjoints sent to the two cells of a face)
-//   gather      -> per-cell sums of the slots of the cell's four faces
+//   face stage  -> per-face records (adjoint of the face values and fields)
+//   gather      -> per-cell sums over the records of the cell's four faces
 //   Step 2      -> adjoint of the cell transforms (eqs. relations1/2)
 //   macros      -> adjoint of eqs. u, P and of F, D
 //   mu          -> adjoint of eq. chemicalpotential
@@ -103,36 +103,79 @@ DFN void tauf_grad(const Consts &K, double phi, double rho, double &dphi, double
   drho = -tf / rho;
 }
 
-// Adjoint of cell_barp (Step 2): out_bar (18) -> til_bar (18), mb, tf_bar.
-DFN void cell_barp_vjp(const Consts &K, const Mac<double> &m, double tf, const double til[18],
-                       const double ob[18], double tilb[18], Mac<double> &mb, double &tfb) {
-  const double uu = m.ux * m.ux + m.uy * m.uy;
-  const double den = 1.0 / (2.0 * tf + K.dt);
-  const double fca = (2.0 * tf - K.h) * den, fcb = 3.0 * K.h * den, fcc = 3.0 * tf * K.h * den;
-  double fcab = 0.0, fcbb = 0.0, fccb = 0.0, uub = 0.0;
-  for (int i = 0; i < 9; ++i) {
-    double feq, geq, ff, fg;
-    point_eq1<double>(K, m, uu, i, feq, geq, ff, fg);
-    tilb[i] = fca * ob[i];
-    fcab += til[i] * ob[i];
-    fcbb += feq * ob[i];
-    fccb += ff * ob[i];
-    tilb[9 + i] = K.gca * ob[9 + i];
-    point_eq1_vjp(K, m, uu, i, fcb * ob[i], K.gcb * ob[9 + i], fcc * ob[i], K.gcc * ob[9 + i],
-                  mb, uub);
+// ---------------------------------------------------------------------------
+// Work arrays of the reverse sweep.
+// ---------------------------------------------------------------------------
+enum {
+  FB_MU, FB_D, FB_PHI, FB_P, FB_DMUX, FB_DMUY, FB_DPHX, FB_DPHY, FB_DPX, FB_DPY, FB_RHO, FB_FX,
+  FB_FY, FB_UX, FB_UY, FB_S0, FB_JX, FB_JY, FB_LAPMU, FB_LAPPHI, FB_KAP, FB_GX, FB_GY, NFB
+};
+// Per-face record of the face stage: adjoint of the 18 reconstructed face
+// values bar (after folding the bounce-back copies), of the 8 face fields and
+// the body-force partials of the face.
+enum {
+  FS_B = 0, FS_MU = 18, FS_D, FS_GMX, FS_GMY, FS_GFX, FS_GFY, FS_GPX, FS_GPY, FS_GX, FS_GY, NFS
+};
+
+struct AdjWork {
+  const double *lam;  // 18 planes: adjoint of the state after the step
+  double *out;        // 18 planes: adjoint of the state before the step
+  double *xs, *ys;    // face records: NFS planes of xplane / yplane
+  double *ab, *gxb, *gyb;  // per cell: bar+ adjoint and its gradient adjoints (18 planes each)
+  double *fb;         // NFB planes of per-cell field adjoints and parameter partials
+  double *pacc;       // 3 planes: per-cell sums over steps of the kappa, gx, gy partials
+};
+
+// Transpose of a three-point stencil along one axis at one cell: the cells
+// whose stencil reads this cell (at most three, each counted once) and the
+// summed weight with which each reads it.  Unused entries have weight 0 and
+// point at the cell itself.
+struct TW {
+  i64 id[3];
+  double w[3];
+};
+
+DFN TW stencil_tw(const Consts &K, int ax, const double *wt3, int i, int j) {
+  const Axis &X = K.ax[ax];
+  const int c = ax == 0 ? i : j;
+  const int cand[3] = {X.lo[c], c, X.hi[c]};
+  TW t;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int cp = cand[a];
+    bool dup = false;
+    for (int b = 0; b < a; ++b) dup |= cand[b] == cp;
+    const int tgt[3] = {X.lo[cp], cp, X.hi[cp]};
+    const double *w = wt3 + 3 * cp;
+    double s = 0.0;
+    if (!dup)
+      for (int m = 0; m < 3; ++m)
+        if (tgt[m] == c) s += w[m];
+    t.w[a] = s;
+    t.id[a] = ax == 0 ? (i64)j * K.ld + cp : (i64)cp * K.ld + i;
   }
-  mb.ux += 2.0 * m.ux * uub;
-  mb.uy += 2.0 * m.uy * uub;
-  const double denb = (2.0 * tf - K.h) * fcab + 3.0 * K.h * fcbb + 3.0 * tf * K.h * fccb;
-  tfb += 2.0 * den * fcab + 3.0 * K.h * den * fccb - 2.0 * den * den * denb;
+  return t;
 }
 
-// Adjoint of face_dist (Step 4 at a face): out_bar (18) -> bar_bar (18),
-// face-field adjoints fb and the body-force partials (gxb, gyb).
-DFN void face_dist_vjp(const Consts &K, const FaceFields<double> &fl, const double bar[18],
-                       const double ob[18], double barb[18], FaceFields<double> &fb,
-                       double &gxb, double &gyb) {
-  // forward recomputation (face_dist)
+DFN double tw_apply(const TW &t, const double *B) {
+  return t.w[0] * B[t.id[0]] + t.w[1] * B[t.id[1]] + t.w[2] * B[t.id[2]];
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of Step 4 at a face (eq. original-function with the face macros
+// of eq. conservedVariable at h, the equilibria and the sources).
+// ob(q): adjoint of the face distribution q.  Accumulates the face-field
+// adjoints into fb and the body-force partials into gxb, gyb; returns what
+// the adjoint of bar q needs: bar_b(q) = fk1 ob(q) + s0b + xi_q . (jxb, jyb)
+// for q < 9 and gk1 ob(q) + phibb for the g populations.
+// ---------------------------------------------------------------------------
+struct FaceBack {
+  double fk1, s0b, jxb, jyb, phibb;
+};
+
+template <class OB>
+DFN FaceBack face_dist_vjp(const Consts &K, const FaceFields<double> &fl, const double bar[18],
+                           const OB &ob, FaceFields<double> &fb, double &gxb, double &gyb) {
   Mac<double> m;
   double phib = 0.0;
   for (int i = 0; i < 9; ++i) phib += bar[9 + i];
@@ -158,47 +201,47 @@ DFN void face_dist_vjp(const Consts &K, const FaceFields<double> &fl, const doub
   const double tf = tauf_of<double>(K, phib, m.rho);
   const double den = 1.0 / (2.0 * tf + K.h);
   const double fk1 = 2.0 * tf * den, fk2 = K.h * den, fk3 = tf * K.h * den;
-  // reverse
   Mac<double> mb;
   mac_zero(mb);
   double uub = 0.0, fk1b = 0.0, fk2b = 0.0, fk3b = 0.0;
-  for (int i = 0; i < 18; ++i) barb[i] = 0.0;
+  // one direction at a time (a rolled loop keeps the register footprint
+  // small); bar is indexed only in unrolled loops so it stays in registers
+#pragma unroll 1
   for (int i = 0; i < 9; ++i) {
     double feq, geq, ff, fg;
     point_eq1<double>(K, m, uu, i, feq, geq, ff, fg);
-    barb[i] += fk1 * ob[i];
-    fk1b += bar[i] * ob[i];
-    fk2b += feq * ob[i];
-    fk3b += ff * ob[i];
-    barb[9 + i] += K.gk1 * ob[9 + i];
-    point_eq1_vjp(K, m, uu, i, fk2 * ob[i], K.gk2 * ob[9 + i], fk3 * ob[i], K.gk3 * ob[9 + i],
-                  mb, uub);
+    const double obf = ob(i), obg = ob(9 + i);
+    fk2b += feq * obf;
+    fk3b += ff * obf;
+    point_eq1_vjp(K, m, uu, i, fk2 * obf, K.gk2 * obg, fk3 * obf, K.gk3 * obg, mb, uub);
   }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fk1b += bar[i] * ob(i);
   // fk1 = 2 tf den, fk2 = h den, fk3 = tf h den, den = 1/(2 tf + h)
   const double denb = 2.0 * tf * fk1b + K.h * fk2b + tf * K.h * fk3b;
-  double tfb = 2.0 * den * fk1b + K.h * den * fk3b - 2.0 * den * den * denb;
-  double phibb = 0.0, rhob = mb.rho;
+  const double tfb = 2.0 * den * fk1b + K.h * den * fk3b - 2.0 * den * den * denb;
   double dtp, dtr;
   tauf_grad(K, phib, m.rho, dtp, dtr);
-  phibb += dtp * tfb;
-  rhob += dtr * tfb;
+  double phibb = dtp * tfb, rhob = mb.rho + dtr * tfb;
   mb.ux += 2.0 * m.ux * uub;
   mb.uy += 2.0 * m.uy * uub;
   // p = s0 + hhcs2 (ux grx + uy gry - gam rho D)
   const double pb = mb.p;
-  double s0b = pb;
   mb.ux += K.hhcs2 * m.grx * pb;
   mb.grx += K.hhcs2 * m.ux * pb;
   mb.uy += K.hhcs2 * m.gry * pb;
   mb.gry += K.hhcs2 * m.uy * pb;
   rhob += -K.hhcs2 * K.gam * m.D * pb;
   mb.D += -K.hhcs2 * K.gam * m.rho * pb;
-  // ux = (jx + hhcs2 Fx) icr
-  const double jxb = m.icr * mb.ux, jyb = m.icr * mb.uy;
+  // u = (j + hhcs2 F) icr
+  FaceBack r;
+  r.fk1 = fk1;
+  r.s0b = pb;
+  r.jxb = m.icr * mb.ux;
+  r.jyb = m.icr * mb.uy;
   mb.Fx += K.hhcs2 * m.icr * mb.ux;
   mb.Fy += K.hhcs2 * m.icr * mb.uy;
   mb.icr += (jx + K.hhcs2 * m.Fx) * mb.ux + (jy + K.hhcs2 * m.Fy) * mb.uy;
-  for (int i = 0; i < 9; ++i) barb[i] += s0b + K.xi0[i] * jxb + K.xi1[i] * jyb;
   // icr = 1/(cs2 rho)
   rhob += -K.cs2 * m.icr * m.icr * mb.icr;
   // F = -phib gm + (rho - rho_ref) g
@@ -214,52 +257,8 @@ DFN void face_dist_vjp(const Consts &K, const FaceFields<double> &fl, const doub
   fb.gpy += mb.gpy;
   fb.mu += mb.mu;
   fb.D += mb.D;
-  phibb += mb.phi + K.drho * rhob;
-  for (int i = 0; i < 9; ++i) barb[9 + i] += phibb;
-}
-
-// ---------------------------------------------------------------------------
-// Work arrays of the reverse sweep.
-// ---------------------------------------------------------------------------
-enum {
-  FB_MU, FB_D, FB_PHI, FB_P, FB_DMUX, FB_DMUY, FB_DPHX, FB_DPHY, FB_DPX, FB_DPY, FB_RHO, FB_FX,
-  FB_FY, FB_UX, FB_UY, FB_S0, FB_JX, FB_JY, FB_LAPMU, FB_LAPPHI, FB_KAP, FB_GX, FB_GY, NFB
-};
-// Per-face record of the face stage: adjoint of the 18 reconstructed face
-// values bar (after folding the bounce-back copies), of the 8 face fields and
-// the body-force partials of the face.
-enum {
-  FS_B = 0, FS_MU = 18, FS_D, FS_GMX, FS_GMY, FS_GFX, FS_GFY, FS_GPX, FS_GPY, FS_GX, FS_GY, NFS
-};
-
-struct AdjWork {
-  const double *lam;  // 18 planes: adjoint of the state after the step
-  double *out;        // 18 planes: adjoint of the state before the step
-  double *xs, *ys;    // face records: NFS planes of xplane / yplane
-  double *ab, *gxb, *gyb;  // per cell: bar+ adjoint and its gradient adjoints (18 planes each)
-  double *fb;         // NFB planes of per-cell field adjoints and parameter partials
-  double *pacc;       // 3 planes: per-cell sums over steps of the kappa, gx, gy partials
-};
-
-// Transpose of a three-point stencil along axis ax at cell (i, j): the sum,
-// over the cells whose stencil reads (i, j), of weight times their adjoint.
-DFN double stencil_T(const Consts &K, int ax, const double *wt3, const double *B, int i, int j) {
-  const Axis &X = K.ax[ax];
-  const int c = ax == 0 ? i : j;
-  const int cand[3] = {X.lo[c], c, X.hi[c]};
-  double acc = 0.0;
-  for (int a = 0; a < 3; ++a) {
-    bool dup = false;
-    for (int b = 0; b < a; ++b) dup |= cand[b] == cand[a];
-    if (dup) continue;
-    const int cp = cand[a];
-    const int tgt[3] = {X.lo[cp], cp, X.hi[cp]};
-    const double *w = wt3 + 3 * cp;
-    const i64 id = ax == 0 ? (i64)j * K.ld + cp : (i64)cp * K.ld + i;
-    for (int s = 0; s < 3; ++s)
-      if (tgt[s] == c) acc += w[s] * B[id];
-  }
-  return acc;
+  r.phibb = phibb + mb.phi + K.drho * rhob;
+  return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -267,8 +266,8 @@ DFN double stencil_T(const Consts &K, int ax, const double *wt3, const double *B
 // ---------------------------------------------------------------------------
 
 // Face stage: adjoint of the face distributions from the update (eq.
-// updatef), then of Step 4 (eq. original-function) and of the bounce-back;
-// the adjoint of bar and of the face fields go to the face record.
+// updatef), then of Step 4 and of the bounce-back copies; the adjoint of bar
+// and of the face fields go to the face record.
 template <int A>
 struct FAdjFace {
   Consts K;
@@ -280,46 +279,54 @@ struct FAdjFace {
     const int cl = ax.fl[k], cr = ax.fr[k];
     const GAcc acc{&K, &w};
     const int TA = 1 - A;
-    const i64 fid = A == 0 ? (i64)t * K.nfx + k : (i64)k * K.ld + t;
     const i64 fpl = A == 0 ? K.xplane : K.yplane;
-    double *rec = (A == 0 ? a.xs : a.ys) + fid;
-#define CX(ia) (A == 0 ? (ia) : t)
-#define CY(ia) (A == 0 ? t : (ia))
+    double *rec = (A == 0 ? a.xs + (i64)t * K.nfx + k : a.ys + (i64)k * K.ld + t);
+    const bool wall = cl < 0 || cr < 0;
+    const int nout = cl < 0 ? -1 : 1;  // outward normal of the fluid cell (walls)
+    const i64 P = K.plane;
+    const i64 cL = cl >= 0 ? (A == 0 ? (i64)t * K.ld + cl : (i64)cl * K.ld + t) : 0;
+    const i64 cR = cr >= 0 ? (A == 0 ? (i64)t * K.ld + cr : (i64)cr * K.ld + t) : 0;
+    const double rL = cl >= 0 ? ax.rdt[cl] : 0.0, rR = cr >= 0 ? ax.rdt[cr] : 0.0;
+    const double *lam = a.lam;
     // the face value enters the update of cell L with -r_L xi_n and of
-    // cell R with +r_R xi_n
-    double ob[18];
-    for (int q = 0; q < 18; ++q) {
-      const int i = q % 9;
-      const double xn = A == 0 ? K.xi0[i] : K.xi1[i];
+    // cell R with +r_R xi_n; at a wall the entering values are copies of
+    // the outgoing opposite ones, so their adjoint folds onto those
+    auto ob_raw = [&](int q) {
+      const double xn = A == 0 ? K.xi0[q % 9] : K.xi1[q % 9];
       double v = 0.0;
-      if (cl >= 0) v += -(ax.rdt[cl] * xn) * a.lam[q * K.plane + (i64)CY(cl) * K.ld + CX(cl)];
-      if (cr >= 0) v += (ax.rdt[cr] * xn) * a.lam[q * K.plane + (i64)CY(cr) * K.ld + CX(cr)];
-      ob[q] = v;
-    }
+      if (cl >= 0) v += -(rL * xn) * lam[q * P + cL];
+      if (cr >= 0) v += (rR * xn) * lam[q * P + cR];
+      return v;
+    };
+    auto en_of = [&](int q) { return A == 0 ? ex_of(q % 9) : ey_of(q % 9); };
+    auto ob = [&](int q) {
+      const int en = en_of(q);
+      if (wall && en * nout < 0) return 0.0;
+      double v = ob_raw(q);
+      if (wall && en * nout > 0) v += ob_raw(q - q % 9 + opp_of(q % 9));
+      return v;
+    };
     const double h = K.h;
-    double bar[18], barb[18];
+    double bar[18];
     FaceFields<double> fl, fb;
     fb.mu = fb.D = fb.gmx = fb.gmy = fb.gfx = fb.gfy = fb.gpx = fb.gpy = 0.0;
     double gxb = 0.0, gyb = 0.0;
-    if (cl < 0 || cr < 0) {
+    if (wall) {
       const int cc = cl < 0 ? cr : cl;
       const double off = cl < 0 ? ax.foffr[k] : ax.foffl[k];
-      const int nout = cl < 0 ? -1 : 1;
-      const GAcc::H HC = acc.cell(CX(cc), CY(cc));
+      const GAcc::H HC = acc.cell(A == 0 ? cc : t, A == 0 ? t : cc);
+#pragma unroll
       for (int q = 0; q < 18; ++q) {
         const int i = q % 9;
-        const int en = A == 0 ? ex_of(i) : ey_of(i);
-        if (en * nout < 0) continue;
+        if (en_of(q) * nout < 0) continue;
         const double Gn = acc.pgrad(A, q, HC), Gt = acc.pgrad(TA, q, HC);
         const double val = acc.A(q, HC) + off * Gn;
         const double sgx = A == 0 ? Gn : Gt, sgy = A == 0 ? Gt : Gn;
         bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
       }
-      for (int q = 0; q < 18; ++q) {
-        const int i = q % 9;
-        const int en = A == 0 ? ex_of(i) : ey_of(i);
-        if (en * nout < 0) bar[q] = bar[q - i + opp_of(i)];
-      }
+#pragma unroll
+      for (int q = 0; q < 18; ++q)
+        if (en_of(q) * nout < 0) bar[q] = bar[q - q % 9 + opp_of(q % 9)];
       fl.mu = acc.mu(HC);
       fl.D = acc.D(HC);
       const double tmu = acc.dmu(TA, HC), tph = acc.dphi(TA, HC), tp = acc.dp(TA, HC);
@@ -329,27 +336,11 @@ struct FAdjFace {
       fl.gfy = A == 0 ? tph : 0.0;
       fl.gpx = A == 0 ? 0.0 : tp;
       fl.gpy = A == 0 ? tp : 0.0;
-      // reverse of: copy of the outgoing face values onto the entering ones
-      for (int q = 0; q < 18; ++q) {
-        const int i = q % 9;
-        const int en = A == 0 ? ex_of(i) : ey_of(i);
-        if (en * nout < 0) {
-          ob[q - i + opp_of(i)] += ob[q];
-          ob[q] = 0.0;
-        }
-      }
-      face_dist_vjp(K, fl, bar, ob, barb, fb, gxb, gyb);
-      for (int q = 0; q < 18; ++q) {
-        const int i = q % 9;
-        const int en = A == 0 ? ex_of(i) : ey_of(i);
-        if (en * nout < 0) {
-          barb[q - i + opp_of(i)] += barb[q];
-          barb[q] = 0.0;
-        }
-      }
     } else {
-      const GAcc::H HL = acc.cell(CX(cl), CY(cl)), HR = acc.cell(CX(cr), CY(cr));
+      const GAcc::H HL = acc.cell(A == 0 ? cl : t, A == 0 ? t : cl);
+      const GAcc::H HR = acc.cell(A == 0 ? cr : t, A == 0 ? t : cr);
       const FaceW fw{ax.fwl[k], ax.fwr[k], ax.finv[k]};
+#pragma unroll
       for (int q = 0; q < 18; ++q) {
         const int i = q % 9;
         const double AL = acc.A(q, HL), AR = acc.A(q, HR);
@@ -372,9 +363,25 @@ struct FAdjFace {
       face_field(fw, acc.p(HL), acc.p(HR), acc.dp(TA, HL), acc.dp(TA, HR), tmp, gn, gt);
       fl.gpx = A == 0 ? gn : gt;
       fl.gpy = A == 0 ? gt : gn;
-      face_dist_vjp(K, fl, bar, ob, barb, fb, gxb, gyb);
     }
-    for (int q = 0; q < 18; ++q) rec[(FS_B + q) * fpl] = barb[q];
+    const FaceBack r = face_dist_vjp(K, fl, bar, ob, fb, gxb, gyb);
+    auto barb = [&](int q) {
+      const int i = q % 9;
+      return q < 9 ? r.fk1 * ob(q) + (r.s0b + K.xi0[i] * r.jxb + K.xi1[i] * r.jyb)
+                   : K.gk1 * ob(q) + r.phibb;
+    };
+#pragma unroll
+    for (int q = 0; q < 18; ++q) {
+      const int en = en_of(q);
+      double v;
+      if (wall && en * nout < 0)
+        v = 0.0;
+      else if (wall && en * nout > 0)
+        v = barb(q) + barb(q - q % 9 + opp_of(q % 9));
+      else
+        v = barb(q);
+      rec[(FS_B + q) * fpl] = v;
+    }
     rec[FS_MU * fpl] = fb.mu;
     rec[FS_D * fpl] = fb.D;
     rec[FS_GMX * fpl] = fb.gmx;
@@ -385,151 +392,202 @@ struct FAdjFace {
     rec[FS_GPY * fpl] = fb.gpy;
     rec[FS_GX * fpl] = gxb;
     rec[FS_GY * fpl] = gyb;
-#undef CX
-#undef CY
   }
 };
 
-// Contribution of one face record of axis A to the adjoint of the cell that
-// lies on side s (0: low side L, 1: high side R) of face k.  Reverse of the
-// face reconstruction of bar (eq. original-function with the central face
-// operator, or the one-sided wall expansion) and of the face fields.
-template <int A>
-DFN void gather_face(const Consts &K, const double *rec, i64 fpl, int k, int s, double ab[18],
-                     double gb[2][18], double fv[12]) {
-  const Axis &ax = K.ax[A];
-  const int TA = 1 - A;
-  const bool wall = ax.fl[k] < 0 || ax.fr[k] < 0;
-  const double h = K.h;
+// Geometry of one face of axis A as seen from the cell on side s (0: low
+// side L, 1: high side R): reverse of the face reconstruction of bar (eq.
+// original-function with the central face operator, or the one-sided wall
+// expansion) and of the face fields.
+struct FaceSide {
+  bool wall;
   double wgt, sg, off;
-  if (wall) {
-    wgt = 1.0;
-    sg = 0.0;
-    off = ax.fl[k] < 0 ? ax.foffr[k] : ax.foffl[k];
+};
+
+template <int A>
+DFN FaceSide face_side(const Consts &K, int k, int s) {
+  const Axis &ax = K.ax[A];
+  FaceSide f;
+  f.wall = ax.fl[k] < 0 || ax.fr[k] < 0;
+  if (f.wall) {
+    f.wgt = 1.0;
+    f.sg = 0.0;
+    f.off = ax.fl[k] < 0 ? ax.foffr[k] : ax.foffl[k];
   } else {
-    wgt = s == 0 ? ax.fwl[k] : ax.fwr[k];
-    sg = (s == 0 ? -1.0 : 1.0) * ax.finv[k];
-    off = 0.0;
+    f.wgt = s == 0 ? ax.fwl[k] : ax.fwr[k];
+    f.sg = (s == 0 ? -1.0 : 1.0) * ax.finv[k];
+    f.off = 0.0;
   }
-  for (int q = 0; q < 18; ++q) {
-    const int i = q % 9;
-    const double bb = rec[(FS_B + q) * fpl];
-    const double xn = A == 0 ? K.xi0[i] : K.xi1[i], xt = A == 0 ? K.xi1[i] : K.xi0[i];
-    if (wall) {
-      // bar = A + off Gn - h (xn Gn + xt Gt)
-      ab[q] += bb;
-      gb[A][q] += (off - h * xn) * bb;
-      gb[TA][q] += -h * xt * bb;
-    } else {
-      // bar = wl AL + wr AR - h (xn (AR - AL) inv + xt (wl GtL + wr GtR))
-      ab[q] += wgt * bb + sg * (-h * xn * bb);
-      gb[TA][q] += wgt * (-h * xt * bb);
-    }
+  return f;
+}
+
+// Contribution of a face's bar adjoint (population q) to the cell's bar+
+// adjoint ab and to the adjoints of its population gradients g[0], g[1].
+template <int A>
+DFN void face_pop_back(const Consts &K, const FaceSide &f, int q, double bb, double &ab,
+                       double g[2]) {
+  const int i = q % 9;
+  const double xn = A == 0 ? K.xi0[i] : K.xi1[i], xt = A == 0 ? K.xi1[i] : K.xi0[i];
+  const double h = K.h;
+  if (f.wall) {
+    // bar = A + off Gn - h (xn Gn + xt Gt)
+    ab += bb;
+    g[A] += (f.off - h * xn) * bb;
+    g[1 - A] += -h * xt * bb;
+  } else {
+    // bar = wl AL + wr AR - h (xn (AR - AL) inv + xt (wl GtL + wr GtR))
+    ab += f.wgt * bb + f.sg * (-h * xn * bb);
+    g[1 - A] += f.wgt * (-h * xt * bb);
   }
+}
+
+// Contribution of a face's field adjoints to the cell fields
+// fv = (mu, D, phi, p, dmu x/y, dphi x/y, dp x/y, gx, gy partials).
+template <int A>
+DFN void face_field_back(const FaceSide &f, int s, const double *rec, i64 fpl, double fv[12]) {
+  const int TA = 1 - A;
   const double mub = rec[FS_MU * fpl], Db = rec[FS_D * fpl];
-  const double mun = rec[(A == 0 ? FS_GMX : FS_GMY) * fpl], mut = rec[(A == 0 ? FS_GMY : FS_GMX) * fpl];
-  const double phn = rec[(A == 0 ? FS_GFX : FS_GFY) * fpl], pht = rec[(A == 0 ? FS_GFY : FS_GFX) * fpl];
-  const double pn = rec[(A == 0 ? FS_GPX : FS_GPY) * fpl], pt = rec[(A == 0 ? FS_GPY : FS_GPX) * fpl];
-  // fv: mu, D, phi, p, dmu[2], dphi[2], dp[2]
-  fv[0] += wgt * mub + sg * mun;
-  fv[1] += wgt * Db;
-  fv[2] += sg * phn;
-  fv[3] += sg * pn;
-  fv[4 + TA] += wgt * mut;
-  fv[6 + TA] += wgt * pht;
-  fv[8 + TA] += wgt * pt;
-  // the face's body-force partials are counted once, on side L (or the fluid side)
-  if (wall || s == 0) {
+  const double mun = rec[(A == 0 ? FS_GMX : FS_GMY) * fpl];
+  const double mut = rec[(A == 0 ? FS_GMY : FS_GMX) * fpl];
+  const double phn = rec[(A == 0 ? FS_GFX : FS_GFY) * fpl];
+  const double pht = rec[(A == 0 ? FS_GFY : FS_GFX) * fpl];
+  const double pn = rec[(A == 0 ? FS_GPX : FS_GPY) * fpl];
+  const double pt = rec[(A == 0 ? FS_GPY : FS_GPX) * fpl];
+  fv[0] += f.wgt * mub + f.sg * mun;
+  fv[1] += f.wgt * Db;
+  fv[2] += f.sg * phn;
+  fv[3] += f.sg * pn;
+  fv[4 + TA] += f.wgt * mut;
+  fv[6 + TA] += f.wgt * pht;
+  fv[8 + TA] += f.wgt * pt;
+  // a face's body-force partials are counted once: on side L, or the fluid side
+  if (f.wall || s == 0) {
     fv[10] += rec[FS_GX * fpl];
     fv[11] += rec[FS_GY * fpl];
   }
 }
 
-// Gather: a cell is side R of its W and S faces and side L of its E and N
-// faces (a wall face has only the fluid side).
+// Faces of cell (i, j): it is side R of its W and S faces and side L of its
+// E and N faces (a wall face has only the fluid side).
+struct CellFaces {
+  int iw, ie, js, jn;
+  i64 fw, fe, fs, fn;
+};
+
+DFN CellFaces cell_faces(const Consts &K, int i, int j) {
+  CellFaces f;
+  f.iw = i;
+  f.ie = (K.ax[0].bc == 0 && i == K.nx - 1) ? 0 : i + 1;
+  f.js = j;
+  f.jn = (K.ax[1].bc == 0 && j == K.ny - 1) ? 0 : j + 1;
+  f.fw = (i64)j * K.nfx + f.iw;
+  f.fe = (i64)j * K.nfx + f.ie;
+  f.fs = (i64)f.js * K.ld + i;
+  f.fn = (i64)f.jn * K.ld + i;
+  return f;
+}
+
+// Gather of the bar adjoints of a cell's four faces: the adjoint of bar+ at
+// the cell (including the 4/3 bar+ of tilde+, eq. relations2) and of its
+// population gradients.
 struct FAdjGather {
   Consts K;
   AdjWork a;
   DFN void operator()(int i, int j) const {
     const i64 c = (i64)j * K.ld + i, P = K.plane;
-    const int ie = (K.ax[0].bc == 0 && i == K.nx - 1) ? 0 : i + 1;
-    const int jn = (K.ax[1].bc == 0 && j == K.ny - 1) ? 0 : j + 1;
-    double ab[18], gb[2][18], fv[12];
+    const CellFaces F = cell_faces(K, i, j);
+    const FaceSide sw = face_side<0>(K, F.iw, 1), se = face_side<0>(K, F.ie, 0);
+    const FaceSide ss = face_side<1>(K, F.js, 1), sn = face_side<1>(K, F.jn, 0);
+#pragma unroll
     for (int q = 0; q < 18; ++q) {
-      ab[q] = (4.0 / 3.0) * a.lam[q * P + c];
-      gb[0][q] = gb[1][q] = 0.0;
+      double ab = (4.0 / 3.0) * a.lam[q * P + c];
+      double g[2] = {0.0, 0.0};
+      face_pop_back<0>(K, sw, q, a.xs[(FS_B + q) * K.xplane + F.fw], ab, g);
+      face_pop_back<0>(K, se, q, a.xs[(FS_B + q) * K.xplane + F.fe], ab, g);
+      face_pop_back<1>(K, ss, q, a.ys[(FS_B + q) * K.yplane + F.fs], ab, g);
+      face_pop_back<1>(K, sn, q, a.ys[(FS_B + q) * K.yplane + F.fn], ab, g);
+      a.ab[q * P + c] = ab;
+      a.gxb[q * P + c] = g[0];
+      a.gyb[q * P + c] = g[1];
     }
-    for (int e = 0; e < 12; ++e) fv[e] = 0.0;
-    gather_face<0>(K, a.xs + (i64)j * K.nfx + i, K.xplane, i, 1, ab, gb, fv);
-    gather_face<0>(K, a.xs + (i64)j * K.nfx + ie, K.xplane, ie, 0, ab, gb, fv);
-    gather_face<1>(K, a.ys + (i64)j * K.ld + i, K.yplane, j, 1, ab, gb, fv);
-    gather_face<1>(K, a.ys + (i64)jn * K.ld + i, K.yplane, jn, 0, ab, gb, fv);
-    for (int q = 0; q < 18; ++q) {
-      a.ab[q * P + c] = ab[q];
-      a.gxb[q * P + c] = gb[0][q];
-      a.gyb[q * P + c] = gb[1][q];
-    }
-    double *fb = a.fb;
-    for (int f = 0; f < NFB; ++f) fb[f * P + c] = 0.0;
-    fb[FB_MU * P + c] = fv[0];
-    fb[FB_D * P + c] = fv[1];
-    fb[FB_PHI * P + c] = fv[2];
-    fb[FB_P * P + c] = fv[3];
-    fb[FB_DMUX * P + c] = fv[4];
-    fb[FB_DMUY * P + c] = fv[5];
-    fb[FB_DPHX * P + c] = fv[6];
-    fb[FB_DPHY * P + c] = fv[7];
-    fb[FB_DPX * P + c] = fv[8];
-    fb[FB_DPY * P + c] = fv[9];
-    fb[FB_GX * P + c] = fv[10];
-    fb[FB_GY * P + c] = fv[11];
   }
 };
 
-// Adjoint of the population gradients and of Step 2 at a cell.
+// Adjoint of the population gradients and of Step 2 at a cell (eqs.
+// relations1 and relations2), one direction at a time, plus the face-field
+// adjoints of the cell's faces; writes the adjoint of tilde (before the
+// macro part) and the cell-field adjoints.
 struct FAdjCell {
   Consts K;
   Work w;
   AdjWork a;
   const double *st;  // state before the step (FP64)
   DFN void operator()(int i, int j) const {
-    const i64 c = (i64)j * K.ld + i;
-    double ob[18], til[18], tilb[18];
-    for (int q = 0; q < 18; ++q) {
-      ob[q] = a.ab[q * K.plane + c] + stencil_T(K, 0, K.ax[0].pg, a.gxb + q * K.plane, i, j) +
-              stencil_T(K, 1, K.ax[1].pg, a.gyb + q * K.plane, i, j);
-      til[q] = st[q * K.plane + c];
-    }
+    const i64 c = (i64)j * K.ld + i, P = K.plane;
+    const TW tx = stencil_tw(K, 0, K.ax[0].pg, i, j), ty = stencil_tw(K, 1, K.ax[1].pg, i, j);
     Mac<double> m, mb;
     cell_mac(K, w, c, m);
     mac_zero(mb);
     const double tf = w.tauf[c];
-    double tfb = 0.0;
-    cell_barp_vjp(K, m, tf, til, ob, tilb, mb, tfb);
-    // tilde+ = 4/3 bar+ - 1/3 tilde: the 4/3 part is in ab; here -1/3
-    for (int q = 0; q < 18; ++q) a.out[q * K.plane + c] = tilb[q] - (1.0 / 3.0) * a.lam[q * K.plane + c];
+    const double uu = m.ux * m.ux + m.uy * m.uy;
+    const double den = 1.0 / (2.0 * tf + K.dt);
+    const double fca = (2.0 * tf - K.h) * den, fcb = 3.0 * K.h * den, fcc = 3.0 * tf * K.h * den;
+    double fcab = 0.0, fcbb = 0.0, fccb = 0.0, uub = 0.0;
+#pragma unroll 1
+    for (int i2 = 0; i2 < 9; ++i2) {
+      const int qf = i2, qg = 9 + i2;
+      double feq, geq, ff, fg;
+      point_eq1<double>(K, m, uu, i2, feq, geq, ff, fg);
+      const double obf = a.ab[qf * P + c] + tw_apply(tx, a.gxb + qf * P) + tw_apply(ty, a.gyb + qf * P);
+      const double obg = a.ab[qg * P + c] + tw_apply(tx, a.gxb + qg * P) + tw_apply(ty, a.gyb + qg * P);
+      // tilde+ = 4/3 bar+ - 1/3 tilde: the 4/3 part is in ab
+      a.out[qf * P + c] = fca * obf - (1.0 / 3.0) * a.lam[qf * P + c];
+      a.out[qg * P + c] = K.gca * obg - (1.0 / 3.0) * a.lam[qg * P + c];
+      fcab += st[qf * P + c] * obf;
+      fcbb += feq * obf;
+      fccb += ff * obf;
+      point_eq1_vjp(K, m, uu, i2, fcb * obf, K.gcb * obg, fcc * obf, K.gcc * obg, mb, uub);
+    }
+    mb.ux += 2.0 * m.ux * uub;
+    mb.uy += 2.0 * m.uy * uub;
+    // fca = (2 tf - h) den, fcb = 3 h den, fcc = 3 tf h den, den = 1/(2 tf + dt)
+    const double denb = (2.0 * tf - K.h) * fcab + 3.0 * K.h * fcbb + 3.0 * tf * K.h * fccb;
+    const double tfb = 2.0 * den * fcab + 3.0 * K.h * den * fccb - 2.0 * den * den * denb;
     double dtp, dtr;
     tauf_grad(K, m.phi, m.rho, dtp, dtr);
+    // face-field adjoints of the four faces
+    const CellFaces F = cell_faces(K, i, j);
+    double fv[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) fv[e] = 0.0;
+    face_field_back<0>(face_side<0>(K, F.iw, 1), 1, a.xs + F.fw, K.xplane, fv);
+    face_field_back<0>(face_side<0>(K, F.ie, 0), 0, a.xs + F.fe, K.xplane, fv);
+    face_field_back<1>(face_side<1>(K, F.js, 1), 1, a.ys + F.fs, K.yplane, fv);
+    face_field_back<1>(face_side<1>(K, F.jn, 0), 0, a.ys + F.fn, K.yplane, fv);
     double *fb = a.fb;
-    const i64 P = K.plane;
-    fb[FB_PHI * P + c] += mb.phi + dtp * tfb;
-    fb[FB_RHO * P + c] += mb.rho + dtr * tfb - K.cs2 * m.icr * m.icr * mb.icr;
-    fb[FB_UX * P + c] += mb.ux;
-    fb[FB_UY * P + c] += mb.uy;
-    fb[FB_P * P + c] += mb.p;
-    fb[FB_MU * P + c] += mb.mu;
-    fb[FB_DPHX * P + c] += K.drho * mb.grx;
-    fb[FB_DPHY * P + c] += K.drho * mb.gry;
-    fb[FB_D * P + c] += mb.D;
-    fb[FB_FX * P + c] += mb.Fx;
-    fb[FB_FY * P + c] += mb.Fy;
-    fb[FB_DPX * P + c] += mb.gpx;
-    fb[FB_DPY * P + c] += mb.gpy;
+    fb[FB_MU * P + c] = fv[0] + mb.mu;
+    fb[FB_D * P + c] = fv[1] + mb.D;
+    fb[FB_PHI * P + c] = fv[2] + (mb.phi + dtp * tfb);
+    fb[FB_P * P + c] = fv[3] + mb.p;
+    fb[FB_DMUX * P + c] = fv[4];
+    fb[FB_DMUY * P + c] = fv[5];
+    fb[FB_DPHX * P + c] = fv[6] + K.drho * mb.grx;
+    fb[FB_DPHY * P + c] = fv[7] + K.drho * mb.gry;
+    fb[FB_DPX * P + c] = fv[8] + mb.gpx;
+    fb[FB_DPY * P + c] = fv[9] + mb.gpy;
+    fb[FB_GX * P + c] = fv[10];
+    fb[FB_GY * P + c] = fv[11];
+    fb[FB_RHO * P + c] = mb.rho + dtr * tfb - K.cs2 * m.icr * m.icr * mb.icr;
+    fb[FB_UX * P + c] = mb.ux;
+    fb[FB_UY * P + c] = mb.uy;
+    fb[FB_FX * P + c] = mb.Fx;
+    fb[FB_FY * P + c] = mb.Fy;
   }
 };
 
-// Adjoint of the cell macros (eqs. u, P; F; D): p adjoint completed by the
-// transpose of its gradient stencil.  init = 1: Step 1 form (u, p given).
+// Adjoint of the cell macros (eqs. u, P; F; D): the p adjoint is completed
+// by the transpose of its gradient stencil.  init = 1: Step 1 form (u, p
+// given, not differentiated).
 struct FAdjMacro {
   Consts K;
   Work w;
@@ -543,27 +601,25 @@ struct FAdjMacro {
     double Fxb = fb[FB_FX * P + c], Fyb = fb[FB_FY * P + c], Db = fb[FB_D * P + c];
     double rhob = 0.0, phib = 0.0;
     if (!init) {
-      const double pb = fb[FB_P * P + c] + stencil_T(K, 0, K.ax[0].d1, fb + FB_DPX * P, i, j) +
-                        stencil_T(K, 1, K.ax[1].d1, fb + FB_DPY * P, i, j);
+      const TW tx = stencil_tw(K, 0, K.ax[0].d1, i, j), ty = stencil_tw(K, 1, K.ax[1].d1, i, j);
+      const double pb = fb[FB_P * P + c] + tw_apply(tx, fb + FB_DPX * P) +
+                        tw_apply(ty, fb + FB_DPY * P);
       const double ux = w.ux[c], uy = w.uy[c];
       const double grx = K.drho * w.dphx[c], gry = K.drho * w.dphy[c];
-      double uxb = fb[FB_UX * P + c] + K.hdtcs2 * grx * pb;
-      double uyb = fb[FB_UY * P + c] + K.hdtcs2 * gry * pb;
+      const double uxb = fb[FB_UX * P + c] + K.hdtcs2 * grx * pb;
+      const double uyb = fb[FB_UY * P + c] + K.hdtcs2 * gry * pb;
       fb[FB_DPHX * P + c] += K.drho * K.hdtcs2 * ux * pb;
       fb[FB_DPHY * P + c] += K.drho * K.hdtcs2 * uy * pb;
       rhob += -K.hdtcs2 * K.gam * D * pb;
       Db += -K.hdtcs2 * K.gam * rh * pb;
       fb[FB_S0 * P + c] = pb;
       const double icr = 1.0 / (K.cs2 * rh);
-      const double Fx = -ph * dmux + (rh - K.rho_ref) * K.gx;
-      const double Fy = -ph * dmuy + (rh - K.rho_ref) * K.gy;
-      // recover jx, jy from u: jx = ux / icr - hdtcs2 Fx
-      const double jx = ux * (K.cs2 * rh) - K.hdtcs2 * Fx, jy = uy * (K.cs2 * rh) - K.hdtcs2 * Fy;
       fb[FB_JX * P + c] = icr * uxb;
       fb[FB_JY * P + c] = icr * uyb;
       Fxb += K.hdtcs2 * icr * uxb;
       Fyb += K.hdtcs2 * icr * uyb;
-      const double icrb = (jx + K.hdtcs2 * Fx) * uxb + (jy + K.hdtcs2 * Fy) * uyb;
+      // u = (j + hdtcs2 F) icr, so j + hdtcs2 F = u / icr = u cs2 rho
+      const double icrb = ux * (K.cs2 * rh) * uxb + uy * (K.cs2 * rh) * uyb;
       rhob += -K.cs2 * icr * icr * icrb;
     } else {
       fb[FB_S0 * P + c] = fb[FB_JX * P + c] = fb[FB_JY * P + c] = 0.0;
@@ -582,8 +638,8 @@ struct FAdjMacro {
   }
 };
 
-// Adjoint of eq. chemicalpotential: mu adjoint completed by the transposes
-// of grad mu and lap mu; kappa partial.
+// Adjoint of eq. chemicalpotential: the mu adjoint is completed by the
+// transposes of grad mu and lap mu; kappa partial (beta fixed).
 struct FAdjMu {
   Consts K;
   Work w;
@@ -591,10 +647,11 @@ struct FAdjMu {
   DFN void operator()(int i, int j) const {
     const i64 c = (i64)j * K.ld + i, P = K.plane;
     double *fb = a.fb;
-    const double mub = fb[FB_MU * P + c] + stencil_T(K, 0, K.ax[0].d1, fb + FB_DMUX * P, i, j) +
-                       stencil_T(K, 1, K.ax[1].d1, fb + FB_DMUY * P, i, j) +
-                       stencil_T(K, 0, K.ax[0].d2, fb + FB_LAPMU * P, i, j) +
-                       stencil_T(K, 1, K.ax[1].d2, fb + FB_LAPMU * P, i, j);
+    const TW t1x = stencil_tw(K, 0, K.ax[0].d1, i, j), t1y = stencil_tw(K, 1, K.ax[1].d1, i, j);
+    const TW t2x = stencil_tw(K, 0, K.ax[0].d2, i, j), t2y = stencil_tw(K, 1, K.ax[1].d2, i, j);
+    const double mub = fb[FB_MU * P + c] + tw_apply(t1x, fb + FB_DMUX * P) +
+                       tw_apply(t1y, fb + FB_DMUY * P) + tw_apply(t2x, fb + FB_LAPMU * P) +
+                       tw_apply(t2y, fb + FB_LAPMU * P);
     const double ph = w.phi[c];
     const double a1 = ph - K.phi_a, b1 = ph - K.phi_b, m1 = ph - K.phimid;
     const double lap = stx(K, K.ax[0].d2, w.phi, i, j) + sty(K, K.ax[1].d2, w.phi, i, j);
@@ -605,7 +662,9 @@ struct FAdjMu {
 };
 
 // Adjoint of eq. phi and eq. oderrho with the transposes of grad phi and
-// lap phi.  Writes the adjoint of the populations (step) or of phi0 (init).
+// lap phi.  Adds the adjoint of the populations through the cell sums (a
+// step) or writes the adjoint of phi0 (Step 1); accumulates the parameter
+// partials of the cell.
 struct FAdjPhi {
   Consts K;
   AdjWork a;
@@ -613,11 +672,11 @@ struct FAdjPhi {
   DFN void operator()(int i, int j) const {
     const i64 c = (i64)j * K.ld + i, P = K.plane;
     const double *fb = a.fb;
+    const TW t1x = stencil_tw(K, 0, K.ax[0].d1, i, j), t1y = stencil_tw(K, 1, K.ax[1].d1, i, j);
+    const TW t2x = stencil_tw(K, 0, K.ax[0].d2, i, j), t2y = stencil_tw(K, 1, K.ax[1].d2, i, j);
     const double phb = fb[FB_PHI * P + c] + K.drho * fb[FB_RHO * P + c] +
-                       stencil_T(K, 0, K.ax[0].d1, fb + FB_DPHX * P, i, j) +
-                       stencil_T(K, 1, K.ax[1].d1, fb + FB_DPHY * P, i, j) +
-                       stencil_T(K, 0, K.ax[0].d2, fb + FB_LAPPHI * P, i, j) +
-                       stencil_T(K, 1, K.ax[1].d2, fb + FB_LAPPHI * P, i, j);
+                       tw_apply(t1x, fb + FB_DPHX * P) + tw_apply(t1y, fb + FB_DPHY * P) +
+                       tw_apply(t2x, fb + FB_LAPPHI * P) + tw_apply(t2y, fb + FB_LAPPHI * P);
     a.pacc[c] += fb[FB_KAP * P + c];
     a.pacc[P + c] += fb[FB_GX * P + c];
     a.pacc[2 * P + c] += fb[FB_GY * P + c];
@@ -626,8 +685,9 @@ struct FAdjPhi {
       return;
     }
     const double s0b = fb[FB_S0 * P + c], jxb = fb[FB_JX * P + c], jyb = fb[FB_JY * P + c];
-    for (int q = 0; q < 9; ++q)
-      a.out[q * P + c] += s0b + K.xi0[q] * jxb + K.xi1[q] * jyb;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) a.out[q * P + c] += s0b + K.xi0[q] * jxb + K.xi1[q] * jyb;
+#pragma unroll
     for (int q = 9; q < 18; ++q) a.out[q * P + c] += phb;
   }
 };
@@ -699,14 +759,14 @@ inline void pack_rows(Consts &K) {
 // Per step of a segment the tape holds the 16 cell fields of the staged
 // step and bar+ (18 planes); the population state of every step but the
 // first is kept too.
-enum { TAPE_FIELDS = 16 };
+enum { TAPE_FIELDS = 16, ADJ_RED_BLOCKS = 256 };
 
 struct AdjLayout {
   size_t tables[2];
   size_t field_bytes;  // one cell plane, padded
   size_t slot_bytes;   // one tape slot: 16 fields + bar+
   size_t state_bytes;  // 18 planes
-  size_t states, tape, dummy, facex, facey, lam[2], xs, ys, ab, gxb, gyb, fb, pacc;
+  size_t states, tape, dummy, facex, facey, lam[2], xs, ys, ab, gxb, gyb, fb, pacc, red;
   size_t total;
   int mseg;
 };
@@ -752,6 +812,8 @@ inline AdjLayout make_adj_layout(const Consts &K, const AxisHost &ax, const Axis
   off += align256(NFB * sizeof(double) * P);
   L.pacc = off;
   off += align256(3 * sizeof(double) * P);
+  L.red = off;  // per-workgroup partial sums of the parameter reduction
+  off += align256(3 * sizeof(double) * ADJ_RED_BLOCKS);
   L.total = off;
   return L;
 }
