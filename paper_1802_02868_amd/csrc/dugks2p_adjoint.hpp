@@ -15,6 +15,7 @@
 // depend on thread scheduling.  CENTRAL reconstruction, phi_clamp off.
 #pragma once
 
+#include "dugks2p_fused.hpp"
 #include "dugks2p_host.hpp"
 
 namespace dg {
@@ -138,14 +139,14 @@ struct TW {
 DFN TW stencil_tw(const Consts &K, int ax, const double *wt3, int i, int j) {
   const Axis &X = K.ax[ax];
   const int c = ax == 0 ? i : j;
-  const int cand[3] = {X.lo[c], c, X.hi[c]};
+  const int cand[3] = {ax_lo(X, c), c, ax_hi(X, c)};
   TW t;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int cp = cand[a];
     bool dup = false;
     for (int b = 0; b < a; ++b) dup |= cand[b] == cp;
-    const int tgt[3] = {X.lo[cp], cp, X.hi[cp]};
+    const int tgt[3] = {ax_lo(X, cp), cp, ax_hi(X, cp)};
     const double *w = wt3 + 3 * cp;
     double s = 0.0;
     if (!dup)
@@ -276,7 +277,7 @@ struct FAdjFace {
   DFN void operator()(int p0, int p1) const {
     const int k = A == 0 ? p0 : p1, t = A == 0 ? p1 : p0;
     const Axis &ax = K.ax[A];
-    const int cl = ax.fl[k], cr = ax.fr[k];
+    const int cl = ax_fl(ax, k), cr = ax_fr(ax, k);
     const GAcc acc{&K, &w};
     const int TA = 1 - A;
     const i64 fpl = A == 0 ? K.xplane : K.yplane;
@@ -408,11 +409,11 @@ template <int A>
 DFN FaceSide face_side(const Consts &K, int k, int s) {
   const Axis &ax = K.ax[A];
   FaceSide f;
-  f.wall = ax.fl[k] < 0 || ax.fr[k] < 0;
+  f.wall = ax_fl(ax, k) < 0 || ax_fr(ax, k) < 0;
   if (f.wall) {
     f.wgt = 1.0;
     f.sg = 0.0;
-    f.off = ax.fl[k] < 0 ? ax.foffr[k] : ax.foffl[k];
+    f.off = ax_fl(ax, k) < 0 ? ax.foffr[k] : ax.foffl[k];
   } else {
     f.wgt = s == 0 ? ax.fwl[k] : ax.fwr[k];
     f.sg = (s == 0 ? -1.0 : 1.0) * ax.finv[k];
@@ -766,7 +767,7 @@ struct AdjLayout {
   size_t field_bytes;  // one cell plane, padded
   size_t slot_bytes;   // one tape slot: 16 fields + bar+
   size_t state_bytes;  // 18 planes
-  size_t states, tape, dummy, facex, facey, lam[2], xs, ys, ab, gxb, gyb, fb, pacc, red;
+  size_t states, tape, dummy, facex, facey, fwork, lam[2], xs, ys, ab, gxb, gyb, fb, pacc, red;
   size_t total;
   int mseg;
 };
@@ -794,6 +795,8 @@ inline AdjLayout make_adj_layout(const Consts &K, const AxisHost &ax, const Axis
   off += align256(18 * sizeof(double) * (size_t)K.xplane);
   L.facey = off;
   off += align256(18 * sizeof(double) * (size_t)K.yplane);
+  L.fwork = off;  // cell fields of the fused step that advances the state
+  off += 19 * L.field_bytes;
   for (int b = 0; b < 2; ++b) {
     L.lam[b] = off;
     off += L.state_bytes;
@@ -836,6 +839,16 @@ struct AdjBufs {
     w.facey = (double *)(base + L.facey);
     return w;
   }
+  // work fields of the fused step (its own, so the tape is untouched)
+  Work fused_work() const {
+    Work w;
+    memset(&w, 0, sizeof w);
+    double **f[19] = {&w.phi, &w.rho, &w.mu, &w.dphx, &w.dphy, &w.dmux, &w.dmuy,
+                      &w.D,   &w.Fx,  &w.Fy, &w.ux,   &w.uy,   &w.p,    &w.dpx,
+                      &w.dpy, &w.tauf, &w.s0, &w.jx,  &w.jy};
+    for (int k = 0; k < 19; ++k) *f[k] = (double *)(base + L.fwork + k * L.field_bytes);
+    return w;
+  }
   double *lam(int b) const { return (double *)(base + L.lam[b]); }
   AdjWork adj(int in) const {
     AdjWork a;
@@ -874,14 +887,20 @@ void seq_adjoint_segment(Ex &ex, const Consts &K, const AdjBufs &B, const double
   const AdjWork a0 = B.adj(0);
   ex.grid(FCopyPlanes{K, nullptr, a0.pacc, 3}, K.nx, K.ny);
   ex.grid(FCopyPlanes{K, lam_end, B.lam(0), 18}, K.nx, K.ny);
+  const Work wf = B.fused_work();
   for (int n = 0; n < nsteps; ++n) {
     const Work w = B.tape(n);
     const double *src = n == 0 ? pops0 : B.state(n);
+    // the tape: cell fields and bar+ of the step (staged stages up to Step 2)
+    seq_staged_macros(ex, K, w, src);
+    ex.grid(FCell<double, double>{K, w, src}, K.nx, K.ny);
+    // the next state, from the fused step (bitwise equal to the staged one)
     if (n + 1 < nsteps) {
-      seq_staged_step(ex, K, w, src, B.state(n + 1));
-    } else {
-      seq_staged_macros(ex, K, w, src);
-      ex.grid(FCell<double, double>{K, w, src}, K.nx, K.ny);
+      const IoF64 a{(double *)src, K.plane}, b{B.state(n + 1), K.plane};
+      if (K.unit)
+        seq_fused_step<Ex, IoF64, double, true>(ex, K, wf, a, b);
+      else
+        seq_fused_step<Ex, IoF64, double, false>(ex, K, wf, a, b);
     }
   }
   int cur = 0;

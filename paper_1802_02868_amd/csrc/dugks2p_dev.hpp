@@ -62,6 +62,35 @@ struct Axis {
   const double *fwl, *fwr, *finv, *foffl, *foffr;
 };
 
+// Neighbours along an axis are topology only: cell k's stencil neighbours
+// are k -+ 1, wrapped on a periodic axis and the cell itself (standing for
+// its mirror ghost) at a wall; face k lies between cells k - 1 and k, with
+// -1 for the wall side.  These equal the tables lo, hi, fl, fr.
+DFN int ax_lo(const Axis &a, int k) { return k > 0 ? k - 1 : (a.bc == 0 ? a.n - 1 : 0); }
+DFN int ax_hi(const Axis &a, int k) { return k < a.n - 1 ? k + 1 : (a.bc == 0 ? 0 : k); }
+DFN int ax_fl(const Axis &a, int k) { return (a.bc == 0 && k == 0) ? a.n - 1 : k - 1; }
+DFN int ax_fr(const Axis &a, int k) { return (a.bc != 0 && k == a.n) ? -1 : k; }
+
+// Geometry of face k of an axis: the cells on either side (-1 = wall), the
+// interpolation weights and inverse distance of the central face operator,
+// and the offsets from the two cell centres to the face.
+struct FaceGeo {
+  int cl, cr;
+  double wl, wr, inv, offl, offr;
+};
+
+DFN FaceGeo face_geo(const Axis &a, int k) {
+  FaceGeo g;
+  g.cl = ax_fl(a, k);
+  g.cr = ax_fr(a, k);
+  g.wl = a.fwl[k];
+  g.wr = a.fwr[k];
+  g.inv = a.finv[k];
+  g.offl = a.foffl[k];
+  g.offr = a.foffr[k];
+  return g;
+}
+
 struct Consts {
   int nx, ny, ld, nfx, nfy, recon, phi_clamp, unit;  // unit: c = sqrt(3 RT) == 1
   i64 plane;   // ny * ld: stride between populations / fields
@@ -142,13 +171,13 @@ DFN double stx(const Consts &K, const double *w3, const double *F, int i, int j)
   const Axis &a = K.ax[0];
   const double *w = w3 + 3 * i;
   const i64 r = (i64)j * K.ld;
-  return w[0] * F[r + a.lo[i]] + w[1] * F[r + i] + w[2] * F[r + a.hi[i]];
+  return w[0] * F[r + ax_lo(a, i)] + w[1] * F[r + i] + w[2] * F[r + ax_hi(a, i)];
 }
 DFN double sty(const Consts &K, const double *w3, const double *F, int i, int j) {
   const Axis &a = K.ax[1];
   const double *w = w3 + 3 * j;
-  return w[0] * F[(i64)a.lo[j] * K.ld + i] + w[1] * F[(i64)j * K.ld + i] +
-         w[2] * F[(i64)a.hi[j] * K.ld + i];
+  return w[0] * F[(i64)ax_lo(a, j) * K.ld + i] + w[1] * F[(i64)j * K.ld + i] +
+         w[2] * F[(i64)ax_hi(a, j) * K.ld + i];
 }
 
 // Scratch fields of the staged step (all FP64, pitch ld, stride plane).
@@ -430,8 +459,8 @@ DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R 
 // fields mu, D, phi, p and their derivatives dmu, dphi, dp along an axis.
 template <int A, class R, class Acc, bool U = false>
 DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
-  const Axis &ax = K.ax[A];
-  const int cl = ax.fl[k], cr = ax.fr[k];
+  const FaceGeo fg = acc.geo(A, k);
+  const int cl = fg.cl, cr = fg.cr;
   const R h = (R)K.h;
   const int TA = 1 - A;  // tangential axis
   R bar[18];
@@ -441,7 +470,7 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
   if (cl < 0 || cr < 0) {
     // wall face: expand from the fluid cell C; bounce-back of entering ones
     const int cc = cl < 0 ? cr : cl;
-    const double off = cl < 0 ? ax.foffr[k] : ax.foffl[k];
+    const double off = cl < 0 ? fg.offr : fg.offl;
     const int nout = cl < 0 ? -1 : 1;
     const typename Acc::H HC = acc.cell(CX(cc), CY(cc));
 #pragma unroll
@@ -482,9 +511,9 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
   }
   const typename Acc::H HL = acc.cell(CX(cl), CY(cl)), HR = acc.cell(CX(cr), CY(cr));
   FaceW fw;
-  fw.wl = ax.fwl[k];
-  fw.wr = ax.fwr[k];
-  fw.inv = ax.finv[k];
+  fw.wl = fg.wl;
+  fw.wr = fg.wr;
+  fw.inv = fg.inv;
 #pragma unroll
   for (int q = 0; q < 18; ++q) {
     const int i = q % 9;
@@ -494,13 +523,13 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
     if (K.recon == 1 && en > 0) {
       const R gx = (R)acc.pgrad(0, q, HL), gy = (R)acc.pgrad(1, q, HL);
       const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
-      val = AL + (R)ax.foffl[k] * Gn;
+      val = AL + (R)fg.offl * Gn;
       sn = Gn;
       st = Gt;
     } else if (K.recon == 1 && en < 0) {
       const R gx = (R)acc.pgrad(0, q, HR), gy = (R)acc.pgrad(1, q, HR);
       const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
-      val = AR + (R)ax.foffr[k] * Gn;
+      val = AR + (R)fg.offr * Gn;
       sn = Gn;
       st = Gt;
     } else {
@@ -545,12 +574,13 @@ struct GAcc {
     h.x = x;
     h.y = y;
     h.c = (i64)y * K->ld + x;
-    h.lo[0] = (i64)y * K->ld + K->ax[0].lo[x];
-    h.hi[0] = (i64)y * K->ld + K->ax[0].hi[x];
-    h.lo[1] = (i64)K->ax[1].lo[y] * K->ld + x;
-    h.hi[1] = (i64)K->ax[1].hi[y] * K->ld + x;
+    h.lo[0] = (i64)y * K->ld + ax_lo(K->ax[0], x);
+    h.hi[0] = (i64)y * K->ld + ax_hi(K->ax[0], x);
+    h.lo[1] = (i64)ax_lo(K->ax[1], y) * K->ld + x;
+    h.hi[1] = (i64)ax_hi(K->ax[1], y) * K->ld + x;
     return h;
   }
+  DFN FaceGeo geo(int a, int k) const { return face_geo(K->ax[a], k); }
   DFN double A(int q, const H &h) const { return w->barp[q * K->plane + h.c]; }
   DFN double pgrad(int a, int q, const H &h) const {
     const double *wt = K->ax[a].pg + 3 * (a == 0 ? h.x : h.y);

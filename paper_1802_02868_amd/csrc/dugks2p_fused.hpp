@@ -54,8 +54,8 @@ DFN void macros_at(const Consts &K, const Work &w, int i, int j) {
   const i64 c = (i64)j * K.ld + i;
   const Axis &X = K.ax[0], &Y = K.ax[1];
   const double mc = mu_at(K, w.phi, i, j);
-  const double mxl = mu_at(K, w.phi, X.lo[i], j), mxh = mu_at(K, w.phi, X.hi[i], j);
-  const double myl = mu_at(K, w.phi, i, Y.lo[j]), myh = mu_at(K, w.phi, i, Y.hi[j]);
+  const double mxl = mu_at(K, w.phi, ax_lo(X, i), j), mxh = mu_at(K, w.phi, ax_hi(X, i), j);
+  const double myl = mu_at(K, w.phi, i, ax_lo(Y, j)), myh = mu_at(K, w.phi, i, ax_hi(Y, j));
   const double *a1 = X.d1 + 3 * i, *a2 = X.d2 + 3 * i, *b1 = Y.d1 + 3 * j, *b2 = Y.d2 + 3 * j;
   const double dmux = a1[0] * mxl + a1[1] * mc + a1[2] * mxh;
   const double dmuy = b1[0] * myl + b1[1] * mc + b1[2] * myh;
@@ -97,6 +97,11 @@ struct TileLds {
     } f;
   } u;
   double phi[W2][W2], mu[W2][W2], p[W2][W2];
+  // App. B weights (population gradient, first derivative) of the tile's
+  // columns (axis 0) and rows (axis 1) at the scalar-window positions, and
+  // the geometry of the tile's faces (local face 0..TT along each axis)
+  double pgw[2][W2][3], d1w[2][W2][3];
+  double fwl[2][TT + 1], fwr[2][TT + 1], finv[2][TT + 1], foffl[2][TT + 1], foffr[2][TT + 1];
 };
 
 // Accessor of the face code over the tile's LDS (bar+, phi, mu, p) and the
@@ -113,54 +118,113 @@ struct LAcc {
     int x, y;
     int o1, lo1[2], hi1[2];  // offsets in the bar+ window (W1 x W1)
     int o2, lo2[2], hi2[2];  // offsets in the scalar window (W2 x W2)
+    int w2[2];               // scalar-window column and row (weight tables)
   };
   DFN int win(int g, int o, int n, int wd) const {
     int d = g - o;
     if (d < 0) d += n;
     else if (d >= wd) d -= n;
 #ifdef DUGKS2P_WINDOW_CHECK
-    if (d < 0 || d >= wd) __builtin_trap();
+    // outside the window: a poisoned offset, trapped only where it is read
+    // (ring cells carry unread offsets of their outer neighbours)
+    if (d < 0 || d >= wd) return -(1 << 20);
 #endif
     return d;
   }
+  // a neighbour's window position, poisoned (under the window check) if it
+  // falls outside the window
+  DFN static int nbw(int p, int wd) {
+#ifdef DUGKS2P_WINDOW_CHECK
+    if (p < 0 || p >= wd) return -(1 << 20);
+#else
+    (void)wd;
+#endif
+    return p;
+  }
+  // The neighbours of a cell sit at the adjacent window positions (on a
+  // periodic axis these hold the wrapped images), or at the cell itself
+  // across a wall (mirror ghost).  The scalar window is the bar+ window
+  // shifted by one, so position p there holds the same cell as p - 1 here.
   DFN H cell(int x, int y) const {
     const Axis &X = K->ax[0], &Y = K->ax[1];
     H h;
     h.x = x;
     h.y = y;
-    const int ax1 = win(x, x0 - 1, K->nx, W1), ay1 = win(y, y0 - 1, K->ny, W1);
-    const int lx1 = win(X.lo[x], x0 - 1, K->nx, W1), hx1 = win(X.hi[x], x0 - 1, K->nx, W1);
-    const int ly1 = win(Y.lo[y], y0 - 1, K->ny, W1), hy1 = win(Y.hi[y], y0 - 1, K->ny, W1);
-    h.o1 = ay1 * W1 + ax1;
-    h.lo1[0] = ay1 * W1 + lx1;
-    h.hi1[0] = ay1 * W1 + hx1;
-    h.lo1[1] = ly1 * W1 + ax1;
-    h.hi1[1] = hy1 * W1 + ax1;
-    const int ax2 = win(x, x0 - 2, K->nx, W2);
-    const int ay2 = win(y, y0 - 2, K->ny, W2);
-    const int lx2 = win(X.lo[x], x0 - 2, K->nx, W2), hx2 = win(X.hi[x], x0 - 2, K->nx, W2);
-    const int ly2 = win(Y.lo[y], y0 - 2, K->ny, W2), hy2 = win(Y.hi[y], y0 - 2, K->ny, W2);
-    h.o2 = ay2 * W2 + ax2;
-    h.lo2[0] = ay2 * W2 + lx2;
-    h.hi2[0] = ay2 * W2 + hx2;
-    h.lo2[1] = ly2 * W2 + ax2;
-    h.hi2[1] = hy2 * W2 + ax2;
+    const int px = win(x, x0 - 1, K->nx, W1), py = win(y, y0 - 1, K->ny, W1);
+    const int sxl = (X.bc != 0 && x == 0) ? 0 : 1, sxh = (X.bc != 0 && x == X.n - 1) ? 0 : 1;
+    const int syl = (Y.bc != 0 && y == 0) ? 0 : 1, syh = (Y.bc != 0 && y == Y.n - 1) ? 0 : 1;
+    const int lx1 = nbw(px - sxl, W1), hx1 = nbw(px + sxh, W1);
+    const int ly1 = nbw(py - syl, W1), hy1 = nbw(py + syh, W1);
+    h.o1 = py * W1 + px;
+    h.lo1[0] = py * W1 + lx1;
+    h.hi1[0] = py * W1 + hx1;
+    h.lo1[1] = ly1 * W1 + px;
+    h.hi1[1] = hy1 * W1 + px;
+    const int qx = px + 1, qy = py + 1;
+    h.w2[0] = qx;
+    h.w2[1] = qy;
+    h.o2 = qy * W2 + qx;
+    h.lo2[0] = qy * W2 + (qx - sxl);
+    h.hi2[0] = qy * W2 + (qx + sxh);
+    h.lo2[1] = (qy - syl) * W2 + qx;
+    h.hi2[1] = (qy + syh) * W2 + qx;
     return h;
   }
+  DFN static int chk(int off, int lim) {
+#ifdef DUGKS2P_WINDOW_CHECK
+    if (off < 0 || off >= lim) {
+      printf("window check: offset %d outside [0, %d)\n", off, lim);
+#if !defined(__HIP_DEVICE_COMPILE__)
+      fflush(stdout);
+#endif
+      __builtin_trap();
+    }
+#else
+    (void)lim;
+#endif
+    return off;
+  }
   DFN const double *Aq(int q) const { return &L->u.A[q][0][0]; }
-  DFN double A(int q, const H &h) const { return Aq(q)[h.o1]; }
+  DFN double A(int q, const H &h) const { return Aq(q)[chk(h.o1, W1 * W1)]; }
   DFN double pgrad(int a, int q, const H &h) const {
-    const double *wt = K->ax[a].pg + 3 * (a == 0 ? h.x : h.y);
+    const double *wt = L->pgw[a][chk(h.w2[a], W2)];
     const double *aq = Aq(q);
-    return wt[0] * aq[h.lo1[a]] + wt[1] * aq[h.o1] + wt[2] * aq[h.hi1[a]];
+    return wt[0] * aq[chk(h.lo1[a], W1 * W1)] + wt[1] * aq[chk(h.o1, W1 * W1)] +
+           wt[2] * aq[chk(h.hi1[a], W1 * W1)];
   }
   DFN double d1(int a, const H &h, const double *f) const {
-    const double *wt = K->ax[a].d1 + 3 * (a == 0 ? h.x : h.y);
-    return wt[0] * f[h.lo2[a]] + wt[1] * f[h.o2] + wt[2] * f[h.hi2[a]];
+    const double *wt = L->d1w[a][chk(h.w2[a], W2)];
+    return wt[0] * f[chk(h.lo2[a], W2 * W2)] + wt[1] * f[chk(h.o2, W2 * W2)] +
+           wt[2] * f[chk(h.hi2[a], W2 * W2)];
   }
-  DFN double mu(const H &h) const { return (&L->mu[0][0])[h.o2]; }
-  DFN double phi(const H &h) const { return (&L->phi[0][0])[h.o2]; }
-  DFN double p(const H &h) const { return (&L->p[0][0])[h.o2]; }
+  // face k of axis a (a face of this tile; a periodic axis passes the face
+  // at the far end as face 0)
+  DFN FaceGeo geo(int a, int k) const {
+    const Axis &X = K->ax[a];
+    int f = k - (a == 0 ? x0 : y0);
+    if (f < 0) f += X.n;
+#ifdef DUGKS2P_WINDOW_CHECK
+    if (f < 0 || f > TT) {
+      printf("face check: axis %d face %d local %d\n", a, k, f);
+#if !defined(__HIP_DEVICE_COMPILE__)
+      fflush(stdout);
+#endif
+      __builtin_trap();
+    }
+#endif
+    FaceGeo g;
+    g.cl = ax_fl(X, k);
+    g.cr = ax_fr(X, k);
+    g.wl = L->fwl[a][f];
+    g.wr = L->fwr[a][f];
+    g.inv = L->finv[a][f];
+    g.offl = L->foffl[a][f];
+    g.offr = L->foffr[a][f];
+    return g;
+  }
+  DFN double mu(const H &h) const { return (&L->mu[0][0])[chk(h.o2, W2 * W2)]; }
+  DFN double phi(const H &h) const { return (&L->phi[0][0])[chk(h.o2, W2 * W2)]; }
+  DFN double p(const H &h) const { return (&L->p[0][0])[chk(h.o2, W2 * W2)]; }
   DFN double D(const H &h) const { return w->D[(i64)h.y * K->ld + h.x]; }
   DFN double dmu(int a, const H &h) const { return d1(a, h, &L->mu[0][0]); }
   DFN double dphi(int a, const H &h) const { return d1(a, h, &L->phi[0][0]); }
@@ -204,6 +268,31 @@ struct FusedTile {
       L->phi[ly][lx] = w.phi[c];
       L->mu[ly][lx] = w.mu[c];
       L->p[ly][lx] = w.p[c];
+    }
+    // weight tables of the window's columns and rows
+    for (int e = tid; e < 2 * W2; e += NTHR) {
+      const int a = e / W2, pos = e % W2;
+      const Axis &X = K.ax[a];
+      const int g = gcol((a == 0 ? x0 : y0) - 2 + pos, X.n, X.bc);
+      if (g < 0) continue;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        L->pgw[a][pos][m] = X.pg[3 * g + m];
+        L->d1w[a][pos][m] = X.d1[3 * g + m];
+      }
+    }
+    // geometry of the tile's faces
+    for (int e = tid; e < 2 * (TT + 1); e += NTHR) {
+      const int a = e / (TT + 1), f = e % (TT + 1);
+      const Axis &X = K.ax[a];
+      int k = (a == 0 ? x0 : y0) + f;
+      if (X.bc == 0 && k == X.n) k = 0;
+      if (k >= X.nf) continue;
+      L->fwl[a][f] = X.fwl[k];
+      L->fwr[a][f] = X.fwr[k];
+      L->finv[a][f] = X.finv[k];
+      L->foffl[a][f] = X.foffl[k];
+      L->foffr[a][f] = X.foffr[k];
     }
   }
 
