@@ -30,6 +30,14 @@ FP64_VEC_PEAK_TF = 78.6    # MI355X FP64 vector
 FP32_VEC_PEAK_TF = 157.3
 
 
+# FP64 work of the fused FP64 step kernel per cell-update, from the
+# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters on the same workload
+# (profiles/fused_rt256x1024_fp64_valu.md); valid for the same sources.
+VALU = {"workload": "rt256x1024", "precision": "fp64", "src_sha": TRAFFIC["src_sha"],
+        "fp64_flop_per_cell": 2716.9}
+FP64_NOFMA_PEAK_TF = FP64_VEC_PEAK_TF / 2  # one add or multiply per instruction
+
+
 def kernel_src_sha():
     import hashlib
     d = os.path.join(ROOT, "paper_1802_02868_amd", "csrc")
@@ -227,8 +235,11 @@ def main():
     # populations read + written once: 18 doubles, or the 76-byte FP32 state
     bytes_per_cell = 288 if prec == D.FP64 else 152
     fused = sim.kernel_kind == D.KERNEL_FUSED
-    launches_per_step = 1 if fused else 7
-    achieved = bytes_per_cell * cells / (ms_per_step / 1e3) / 1e9
+    # the dominant kernel's own launch time: HIP events around the tile
+    # kernel on the handle's stream, over a second pass of the same steps
+    kms, klaunch = sim.time_kernel(args.steps) if fused else (0.0, 0)
+    kernel_ms = kms / klaunch if klaunch else ms_per_step
+    achieved = bytes_per_cell * cells / (kernel_ms / 1e3) / 1e9
     traffic = None
     if (fused and prec == D.FP64 and args.workload == TRAFFIC["workload"]
             and kernel_src_sha() == TRAFFIC["src_sha"]):
@@ -236,9 +247,23 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "traffic_unit": "bytes per launch (HBM, counters)",
-            "kernel": "dugks2p fused step" if fused else "staged step (7 kernels, summed)",
+            "kernel": "k_fused_tile (Steps 2-6)" if fused else "staged step (7 kernels, summed)",
+            "kernel_avg_us": round(kernel_ms * 1e3, 2),
+            "timed_launches": klaunch,
             "algorithmic_bytes_per_cell": bytes_per_cell,
-            "launches_per_step": launches_per_step}
+            "step_effective_gbs": round(bytes_per_cell * cells / (ms_per_step / 1e3) / 1e9, 1),
+            "launches_per_step": 3 if fused else 7}
+    if (VALU["fp64_flop_per_cell"] and fused and prec == D.FP64
+            and args.workload == VALU["workload"] and kernel_src_sha() == VALU["src_sha"]):
+        tf = VALU["fp64_flop_per_cell"] * cells / (kernel_ms / 1e3) / 1e12
+        roof_alu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VEC_PEAK_TF,
+                    "unit": "TFLOP/s", "frac": round(tf / FP64_VEC_PEAK_TF, 4),
+                    "peak_without_fma": FP64_NOFMA_PEAK_TF,
+                    "frac_without_fma": round(tf / FP64_NOFMA_PEAK_TF, 4),
+                    "flop_per_cell": VALU["fp64_flop_per_cell"],
+                    "source": "FP64 VALU instruction counters x 64 lanes"}
+    else:
+        roof_alu = None
     out = {
         "metric": "MLUPS (f+g D2Q9)",
         "value": round(mlups, 3),
@@ -256,6 +281,7 @@ def main():
             case.name, args.precision, case.nx, case.ny), "cells": cells,
             "kernel": args.kernel, "dt": sim.dt},
         "roofline": roof,
+        "roofline_alu": roof_alu,
         "wall_s": round(wall, 3),
         "monitor_nonfinite": int(mon[4]),
     }

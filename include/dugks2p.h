@@ -150,6 +150,16 @@ double dugks2p_dt(const dugks2p *h);
 int64_t dugks2p_step_count(const dugks2p *h);
 int dugks2p_kernel(const dugks2p *h);
 
+/* Measurement aid.  While enabled, each step records a HIP event before and
+ * after its tile kernel (the fused form's Steps 2-6 kernel) on the handle's
+ * stream, which adds a small gap between launches.  dugks2p_profile(h, 1)
+ * enables and clears the record, (h, 0) disables it.  dugks2p_profile_read
+ * synchronises the stream, writes the summed kernel time in milliseconds
+ * (host *ms) and the number of timed launches (host *launches; 0 for the
+ * staged form, which has no tile kernel), and clears the record. */
+int dugks2p_profile(dugks2p *h, int enable);
+int dugks2p_profile_read(dugks2p *h, double *ms, int64_t *launches);
+
 /* Release the handle and its device memory (NULL is accepted). */
 int dugks2p_destroy(dugks2p *h);
 

@@ -112,7 +112,12 @@ class Oracle:
             lib().orc_destroy(self._h)
             self._h = None
 
-    __del__ = close
+    def __del__(self):
+        # at interpreter shutdown the module globals may already be gone
+        try:
+            self.close()
+        except Exception:
+            pass
 
     @property
     def dt(self):

@@ -36,9 +36,28 @@ __global__ __launch_bounds__(256) void k_grid(F f, int n0, int n1) {
   if (i < n0 && j < n1) f(i, j);
 }
 
+// Event pairs recorded around the tile-kernel launches of a handle while
+// timing is enabled (dugks2p_profile); events are created on first use and
+// reused.
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  bool on = false;
+  hipError_t record(hipStream_t s) {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      const hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+    return hipEventRecord(ev[used++], s);
+  }
+};
+
 struct GpuEx {
   hipStream_t s;
   hipError_t err;
+  KernelTimer *kt = nullptr;
   template <class F>
   void grid(const F &f, int n0, int n1) {
     if (n0 <= 0 || n1 <= 0) return;
@@ -50,9 +69,14 @@ struct GpuEx {
   template <class IO, class R, bool U>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x(K), nt = ntx * tiles_y(K);
+    const bool timed = kt && kt->on;
+    if (timed) note(kt->record(s));
     hipLaunchKernelGGL((k_fused_tile<IO, R, U>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst, ntx,
                        nt);
-    const hipError_t e = hipGetLastError();
+    note(hipGetLastError());
+    if (timed) note(kt->record(s));
+  }
+  void note(hipError_t e) {
     if (e != hipSuccess && err == hipSuccess) err = e;
   }
 };
@@ -151,6 +175,7 @@ struct dugks2p {
   Work w;
   double *mon_part, *mon_out;
   int64_t nstep;
+  KernelTimer kt;
 };
 
 namespace {
@@ -186,7 +211,7 @@ std::string prepare(const dugks2p_params *P, Prepared &pr) {
 
 // One time step on the handle's stream.
 int launch_step(dugks2p *h) {
-  GpuEx ex{h->stream, hipSuccess};
+  GpuEx ex{h->stream, hipSuccess, &h->kt};
   if (h->precision == DUGKS2P_FP64 && h->kernel == DUGKS2P_KERNEL_STAGED) {
     seq_staged_step<GpuEx, double, double>(ex, h->K, h->w, (const double *)h->state[h->cur],
                                            (double *)h->state[1 - h->cur]);
@@ -405,9 +430,32 @@ double dugks2p_dt(const dugks2p *h) { return h ? h->K.dt : 0.0; }
 int64_t dugks2p_step_count(const dugks2p *h) { return h ? h->nstep : -1; }
 int dugks2p_kernel(const dugks2p *h) { return h ? h->kernel : DUGKS2P_EINVAL; }
 
+int dugks2p_profile(dugks2p *h, int enable) {
+  if (!h) return fail(DUGKS2P_EINVAL, "handle is NULL");
+  h->kt.on = enable != 0;
+  h->kt.used = 0;
+  return DUGKS2P_OK;
+}
+
+int dugks2p_profile_read(dugks2p *h, double *ms, int64_t *launches) {
+  if (!h || !ms || !launches) return fail(DUGKS2P_EINVAL, "NULL argument");
+  *ms = 0.0;
+  *launches = 0;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (size_t k = 0; k + 1 < h->kt.used; k += 2) {
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, h->kt.ev[k], h->kt.ev[k + 1]));
+    *ms += t;
+    ++*launches;
+  }
+  h->kt.used = 0;
+  return DUGKS2P_OK;
+}
+
 int dugks2p_destroy(dugks2p *h) {
   if (!h) return DUGKS2P_OK;
   (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->kt.ev) (void)hipEventDestroy(e);
   if (h->own_ws) (void)hipFree(h->ws);
   delete h;
   return DUGKS2P_OK;

@@ -62,6 +62,10 @@ def _load():
     L.dugks2p_kernel.argtypes = [vp]
     L.dugks2p_destroy.restype = ctypes.c_int
     L.dugks2p_destroy.argtypes = [vp]
+    L.dugks2p_profile.restype = ctypes.c_int
+    L.dugks2p_profile.argtypes = [vp, ctypes.c_int]
+    L.dugks2p_profile_read.restype = ctypes.c_int
+    L.dugks2p_profile_read.argtypes = [vp, P(d), P(ctypes.c_int64)]
     L.dugks2p_last_error.restype = ctypes.c_char_p
     L.dugks2p_last_error.argtypes = []
     PP = ctypes.POINTER(ctypes.c_void_p)
@@ -98,6 +102,7 @@ EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2
             "dugks2p_monitors", "dugks2p_get_populations", "dugks2p_set_populations",
             "dugks2p_state_bytes", "dugks2p_get_state", "dugks2p_set_state", "dugks2p_dt",
             "dugks2p_step_count", "dugks2p_kernel", "dugks2p_destroy", "dugks2p_last_error",
+            "dugks2p_profile", "dugks2p_profile_read",
             "dugks2p_batch_create", "dugks2p_batch_step", "dugks2p_batch_moments",
             "dugks2p_batch_monitors", "dugks2p_batch_get_populations", "dugks2p_batch_cells",
             "dugks2p_batch_destroy", "dugks2p_adjoint_workspace_bytes", "dugks2p_adjoint_create",
@@ -195,6 +200,18 @@ class Simulation:
 
     def step(self, n=1):
         _check(lib.dugks2p_step(self._h, int(n)))
+
+    def time_kernel(self, n):
+        """Run n steps with HIP events around the tile kernel; returns
+        (total kernel milliseconds, timed launches)."""
+        _check(lib.dugks2p_profile(self._h, 1))
+        try:
+            self.step(n)
+            ms, cnt = ctypes.c_double(), ctypes.c_int64()
+            _check(lib.dugks2p_profile_read(self._h, ctypes.byref(ms), ctypes.byref(cnt)))
+        finally:
+            lib.dugks2p_profile(self._h, 0)
+        return ms.value, cnt.value
 
     def moments(self):
         t = self.torch

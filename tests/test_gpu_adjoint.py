@@ -106,10 +106,10 @@ def test_gpu_adjoint_contracts(D):
 
 
 def test_gpu_rollout_gradient_rt64x256(D, oracle_mod):
-    """dJ/d(a_1..a_64, kappa, g) of J = sum (phi(T) - phi_ref)^2 through the
-    autograd.Function (checkpoints every 50 steps, ragged last segment),
+    """dJ/d(a_1..a_64, kappa, g) of J = sum (phi(T) - phi_ref(T))^2 through
+    the autograd.Function (checkpoints every 50 steps, ragged last segment),
     against central differences of the oracle in scaled coordinates
-    (a / sigma_a, kappa / kappa0, g / g0) along seeded unit directions."""
+    (a / sigma_a, kappa / kappa0, g / g0) along 8 seeded unit directions."""
     import torch
     from paper_1802_02868_amd.rollout import rollout
     case = W.rt_case(64)
@@ -117,7 +117,11 @@ def test_gpu_rollout_gradient_rt64x256(D, oracle_mod):
     print("rollout gradient:", case.name, steps, every, flush=True)
     a0 = W.rt_mode_amplitudes(64, 64, seed=2024)
     sig = 1e-3 * 64
-    ref = W.rt_interface_phi0(W.rt_mode_amplitudes(64, 64, seed=77), case)
+    # phi_ref(T): the oracle's rollout from a second seed's interface modes
+    o_ref = oracle_mod.Oracle.from_case(dataclasses.replace(
+        case, phi0=W.rt_interface_phi0(W.rt_mode_amplitudes(64, 64, seed=77), case)))
+    o_ref.step(steps)
+    ref = o_ref.pops()[9:].sum(0)
     k0, g0 = case.params["kappa"], case.params["gy"]
     a = torch.tensor(a0, dtype=torch.float64, device="cuda", requires_grad=True)
     kap = torch.tensor(k0, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -148,7 +152,7 @@ def test_gpu_rollout_gradient_rt64x256(D, oracle_mod):
     # a step of 1e-4 in scaled coordinates: the truncation error is then
     # below 1e-8 relative and roundoff in the differences is still small
     eps = 1e-4
-    for _ in range(4):
+    for _ in range(8):
         d = rng.standard_normal(theta.size)
         d /= np.linalg.norm(d)
         fd = J_oracle_diff(theta + eps * d, theta - eps * d) / (2 * eps)
@@ -157,7 +161,7 @@ def test_gpu_rollout_gradient_rt64x256(D, oracle_mod):
         assert abs(ad - fd) <= 1e-6 * abs(fd)
     # forward of the Function is the oracle's rollout bit for bit
     c = dataclasses.replace(case, phi0=W.rt_interface_phi0(a0, case))
-    assert float(J) > 0.0
+    assert float(J.detach()) > 0.0
     o = oracle_mod.Oracle.from_case(c)
     o.step(steps)
     phi_o = o.pops()[9:].sum(0)

@@ -184,3 +184,22 @@ def test_fp32_state_checkpoint_and_populations(D):
     b.step(20)
     assert np.array_equal(b.populations().cpu().numpy(), ref)
     assert b.monitors()[4] == 0
+
+
+@pytest.mark.gpu
+def test_kernel_timing_counts_tile_launches():
+    """The measurement aid times one tile-kernel launch per fused step and
+    leaves the results unchanged."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_02868_amd import dugks2p as D
+    case = W.drop_case(n=32, radius=8.0)
+    a = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)
+    b = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)
+    ms, n = a.time_kernel(7)
+    b.step(7)
+    assert n == 7 and ms > 0.0
+    assert torch.equal(a.populations(), b.populations())
+    s = D.Simulation.from_case(case, kernel=D.KERNEL_STAGED)
+    assert s.time_kernel(2)[1] == 0
