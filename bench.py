@@ -100,6 +100,7 @@ def batched_vs_plain(steps, precision):
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) / 1e3
     mon = [b.monitors(i, raise_nonfinite=False)[4] for i in range(len(cases))]
+    tile = b.tile
     b.close()
     sims = [D.Simulation.from_case(c, precision=precision, kernel=D.KERNEL_FUSED) for c in cases]
     for s_ in sims:
@@ -125,6 +126,7 @@ def batched_vs_plain(steps, precision):
             "plain_loop_mlups": round(cells * steps / best[1] / 1e6, 1),
             "plain_loop_order": best[0], "speedup": round(best[1] / t_batch, 3),
             "nonfinite_instances": int(sum(1 for m in mon if m > 0)),
+            "tile": ["auto", "14x14", "30x6", "6x30"][tile],
             "precision": "fp64" if precision == D.FP64 else "fp32-state"}
 
 
@@ -279,7 +281,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s %s (%dx%d cells, Rayleigh-Taylor, walls in y)" % (
             case.name, args.precision, case.nx, case.ny), "cells": cells,
-            "kernel": args.kernel, "dt": sim.dt},
+            "kernel": args.kernel, "tile": ["auto", "14x14", "30x6", "6x30"][sim.tile], "dt": sim.dt},
         "roofline": roof,
         "roofline_alu": roof_alu,
         "wall_s": round(wall, 3),

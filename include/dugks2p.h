@@ -47,6 +47,15 @@ enum { DUGKS2P_BC_PERIODIC = 0, DUGKS2P_BC_WALL = 1 };
 enum { DUGKS2P_FP64 = 0, DUGKS2P_FP32_STATE = 1 };
 enum { DUGKS2P_RECON_CENTRAL = 0, DUGKS2P_RECON_UPWIND = 1 };
 enum { DUGKS2P_KERNEL_AUTO = 0, DUGKS2P_KERNEL_STAGED = 1, DUGKS2P_KERNEL_FUSED = 2 };
+/* Tile shape of the fused kernel: cells per tile (x by y).  AUTO times the
+ * shapes on the problem at creation and keeps the fastest.  The wide and
+ * tall shapes apply at unit lattice speed (RT = 1/3); otherwise square. */
+enum {
+  DUGKS2P_TILE_AUTO = 0,
+  DUGKS2P_TILE_SQUARE = 1, /* 14 x 14 */
+  DUGKS2P_TILE_WIDE = 2,   /* 30 x 6  */
+  DUGKS2P_TILE_TALL = 3    /* 6 x 30  */
+};
 
 /*
  * Problem statement (Sec. 2 and 3 of the paper).
@@ -77,6 +86,9 @@ enum { DUGKS2P_KERNEL_AUTO = 0, DUGKS2P_KERNEL_STAGED = 1, DUGKS2P_KERNEL_FUSED 
  *                interpolation of value and gradient (the paper's choice);
  *                UPWIND = expansion from the upwind cell.
  *   kernel:      DUGKS2P_KERNEL_* implementation choice (AUTO = fused).
+ *   tile:        DUGKS2P_TILE_* tile shape of the fused kernel (a
+ *                performance choice: every shape gives the same results
+ *                bit for bit).
  *   workspace:   optional device memory of at least
  *                dugks2p_workspace_bytes(params) bytes, 256-byte aligned,
  *                owned by the caller and used instead of a library allocation.
@@ -89,7 +101,7 @@ typedef struct {
   int32_t recon;
   int32_t phi_clamp;
   int32_t kernel;
-  int32_t reserved0;
+  int32_t tile; /* DUGKS2P_TILE_* */
   const double *x_faces;
   const double *y_faces;
   double cfl, c_max, dt, rt;
@@ -149,6 +161,9 @@ int dugks2p_set_state(dugks2p *h, const void *src);
 double dugks2p_dt(const dugks2p *h);
 int64_t dugks2p_step_count(const dugks2p *h);
 int dugks2p_kernel(const dugks2p *h);
+/* DUGKS2P_TILE_* shape the handle's fused kernel uses (AUTO resolved; the
+ * staged form reports DUGKS2P_TILE_SQUARE). */
+int dugks2p_tile(const dugks2p *h);
 
 /* Measurement aid.  While enabled, each step records a HIP event before and
  * after its tile kernel (the fused form's Steps 2-6 kernel) on the handle's
@@ -172,7 +187,8 @@ const char *dugks2p_last_error(void);
  * 14x14 tile) entries), and runs of steps are captured once into HIP graphs
  * and replayed.  Each instance evolves exactly as a single handle with the
  * same parameters would (bit for bit).  All instances must share the
- * precision and use CENTRAL reconstruction (the fused kernel).
+ * precision and use CENTRAL reconstruction (the fused kernel); one tile
+ * shape serves the whole batch (dugks2p_batch_tile).
  *   params[n]: per-instance parameters (workspace fields ignored);
  *   phi0[n], ux0[n], uy0[n], p0[n]: device FP64 initial fields, each
  *   [ny_i][nx_i] for instance i.  The batch owns one device allocation. */
@@ -187,6 +203,10 @@ int dugks2p_batch_moments(dugks2p_batch *b, int32_t i, double *phi, double *rho,
 int dugks2p_batch_monitors(dugks2p_batch *b, int32_t i, double out[6]);
 int dugks2p_batch_get_populations(dugks2p_batch *b, int32_t i, double *dst);
 int64_t dugks2p_batch_cells(const dugks2p_batch *b);
+/* Tile shape of the batched tile kernel: the shape requested by every
+ * instance when they agree on one, else (AUTO) the fastest shape found by
+ * timing the batch's own step at creation. */
+int dugks2p_batch_tile(const dugks2p_batch *b);
 int dugks2p_batch_destroy(dugks2p_batch *b);
 
 

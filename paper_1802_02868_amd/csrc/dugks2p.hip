@@ -4,6 +4,7 @@
 
 #include <stdio.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -66,13 +67,13 @@ struct GpuEx {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess && err == hipSuccess) err = e;
   }
-  template <class IO, class R, bool U>
+  template <class IO, class R, bool U, class S>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
-    const int ntx = tiles_x(K), nt = ntx * tiles_y(K);
+    const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
     const bool timed = kt && kt->on;
     if (timed) note(kt->record(s));
-    hipLaunchKernelGGL((k_fused_tile<IO, R, U>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst, ntx,
-                       nt);
+    hipLaunchKernelGGL((k_fused_tile<IO, R, U, S>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst,
+                       ntx, nt);
     note(hipGetLastError());
     if (timed) note(kt->record(s));
   }
@@ -167,7 +168,7 @@ struct dugks2p {
   Consts K;
   Layout L;
   hipStream_t stream;
-  int precision, kernel;
+  int precision, kernel, tile;
   unsigned char *ws;
   bool own_ws;
   void *state[2];
@@ -209,31 +210,83 @@ std::string prepare(const dugks2p_params *P, Prepared &pr) {
   return std::string();
 }
 
-// One time step on the handle's stream.
-int launch_step(dugks2p *h) {
+// Enqueue one time step from state[cur] into state[1 - cur] with tile shape
+// `shape` (fused form), without committing it.
+int enqueue_step(dugks2p *h, int shape) {
   GpuEx ex{h->stream, hipSuccess, &h->kt};
   if (h->precision == DUGKS2P_FP64 && h->kernel == DUGKS2P_KERNEL_STAGED) {
     seq_staged_step<GpuEx, double, double>(ex, h->K, h->w, (const double *)h->state[h->cur],
                                            (double *)h->state[1 - h->cur]);
   } else if (h->precision == DUGKS2P_FP64) {
     const IoF64 src = io_f64(h->state[h->cur], h->K), dst = io_f64(h->state[1 - h->cur], h->K);
-    if (h->K.unit)
-      seq_fused_step<GpuEx, IoF64, double, true>(ex, h->K, h->w, src, dst);
-    else
-      seq_fused_step<GpuEx, IoF64, double, false>(ex, h->K, h->w, src, dst);
+    with_tile_shape(shape, h->K.unit, [&](auto sh) {
+      using S = decltype(sh);
+      if (h->K.unit)
+        seq_fused_step<GpuEx, IoF64, double, true, S>(ex, h->K, h->w, src, dst);
+      else
+        seq_fused_step<GpuEx, IoF64, double, false, TileSq>(ex, h->K, h->w, src, dst);
+    });
   } else {
     const IoE32 src = io_e32(h->state[h->cur], h->K, h->L);
     const IoE32 dst = io_e32(h->state[1 - h->cur], h->K, h->L);
-    if (h->K.unit)
-      seq_fused_step<GpuEx, IoE32, double, true>(ex, h->K, h->w, src, dst);
-    else
-      seq_fused_step<GpuEx, IoE32, double, false>(ex, h->K, h->w, src, dst);
+    with_tile_shape(shape, h->K.unit, [&](auto sh) {
+      using S = decltype(sh);
+      if (h->K.unit)
+        seq_fused_step<GpuEx, IoE32, double, true, S>(ex, h->K, h->w, src, dst);
+      else
+        seq_fused_step<GpuEx, IoE32, double, false, TileSq>(ex, h->K, h->w, src, dst);
+    });
   }
   if (ex.err != hipSuccess)
     return fail(DUGKS2P_EHIP, std::string("kernel launch: ") + hipGetErrorString(ex.err));
+  return DUGKS2P_OK;
+}
+
+// One time step on the handle's stream.
+int launch_step(dugks2p *h) {
+  const int rc = enqueue_step(h, h->tile);
+  if (rc) return rc;
   h->cur = 1 - h->cur;
   h->nstep++;
   return DUGKS2P_OK;
+}
+
+// Tile-shape tuner: time a few uncommitted steps with each shape (the step
+// writes only the spare ping-pong buffer and the work fields, which the next
+// real step rewrites) and keep the fastest.  Results do not depend on the
+// shape, only the speed does.
+int tune_tile(dugks2p *h) {
+  if (h->kernel != DUGKS2P_KERNEL_FUSED || !h->K.unit) {
+    h->tile = DUGKS2P_TILE_SQUARE;
+    return DUGKS2P_OK;
+  }
+  enum { WARM = 1, REPS = 3 };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = DUGKS2P_OK;
+  float best = 0.0f;
+  int pick = DUGKS2P_TILE_SQUARE;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = fail(DUGKS2P_EHIP, "tuner events");
+  for (int shape = DUGKS2P_TILE_SQUARE; rc == DUGKS2P_OK && shape <= DUGKS2P_TILE_TALL; ++shape) {
+    for (int r = 0; r < WARM + REPS && rc == DUGKS2P_OK; ++r) {
+      if (r == WARM && hipEventRecord(e0, h->stream) != hipSuccess)
+        rc = fail(DUGKS2P_EHIP, "tuner event");
+      if (rc == DUGKS2P_OK) rc = enqueue_step(h, shape);
+    }
+    float ms = 0.0f;
+    if (rc == DUGKS2P_OK &&
+        (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(DUGKS2P_EHIP, "tuner timing");
+    if (rc == DUGKS2P_OK && (shape == DUGKS2P_TILE_SQUARE || ms < best)) {
+      best = ms;
+      pick = shape;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  h->tile = pick;
+  return rc;
 }
 
 // Cell fields of the current state into the work arrays.
@@ -277,6 +330,9 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
   h->stream = (hipStream_t)hip_stream;
   h->precision = P->precision;
   h->kernel = use_staged(P) ? DUGKS2P_KERNEL_STAGED : DUGKS2P_KERNEL_FUSED;
+  h->tile = (h->kernel == DUGKS2P_KERNEL_FUSED && pr.K.unit && P->tile != DUGKS2P_TILE_AUTO)
+                ? P->tile
+                : DUGKS2P_TILE_SQUARE;
   h->cur = 0;
   h->nstep = 0;
   if (P->workspace) {
@@ -325,6 +381,7 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
       rc = fail(DUGKS2P_EHIP, std::string("init launch: ") + hipGetErrorString(ex.err));
       break;
     }
+    if (P->tile == DUGKS2P_TILE_AUTO) rc = tune_tile(h);
   } while (0);
   if (rc != DUGKS2P_OK) {
     (void)hipStreamSynchronize(h->stream);
@@ -429,6 +486,7 @@ int dugks2p_set_state(dugks2p *h, const void *src) {
 double dugks2p_dt(const dugks2p *h) { return h ? h->K.dt : 0.0; }
 int64_t dugks2p_step_count(const dugks2p *h) { return h ? h->nstep : -1; }
 int dugks2p_kernel(const dugks2p *h) { return h ? h->kernel : DUGKS2P_EINVAL; }
+int dugks2p_tile(const dugks2p *h) { return h ? h->tile : DUGKS2P_EINVAL; }
 
 int dugks2p_profile(dugks2p *h, int enable) {
   if (!h) return fail(DUGKS2P_EINVAL, "handle is NULL");

@@ -18,7 +18,22 @@
 
 namespace dg {
 
-enum { TT = 14, W1 = TT + 2, W2 = TT + 4, NTHR = W1 * W1 };  // 256 threads
+enum { NTHR = 256 };  // threads of a tile workgroup
+
+// Tile shape: TX x TY cells, a one-cell ring for bar+ (the WX x WY window,
+// one thread per window cell) and a two-cell ring for the cell scalars (the
+// SX x SY window).  SM, FM: lengths of the per-axis weight and face tables.
+template <int TX_, int TY_>
+struct Tile {
+  enum {
+    TX = TX_, TY = TY_, WX = TX + 2, WY = TY + 2, SX = TX + 4, SY = TY + 4,
+    SM = SX > SY ? SX : SY, FM = (TX > TY ? TX : TY) + 1
+  };
+  static_assert(WX * WY == NTHR, "one thread per bar+ window cell");
+};
+typedef Tile<14, 14> TileSq;   // square tiles (the default)
+typedef Tile<30, 6> TileWide;  // wide tiles (long rows)
+typedef Tile<6, 30> TileTall;  // tall tiles (long columns)
 
 // x-face flux slots: directions with e_x != 0 (1, 3, 5, 6, 7, 8); y-face:
 // e_y != 0 (2, 4, 5, 6, 7, 8).  -1 = no flux across that face.
@@ -88,20 +103,21 @@ struct FMacF {
 
 // LDS of one tile.  A (bar+ on the tile and its ring) is dead once the faces
 // are computed; the face fluxes then reuse its space.
+template <class S>
 struct TileLds {
   union {
-    double A[18][W1][W1];
+    double A[18][S::WY][S::WX];
     struct {
-      double X[12][TT][TT + 1];
-      double Y[12][TT + 1][TT];
+      double X[12][S::TY][S::TX + 1];
+      double Y[12][S::TY + 1][S::TX];
     } f;
   } u;
-  double phi[W2][W2], mu[W2][W2], p[W2][W2];
+  double phi[S::SY][S::SX], mu[S::SY][S::SX], p[S::SY][S::SX];
   // App. B weights (population gradient, first derivative) of the tile's
   // columns (axis 0) and rows (axis 1) at the scalar-window positions, and
-  // the geometry of the tile's faces (local face 0..TT along each axis)
-  double pgw[2][W2][3], d1w[2][W2][3];
-  double fwl[2][TT + 1], fwr[2][TT + 1], finv[2][TT + 1], foffl[2][TT + 1], foffr[2][TT + 1];
+  // the geometry of the tile's faces (local face 0..TX along x, 0..TY along y)
+  double pgw[2][S::SM][3], d1w[2][S::SM][3];
+  double fwl[2][S::FM], fwr[2][S::FM], finv[2][S::FM], foffl[2][S::FM], foffr[2][S::FM];
 };
 
 // Accessor of the face code over the tile's LDS (bar+, phi, mu, p) and the
@@ -109,15 +125,16 @@ struct TileLds {
 // folded back; a window position holding another image of the same cell
 // holds the same value.  A handle carries the LDS offsets of the cell and of
 // its stencil neighbours, computed once per face.
+template <class S>
 struct LAcc {
   const Consts *K;
   const Work *w;
-  const TileLds *L;
+  const TileLds<S> *L;
   int x0, y0;
   struct H {
     int x, y;
-    int o1, lo1[2], hi1[2];  // offsets in the bar+ window (W1 x W1)
-    int o2, lo2[2], hi2[2];  // offsets in the scalar window (W2 x W2)
+    int o1, lo1[2], hi1[2];  // offsets in the bar+ window (WX x WY)
+    int o2, lo2[2], hi2[2];  // offsets in the scalar window (SX x SY)
     int w2[2];               // scalar-window column and row (weight tables)
   };
   DFN int win(int g, int o, int n, int wd) const {
@@ -150,24 +167,24 @@ struct LAcc {
     H h;
     h.x = x;
     h.y = y;
-    const int px = win(x, x0 - 1, K->nx, W1), py = win(y, y0 - 1, K->ny, W1);
+    const int px = win(x, x0 - 1, K->nx, S::WX), py = win(y, y0 - 1, K->ny, S::WY);
     const int sxl = (X.bc != 0 && x == 0) ? 0 : 1, sxh = (X.bc != 0 && x == X.n - 1) ? 0 : 1;
     const int syl = (Y.bc != 0 && y == 0) ? 0 : 1, syh = (Y.bc != 0 && y == Y.n - 1) ? 0 : 1;
-    const int lx1 = nbw(px - sxl, W1), hx1 = nbw(px + sxh, W1);
-    const int ly1 = nbw(py - syl, W1), hy1 = nbw(py + syh, W1);
-    h.o1 = py * W1 + px;
-    h.lo1[0] = py * W1 + lx1;
-    h.hi1[0] = py * W1 + hx1;
-    h.lo1[1] = ly1 * W1 + px;
-    h.hi1[1] = hy1 * W1 + px;
+    const int lx1 = nbw(px - sxl, S::WX), hx1 = nbw(px + sxh, S::WX);
+    const int ly1 = nbw(py - syl, S::WY), hy1 = nbw(py + syh, S::WY);
+    h.o1 = py * S::WX + px;
+    h.lo1[0] = py * S::WX + lx1;
+    h.hi1[0] = py * S::WX + hx1;
+    h.lo1[1] = ly1 * S::WX + px;
+    h.hi1[1] = hy1 * S::WX + px;
     const int qx = px + 1, qy = py + 1;
     h.w2[0] = qx;
     h.w2[1] = qy;
-    h.o2 = qy * W2 + qx;
-    h.lo2[0] = qy * W2 + (qx - sxl);
-    h.hi2[0] = qy * W2 + (qx + sxh);
-    h.lo2[1] = (qy - syl) * W2 + qx;
-    h.hi2[1] = (qy + syh) * W2 + qx;
+    h.o2 = qy * S::SX + qx;
+    h.lo2[0] = qy * S::SX + (qx - sxl);
+    h.hi2[0] = qy * S::SX + (qx + sxh);
+    h.lo2[1] = (qy - syl) * S::SX + qx;
+    h.hi2[1] = (qy + syh) * S::SX + qx;
     return h;
   }
   DFN static int chk(int off, int lim) {
@@ -185,17 +202,18 @@ struct LAcc {
     return off;
   }
   DFN const double *Aq(int q) const { return &L->u.A[q][0][0]; }
-  DFN double A(int q, const H &h) const { return Aq(q)[chk(h.o1, W1 * W1)]; }
+  enum { NW1 = S::WX * S::WY, NW2 = S::SX * S::SY };
+  DFN double A(int q, const H &h) const { return Aq(q)[chk(h.o1, NW1)]; }
   DFN double pgrad(int a, int q, const H &h) const {
-    const double *wt = L->pgw[a][chk(h.w2[a], W2)];
+    const double *wt = L->pgw[a][chk(h.w2[a], a == 0 ? S::SX : S::SY)];
     const double *aq = Aq(q);
-    return wt[0] * aq[chk(h.lo1[a], W1 * W1)] + wt[1] * aq[chk(h.o1, W1 * W1)] +
-           wt[2] * aq[chk(h.hi1[a], W1 * W1)];
+    return wt[0] * aq[chk(h.lo1[a], NW1)] + wt[1] * aq[chk(h.o1, NW1)] +
+           wt[2] * aq[chk(h.hi1[a], NW1)];
   }
   DFN double d1(int a, const H &h, const double *f) const {
-    const double *wt = L->d1w[a][chk(h.w2[a], W2)];
-    return wt[0] * f[chk(h.lo2[a], W2 * W2)] + wt[1] * f[chk(h.o2, W2 * W2)] +
-           wt[2] * f[chk(h.hi2[a], W2 * W2)];
+    const double *wt = L->d1w[a][chk(h.w2[a], a == 0 ? S::SX : S::SY)];
+    return wt[0] * f[chk(h.lo2[a], NW2)] + wt[1] * f[chk(h.o2, NW2)] +
+           wt[2] * f[chk(h.hi2[a], NW2)];
   }
   // face k of axis a (a face of this tile; a periodic axis passes the face
   // at the far end as face 0)
@@ -204,7 +222,7 @@ struct LAcc {
     int f = k - (a == 0 ? x0 : y0);
     if (f < 0) f += X.n;
 #ifdef DUGKS2P_WINDOW_CHECK
-    if (f < 0 || f > TT) {
+    if (f < 0 || f > (a == 0 ? S::TX : S::TY)) {
       printf("face check: axis %d face %d local %d\n", a, k, f);
 #if !defined(__HIP_DEVICE_COMPILE__)
       fflush(stdout);
@@ -222,9 +240,9 @@ struct LAcc {
     g.offr = L->foffr[a][f];
     return g;
   }
-  DFN double mu(const H &h) const { return (&L->mu[0][0])[chk(h.o2, W2 * W2)]; }
-  DFN double phi(const H &h) const { return (&L->phi[0][0])[chk(h.o2, W2 * W2)]; }
-  DFN double p(const H &h) const { return (&L->p[0][0])[chk(h.o2, W2 * W2)]; }
+  DFN double mu(const H &h) const { return (&L->mu[0][0])[chk(h.o2, NW2)]; }
+  DFN double phi(const H &h) const { return (&L->phi[0][0])[chk(h.o2, NW2)]; }
+  DFN double p(const H &h) const { return (&L->p[0][0])[chk(h.o2, NW2)]; }
   DFN double D(const H &h) const { return w->D[(i64)h.y * K->ld + h.x]; }
   DFN double dmu(int a, const H &h) const { return d1(a, h, &L->mu[0][0]); }
   DFN double dphi(int a, const H &h) const { return d1(a, h, &L->phi[0][0]); }
@@ -236,15 +254,15 @@ DFN int wrapi(int g, int n) {
   return r < 0 ? r + n : r;
 }
 
-// One 14 x 14 tile with origin (x0, y0).
-template <class IO, class R, bool U = false>
+// One tile of shape S with origin (x0, y0).
+template <class IO, class R, bool U = false, class S = TileSq>
 struct FusedTile {
   const Consts &K;
   const Work &w;
   IO src;
   IO dst;
   int x0, y0;
-  TileLds *L;
+  TileLds<S> *L;
 
   struct TS {
     R fx[12], fy[12];
@@ -259,8 +277,8 @@ struct FusedTile {
 
   // P0: phi, mu, p on the tile and a two-cell ring.
   DFN void p0(int tid) const {
-    for (int e = tid; e < W2 * W2; e += NTHR) {
-      const int lx = e % W2, ly = e / W2;
+    for (int e = tid; e < S::SX * S::SY; e += NTHR) {
+      const int lx = e % S::SX, ly = e / S::SX;
       const int gx = gcol(x0 - 2 + lx, K.nx, K.ax[0].bc);
       const int gy = gcol(y0 - 2 + ly, K.ny, K.ax[1].bc);
       if (gx < 0 || gy < 0) continue;
@@ -270,8 +288,8 @@ struct FusedTile {
       L->p[ly][lx] = w.p[c];
     }
     // weight tables of the window's columns and rows
-    for (int e = tid; e < 2 * W2; e += NTHR) {
-      const int a = e / W2, pos = e % W2;
+    for (int e = tid; e < S::SX + S::SY; e += NTHR) {
+      const int a = e < S::SX ? 0 : 1, pos = a == 0 ? e : e - S::SX;
       const Axis &X = K.ax[a];
       const int g = gcol((a == 0 ? x0 : y0) - 2 + pos, X.n, X.bc);
       if (g < 0) continue;
@@ -282,8 +300,8 @@ struct FusedTile {
       }
     }
     // geometry of the tile's faces
-    for (int e = tid; e < 2 * (TT + 1); e += NTHR) {
-      const int a = e / (TT + 1), f = e % (TT + 1);
+    for (int e = tid; e < S::TX + S::TY + 2; e += NTHR) {
+      const int a = e <= S::TX ? 0 : 1, f = a == 0 ? e : e - S::TX - 1;
       const Axis &X = K.ax[a];
       int k = (a == 0 ? x0 : y0) + f;
       if (X.bc == 0 && k == X.n) k = 0;
@@ -298,13 +316,13 @@ struct FusedTile {
 
   // P1: Step 2 on the tile and a one-cell ring; tilde+ kept for the tile.
   DFN void p1(int tid, TS &ts) const {
-    const int lx = tid % W1, ly = tid / W1;
+    const int lx = tid % S::WX, ly = tid / S::WX;
     const int gx = gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
     const int gy = gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
     if (gx < 0 || gy < 0) return;
     const i64 c = (i64)gy * K.ld + gx;
-    const LAcc acc{&K, &w, L, x0, y0};
-    const LAcc::H hc = acc.cell(gx, gy);
+    const LAcc<S> acc{&K, &w, L, x0, y0};
+    const typename LAcc<S>::H hc = acc.cell(gx, gy);
     const double ph = acc.phi(hc);
     const double rh = rho_of<double>(K, ph);
     Mac<R> m;
@@ -332,7 +350,8 @@ struct FusedTile {
 #pragma unroll
     for (int q = 0; q < 18; ++q) L->u.A[q][ly][lx] = (double)out[q];
     // tilde+ of the tile's own cells waits in the output buffer for P4
-    if (lx >= 1 && lx <= TT && ly >= 1 && ly <= TT && x0 + lx - 1 < K.nx && y0 + ly - 1 < K.ny) {
+    if (lx >= 1 && lx <= S::TX && ly >= 1 && ly <= S::TY && x0 + lx - 1 < K.nx &&
+        y0 + ly - 1 < K.ny) {
 #pragma unroll
       for (int q = 0; q < 18; ++q)
         tv[q] = (double)((R)(4.0 / 3.0) * (R)(double)out[q] - (R)(1.0 / 3.0) * til[q]);
@@ -343,15 +362,15 @@ struct FusedTile {
   // P2: Steps 3-4 at the x-face west of tile column tx and the y-face south
   // of tile row ty.
   DFN void p2(int tid, TS &ts) const {
-    const int tx = tid % W1, ty = tid / W1;
-    const LAcc acc{&K, &w, L, x0, y0};
+    const int tx = tid % S::WX, ty = tid / S::WX;
+    const LAcc<S> acc{&K, &w, L, x0, y0};
     ts.hx = ts.hy = false;
     R out[18];
     const bool perx = K.ax[0].bc == 0, pery = K.ax[1].bc == 0;
-    if (tx <= TT && ty < TT) {
+    if (tx <= S::TX && ty < S::TY) {
       const int k = x0 + tx, t = y0 + ty;
       if (t < K.ny && k <= K.nx) {
-        face_core<0, R, LAcc, U>(K, acc, (perx && k == K.nx) ? 0 : k, t, out);
+        face_core<0, R, LAcc<S>, U>(K, acc, (perx && k == K.nx) ? 0 : k, t, out);
 #pragma unroll
         for (int q = 0; q < 18; ++q) {
           const int s = xslot(q % 9);
@@ -360,10 +379,10 @@ struct FusedTile {
         ts.hx = true;
       }
     }
-    if (tx < TT && ty <= TT) {
+    if (tx < S::TX && ty <= S::TY) {
       const int k = y0 + ty, t = x0 + tx;
       if (t < K.nx && k <= K.ny) {
-        face_core<1, R, LAcc, U>(K, acc, (pery && k == K.ny) ? 0 : k, t, out);
+        face_core<1, R, LAcc<S>, U>(K, acc, (pery && k == K.ny) ? 0 : k, t, out);
 #pragma unroll
         for (int q = 0; q < 18; ++q) {
           const int s = yslot(q % 9);
@@ -376,7 +395,7 @@ struct FusedTile {
 
   // P3: face values into LDS (over the dead bar+).
   DFN void p3(int tid, const TS &ts) const {
-    const int tx = tid % W1, ty = tid / W1;
+    const int tx = tid % S::WX, ty = tid / S::WX;
     if (ts.hx)
 #pragma unroll
       for (int s = 0; s < 12; ++s) L->u.f.X[s][ty][tx] = (double)ts.fx[s];
@@ -387,8 +406,8 @@ struct FusedTile {
 
   // P4: Steps 5-6 (eq. updatef) for the tile's cells.
   DFN void p4(int tid, const TS &ts) const {
-    const int lx = tid % W1, ly = tid / W1;
-    if (lx < 1 || lx > TT || ly < 1 || ly > TT) return;
+    const int lx = tid % S::WX, ly = tid / S::WX;
+    if (lx < 1 || lx > S::TX || ly < 1 || ly > S::TY) return;
     const int cx = lx - 1, cy = ly - 1;
     const int gx = x0 + cx, gy = y0 + cy;
     if (gx >= K.nx || gy >= K.ny) return;
@@ -399,31 +418,33 @@ struct FusedTile {
 #pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int d = q % 9, sx = xslot(d), sy = yslot(d);
-      R W = (R)0.0, E = (R)0.0, S = (R)0.0, N = (R)0.0;
+      R W = (R)0.0, E = (R)0.0, Sf = (R)0.0, N = (R)0.0;
       if (sx >= 0) {
         W = (R)L->u.f.X[(q / 9) * 6 + sx][cy][cx];
         E = (R)L->u.f.X[(q / 9) * 6 + sx][cy][cx + 1];
       }
       if (sy >= 0) {
-        S = (R)L->u.f.Y[(q / 9) * 6 + sy][cy][cx];
+        Sf = (R)L->u.f.Y[(q / 9) * 6 + sy][cy][cx];
         N = (R)L->u.f.Y[(q / 9) * 6 + sy][cy + 1][cx];
       }
       const R tilp = (R)tv[q];
       if (U) {
         // (rx * e_x) (E - W) with e_x in {-1, 0, 1}; a zero term leaves tilp
         const R tx = sx >= 0 ? (ex_of(d) > 0 ? rx : -rx) * (E - W) : (R)0.0;
-        const R ty = sy >= 0 ? (ey_of(d) > 0 ? ry : -ry) * (N - S) : (R)0.0;
+        const R ty = sy >= 0 ? (ey_of(d) > 0 ? ry : -ry) * (N - Sf) : (R)0.0;
         tv[q] = (double)(tilp - tx - ty);
       } else {
-        tv[q] = (double)(tilp - rx * (R)K.xi0[d] * (E - W) - ry * (R)K.xi1[d] * (N - S));
+        tv[q] = (double)(tilp - rx * (R)K.xi0[d] * (E - W) - ry * (R)K.xi1[d] * (N - Sf));
       }
     }
     dst.store(c, tv);
   }
 };
 
-inline int tiles_x(const Consts &K) { return (K.nx + TT - 1) / TT; }
-inline int tiles_y(const Consts &K) { return (K.ny + TT - 1) / TT; }
+template <class S>
+DFN int tiles_x(const Consts &K) { return (K.nx + S::TX - 1) / S::TX; }
+template <class S>
+DFN int tiles_y(const Consts &K) { return (K.ny + S::TY - 1) / S::TY; }
 
 // Workgroups are dealt to the 8 XCDs round robin; give each XCD a contiguous
 // run of tiles so that neighbouring tiles share its L2.
@@ -434,13 +455,13 @@ DFN int xcd_tile(int b, int n) {
 }
 
 #if defined(__HIPCC__)
-template <class IO, class R, bool U>
+template <class IO, class R, bool U, class S>
 __global__ __launch_bounds__(NTHR) void k_fused_tile(Consts K, Work w, IO src, IO dst, int ntx,
                                                      int ntiles) {
-  __shared__ TileLds L;
+  __shared__ TileLds<S> L;
   const int tile = xcd_tile(blockIdx.x, ntiles);
-  FusedTile<IO, R, U> ft{K, w, src, dst, (tile % ntx) * TT, (tile / ntx) * TT, &L};
-  typename FusedTile<IO, R, U>::TS ts;
+  FusedTile<IO, R, U, S> ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY, &L};
+  typename FusedTile<IO, R, U, S>::TS ts;
   const int tid = threadIdx.x;
   ft.p0(tid);
   __syncthreads();
@@ -454,13 +475,26 @@ __global__ __launch_bounds__(NTHR) void k_fused_tile(Consts K, Work w, IO src, I
 }
 #endif
 
-// One fused time step (Ex: grid(functor, n0, n1) and tiles<T, R>(...)).
-// U: unit lattice speed (RT = 1/3), chosen by the host.
-template <class Ex, class IO, class R, bool U>
+// One fused time step (Ex: grid(functor, n0, n1) and tiles<IO, R, U, S>(...)).
+// U: unit lattice speed (RT = 1/3), chosen by the host; S: tile shape.
+template <class Ex, class IO, class R, bool U, class S = TileSq>
 void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const IO &src, const IO &dst) {
   ex.grid(FPhiSums<IO, U>{K, w, src}, K.nx, K.ny);
   ex.grid(FMacF{K, w}, K.nx, K.ny);
-  ex.template tiles<IO, R, U>(K, w, src, dst);
+  ex.template tiles<IO, R, U, S>(K, w, src, dst);
+}
+
+// Calls f(S{}) with the tile shape of a DUGKS2P_TILE_* value (1 square,
+// 2 wide, 3 tall).  The non-square shapes exist for unit lattice speed only;
+// other speeds always take square tiles.
+template <class F>
+void with_tile_shape(int shape, bool unit, F &&f) {
+  if (unit && shape == 2)
+    f(TileWide{});
+  else if (unit && shape == 3)
+    f(TileTall{});
+  else
+    f(TileSq{});
 }
 
 // Cell fields of the current state for moments and monitors (phi, mu, D, F,

@@ -144,6 +144,8 @@ inline std::string validate(const dugks2p_params *P) {
     return "recon must be DUGKS2P_RECON_CENTRAL or DUGKS2P_RECON_UPWIND";
   if (P->kernel < DUGKS2P_KERNEL_AUTO || P->kernel > DUGKS2P_KERNEL_FUSED)
     return "kernel must be a DUGKS2P_KERNEL_* value";
+  if (P->tile < DUGKS2P_TILE_AUTO || P->tile > DUGKS2P_TILE_TALL)
+    return "tile must be a DUGKS2P_TILE_* value";
   if (!P->x_faces || !P->y_faces) return "x_faces / y_faces is NULL";
   if (!strictly_increasing(P->x_faces, P->nx) || !strictly_increasing(P->y_faces, P->ny))
     return "faces must be strictly increasing";

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libdugks2p.so")
 from .dugks2p_params import (ABI_VERSION, BC_PERIODIC, BC_WALL, EHIP, EINVAL,  # noqa: F401
                              ENOMEM, ENONFINITE, EUNSUPPORTED, FP32_STATE, FP64,
                              KERNEL_AUTO, KERNEL_FUSED, KERNEL_STAGED, OK, RECON_CENTRAL,
-                             RECON_UPWIND, Params, make_params)
+                             RECON_UPWIND, TILE_AUTO, TILE_SQUARE, TILE_TALL, TILE_WIDE,
+                             Params, make_params)
 
 
 class DugksError(RuntimeError):
@@ -60,6 +61,8 @@ def _load():
     L.dugks2p_step_count.argtypes = [vp]
     L.dugks2p_kernel.restype = ctypes.c_int
     L.dugks2p_kernel.argtypes = [vp]
+    L.dugks2p_tile.restype = ctypes.c_int
+    L.dugks2p_tile.argtypes = [vp]
     L.dugks2p_destroy.restype = ctypes.c_int
     L.dugks2p_destroy.argtypes = [vp]
     L.dugks2p_profile.restype = ctypes.c_int
@@ -81,6 +84,8 @@ def _load():
     L.dugks2p_batch_get_populations.argtypes = [vp, ctypes.c_int32, vp]
     L.dugks2p_batch_cells.restype = ctypes.c_int64
     L.dugks2p_batch_cells.argtypes = [vp]
+    L.dugks2p_batch_tile.restype = ctypes.c_int
+    L.dugks2p_batch_tile.argtypes = [vp]
     L.dugks2p_batch_destroy.restype = ctypes.c_int
     L.dugks2p_batch_destroy.argtypes = [vp]
     L.dugks2p_adjoint_workspace_bytes.restype = ctypes.c_size_t
@@ -101,10 +106,12 @@ lib = _load()
 EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2p_moments",
             "dugks2p_monitors", "dugks2p_get_populations", "dugks2p_set_populations",
             "dugks2p_state_bytes", "dugks2p_get_state", "dugks2p_set_state", "dugks2p_dt",
-            "dugks2p_step_count", "dugks2p_kernel", "dugks2p_destroy", "dugks2p_last_error",
+            "dugks2p_step_count", "dugks2p_kernel", "dugks2p_tile", "dugks2p_destroy",
+            "dugks2p_last_error",
             "dugks2p_profile", "dugks2p_profile_read",
             "dugks2p_batch_create", "dugks2p_batch_step", "dugks2p_batch_moments",
             "dugks2p_batch_monitors", "dugks2p_batch_get_populations", "dugks2p_batch_cells",
+            "dugks2p_batch_tile",
             "dugks2p_batch_destroy", "dugks2p_adjoint_workspace_bytes", "dugks2p_adjoint_create",
             "dugks2p_adjoint_segment", "dugks2p_adjoint_initial", "dugks2p_adjoint_destroy")
 
@@ -197,6 +204,11 @@ class Simulation:
     @property
     def nstep(self):
         return lib.dugks2p_step_count(self._h)
+
+    @property
+    def tile(self):
+        """TILE_* shape the fused kernel uses (AUTO resolved)."""
+        return lib.dugks2p_tile(self._h)
 
     def step(self, n=1):
         _check(lib.dugks2p_step(self._h, int(n)))
@@ -297,6 +309,11 @@ class BatchSimulation:
     @property
     def cells(self):
         return int(lib.dugks2p_batch_cells(self._h))
+
+    @property
+    def tile(self):
+        """TILE_* shape of the batched tile kernel (AUTO resolved)."""
+        return lib.dugks2p_batch_tile(self._h)
 
     def step(self, n=1):
         _check(lib.dugks2p_batch_step(self._h, int(n)))

@@ -11,12 +11,13 @@ BC_PERIODIC, BC_WALL = 0, 1
 FP64, FP32_STATE = 0, 1
 RECON_CENTRAL, RECON_UPWIND = 0, 1
 KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED = 0, 1, 2
+TILE_AUTO, TILE_SQUARE, TILE_WIDE, TILE_TALL = 0, 1, 2, 3
 ABI_VERSION = 1
 
 _DOUBLE_FIELDS = ("cfl", "c_max", "dt", "rt", "tau_g", "mobility", "tau_f", "beta", "kappa",
                   "phi_a", "phi_b", "rho_a", "rho_b", "nu_a", "nu_b", "gx", "gy", "rho_ref")
 _INT_FIELDS = ("abi_version", "nx", "ny", "bc_x", "bc_y", "precision", "recon", "phi_clamp",
-               "kernel", "reserved0")
+               "kernel", "tile")
 
 
 class Params(ctypes.Structure):

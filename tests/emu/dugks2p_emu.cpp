@@ -25,15 +25,16 @@ struct CpuEx {
   }
   // Every workgroup of the tile kernel in turn; each phase runs for all 256
   // threads before the next (the barrier between phases).
-  template <class IO, class R, bool U>
+  template <class IO, class R, bool U, class S>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
-    const int ntx = tiles_x(K), nt = ntx * tiles_y(K);
-    std::vector<TileLds> L(1);
-    std::vector<typename FusedTile<IO, R, U>::TS> ts(NTHR);
+    const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
+    std::vector<TileLds<S>> L(1);
+    std::vector<typename FusedTile<IO, R, U, S>::TS> ts(NTHR);
     for (int b = 0; b < nt; ++b) {
       const int tile = xcd_tile(b, nt);
-      memset((void *)L.data(), 0xff, sizeof(TileLds));  // NaN poison: stray reads show
-      FusedTile<IO, R, U> ft{K, w, src, dst, (tile % ntx) * TT, (tile / ntx) * TT, L.data()};
+      memset((void *)L.data(), 0xff, sizeof(TileLds<S>));  // NaN poison: stray reads show
+      FusedTile<IO, R, U, S> ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY,
+                                L.data()};
       for (int t = 0; t < NTHR; ++t) ft.p0(t);
       for (int t = 0; t < NTHR; ++t) ft.p1(t, ts[t]);
       for (int t = 0; t < NTHR; ++t) ft.p2(t, ts[t]);
@@ -46,12 +47,16 @@ struct CpuEx {
 
 template <class IO>
 static void run_steps(CpuEx &ex, const Consts &K, const Work &w, IO st[2], int &cur, bool fused,
-                      long long nsteps) {
+                      long long nsteps, int shape) {
   for (long long n = 0; n < nsteps; ++n) {
-    if (fused && K.unit)
-      seq_fused_step<CpuEx, IO, double, true>(ex, K, w, st[cur], st[1 - cur]);
-    else if (fused)
-      seq_fused_step<CpuEx, IO, double, false>(ex, K, w, st[cur], st[1 - cur]);
+    if (fused)
+      with_tile_shape(shape, K.unit, [&](auto sh) {
+        using S = decltype(sh);
+        if (K.unit)
+          seq_fused_step<CpuEx, IO, double, true, S>(ex, K, w, st[cur], st[1 - cur]);
+        else
+          seq_fused_step<CpuEx, IO, double, false, TileSq>(ex, K, w, st[cur], st[1 - cur]);
+      });
     cur = 1 - cur;
   }
 }
@@ -86,7 +91,7 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
     IoF64 st[2] = {io_f64(base + L.state[0], K), io_f64(base + L.state[1], K)};
     seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
     if (fused) {
-      run_steps(ex, K, w, st, cur, true, nsteps);
+      run_steps(ex, K, w, st, cur, true, nsteps, P->tile);
     } else {
       for (long long n = 0; n < nsteps; ++n) {
         seq_staged_step(ex, K, w, (const double *)st[cur].p, st[1 - cur].p);
@@ -102,7 +107,7 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
   } else {
     IoE32 st[2] = {io_e32(base + L.state[0], K, L), io_e32(base + L.state[1], K, L)};
     seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
-    run_steps(ex, K, w, st, cur, true, nsteps);
+    run_steps(ex, K, w, st, cur, true, nsteps, P->tile);
     for (int j = 0; j < K.ny; ++j)
       for (int i = 0; i < K.nx; ++i) {
         st[cur].load((i64)j * K.ld + i, v);

@@ -46,3 +46,24 @@ def test_batch_rejects_mixed_precision(D):
     c2.params = dict(c2.params, precision=1)
     with pytest.raises(D.DugksError):
         D.BatchSimulation([c, c2])
+
+
+@pytest.mark.parametrize("tile", [0, 2, 3], ids=["tuned", "wide", "tall"])
+def test_batch_tile_shapes_bitwise_equal_single(D, tile):
+    """A batch run with a fixed or a tuned tile shape matches single handles
+    (square tiles) bit for bit."""
+    cases = _cases()[:3]
+    for c in cases:
+        c.params["tile"] = tile
+    b = D.BatchSimulation(cases, precision=D.FP32_STATE)
+    if tile:
+        assert b.tile == tile
+    else:
+        assert b.tile in (D.TILE_SQUARE, D.TILE_WIDE, D.TILE_TALL)
+    b.step(11)
+    for i, c in enumerate(cases):
+        print("batch tile", tile, i, c.name, flush=True)
+        c.params["tile"] = D.TILE_SQUARE
+        s = D.Simulation.from_case(c, precision=D.FP32_STATE, kernel=D.KERNEL_FUSED)
+        s.step(11)
+        assert np.array_equal(b.populations(i).cpu().numpy(), s.populations().cpu().numpy()), i

@@ -203,3 +203,41 @@ def test_kernel_timing_counts_tile_launches():
     assert torch.equal(a.populations(), b.populations())
     s = D.Simulation.from_case(case, kernel=D.KERNEL_STAGED)
     assert s.time_kernel(2)[1] == 0
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("tile", [1, 2, 3], ids=["square", "wide", "tall"])
+def test_tile_shapes_equal_staged_bitwise(D, tile):
+    """Every tile shape of the fused kernel gives the staged kernel's results
+    bit for bit (ragged tiles, walls, a grid one cell wider than a tile)."""
+    import torch
+    for case, steps in [(W.rt_case(30, ny=50, amp_frac=0.2), 12),
+                        (W.bubble_case(32, 48, eo=20.0, mo=1e-3), 12),
+                        (W.drop_case(n=31, radius=8.0), 9)]:
+        print("tile", tile, case.name, flush=True)
+        case.params["tile"] = tile
+        f = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)
+        assert f.tile == tile
+        s = D.Simulation.from_case(case, kernel=D.KERNEL_STAGED)
+        f.step(steps)
+        s.step(steps)
+        assert torch.equal(f.populations(), s.populations())
+
+
+@pytest.mark.gpu
+def test_tile_tuner_picks_a_shape(D):
+    """AUTO times the shapes at creation without advancing the state."""
+    import torch
+    case = W.rt_case(64)
+    a = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)  # tile AUTO
+    case.params["tile"] = D.TILE_SQUARE
+    b = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)
+    assert a.tile in (D.TILE_SQUARE, D.TILE_WIDE, D.TILE_TALL)
+    assert a.nstep == 0
+    assert torch.equal(a.populations(), b.populations())
+    a.step(5)
+    b.step(5)
+    assert torch.equal(a.populations(), b.populations())
+    with pytest.raises(D.DugksError):
+        case.params["tile"] = 7
+        D.Simulation.from_case(case)

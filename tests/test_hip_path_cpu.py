@@ -88,6 +88,22 @@ def test_fused_kernel_logic_bitwise_equal_to_oracle(oracle_mod, name):
     assert np.array_equal(pops, o.pops())
 
 
+@pytest.mark.parametrize("tile", [2, 3], ids=["wide30x6", "tall6x30"])
+@pytest.mark.parametrize("name", ["drop", "rt_walls_ragged", "bubble_four_walls",
+                                  "single_cell", "tile_plus_one"])
+def test_fused_tile_shapes_bitwise_equal_to_oracle(oracle_mod, name, tile):
+    """The wide (30 x 6) and tall (6 x 30) tile shapes give the oracle's
+    results bit for bit, like the square one (ragged edges, walls, periodic
+    wrap inside one tile)."""
+    make, steps = FUSED_CASES[name]
+    case = make()
+    case.params["tile"] = tile
+    pops, _ = _emu.run(case, steps, kernel=2)
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    assert np.array_equal(pops, o.pops())
+
+
 def test_general_lattice_speed_kernel_logic(oracle_mod):
     """RT != 1/3 (c != 1) runs the general-direction code of both kernels."""
     case = W.drop_case(n=20, radius=5.0)
