@@ -23,8 +23,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # 256 x 1024 workload, from FETCH_SIZE / WRITE_SIZE counters scaled by a
 # plain copy (profiles/fused_rt256x1024_fp64_traffic.md).  Valid only while
 # the kernel sources hash to the measured version.
-TRAFFIC = {"workload": "rt256x1024", "precision": "fp64", "src_sha": "563dae05102bf41a",
-           "bytes_per_launch": 151.05e6}
+TRAFFIC = {"workload": "rt256x1024", "precision": "fp64", "tile": 1, "src_sha": "9c8c740ac4c9136a",
+           "bytes_per_launch": 150.99e6}
 
 FP64_VEC_PEAK_TF = 78.6    # MI355X FP64 vector
 FP32_VEC_PEAK_TF = 157.3
@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--workload", default="rt256x1024")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
     ap.add_argument("--kernel", choices=("auto", "staged", "fused"), default="auto")
+    ap.add_argument("--tile", choices=("auto", "square", "wide", "tall"), default="square",
+                    help="tile shape of the headline run (auto: timed at creation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
@@ -215,6 +217,8 @@ def main():
     case = workload(args.workload)
     prec = D.FP64 if args.precision == "fp64" else D.FP32_STATE
     kern = {"auto": D.KERNEL_AUTO, "staged": D.KERNEL_STAGED, "fused": D.KERNEL_FUSED}[args.kernel]
+    case.params["tile"] = {"auto": D.TILE_AUTO, "square": D.TILE_SQUARE, "wide": D.TILE_WIDE,
+                           "tall": D.TILE_TALL}[args.tile]
     sim = D.Simulation.from_case(case, precision=prec, kernel=kern)
     stream = sim.stream
     cells = case.nx * case.ny
@@ -244,7 +248,7 @@ def main():
     achieved = bytes_per_cell * cells / (kernel_ms / 1e3) / 1e9
     traffic = None
     if (fused and prec == D.FP64 and args.workload == TRAFFIC["workload"]
-            and kernel_src_sha() == TRAFFIC["src_sha"]):
+            and sim.tile == TRAFFIC["tile"] and kernel_src_sha() == TRAFFIC["src_sha"]):
         traffic = TRAFFIC["bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -255,7 +259,7 @@ def main():
             "algorithmic_bytes_per_cell": bytes_per_cell,
             "step_effective_gbs": round(bytes_per_cell * cells / (ms_per_step / 1e3) / 1e9, 1),
             "launches_per_step": 3 if fused else 7}
-    if (VALU["fp64_flop_per_cell"] and fused and prec == D.FP64
+    if (VALU["fp64_flop_per_cell"] and fused and prec == D.FP64 and sim.tile == TRAFFIC["tile"]
             and args.workload == VALU["workload"] and kernel_src_sha() == VALU["src_sha"]):
         tf = VALU["fp64_flop_per_cell"] * cells / (kernel_ms / 1e3) / 1e12
         roof_alu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VEC_PEAK_TF,

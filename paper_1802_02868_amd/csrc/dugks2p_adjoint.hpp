@@ -122,7 +122,7 @@ struct AdjWork {
   const double *lam;  // 18 planes: adjoint of the state after the step
   double *out;        // 18 planes: adjoint of the state before the step
   double *xs, *ys;    // face records: NFS planes of xplane / yplane
-  double *ab, *gxb, *gyb;  // per cell: bar+ adjoint and its gradient adjoints (18 planes each)
+  double *gxb, *gyb;  // per cell: adjoints of the population gradients (18 planes each)
   double *fb;         // NFB planes of per-cell field adjoints and parameter partials
   double *pacc;       // 3 planes: per-cell sums over steps of the kappa, gx, gy partials
 };
@@ -402,7 +402,7 @@ struct FAdjFace {
 // expansion) and of the face fields.
 struct FaceSide {
   bool wall;
-  double wgt, sg, off;
+  double wgt, sg, off, wa;  // wa = 1 at a wall face, else 0
 };
 
 template <int A>
@@ -414,32 +414,32 @@ DFN FaceSide face_side(const Consts &K, int k, int s) {
     f.wgt = 1.0;
     f.sg = 0.0;
     f.off = ax_fl(ax, k) < 0 ? ax.foffr[k] : ax.foffl[k];
+    f.wa = 1.0;
   } else {
     f.wgt = s == 0 ? ax.fwl[k] : ax.fwr[k];
     f.sg = (s == 0 ? -1.0 : 1.0) * ax.finv[k];
     f.off = 0.0;
+    f.wa = 0.0;
   }
   return f;
 }
 
 // Contribution of a face's bar adjoint (population q) to the cell's bar+
-// adjoint ab and to the adjoints of its population gradients g[0], g[1].
+// adjoint and to the adjoints of its population gradients g[0], g[1].
+// Interior face: bar = wl AL + wr AR - h (xn (AR - AL) inv + xt (wl GtL +
+// wr GtR)); wall face: bar = A + off Gn - h (xn Gn + xt Gt).  One branch-free
+// form covers both (wgt = 1, sg = 0, wa = 1 at a wall).
 template <int A>
-DFN void face_pop_back(const Consts &K, const FaceSide &f, int q, double bb, double &ab,
-                       double g[2]) {
+DFN double face_ab_back(const Consts &K, const FaceSide &f, int q, double bb) {
+  const double xn = A == 0 ? K.xi0[q % 9] : K.xi1[q % 9];
+  return f.wgt * bb + f.sg * (-K.h * xn * bb);
+}
+template <int A>
+DFN void face_grad_back(const Consts &K, const FaceSide &f, int q, double bb, double g[2]) {
   const int i = q % 9;
   const double xn = A == 0 ? K.xi0[i] : K.xi1[i], xt = A == 0 ? K.xi1[i] : K.xi0[i];
-  const double h = K.h;
-  if (f.wall) {
-    // bar = A + off Gn - h (xn Gn + xt Gt)
-    ab += bb;
-    g[A] += (f.off - h * xn) * bb;
-    g[1 - A] += -h * xt * bb;
-  } else {
-    // bar = wl AL + wr AR - h (xn (AR - AL) inv + xt (wl GtL + wr GtR))
-    ab += f.wgt * bb + f.sg * (-h * xn * bb);
-    g[1 - A] += f.wgt * (-h * xt * bb);
-  }
+  g[A] += f.wa * ((f.off - K.h * xn) * bb);
+  g[1 - A] += f.wgt * (-K.h * xt * bb);
 }
 
 // Contribution of a face's field adjoints to the cell fields
@@ -488,9 +488,9 @@ DFN CellFaces cell_faces(const Consts &K, int i, int j) {
   return f;
 }
 
-// Gather of the bar adjoints of a cell's four faces: the adjoint of bar+ at
-// the cell (including the 4/3 bar+ of tilde+, eq. relations2) and of its
-// population gradients.
+// Gather of the adjoints of a cell's population gradients from the bar
+// adjoints of its four faces (the cell's own bar+ adjoint is formed where it
+// is used, in FAdjCell).
 struct FAdjGather {
   Consts K;
   AdjWork a;
@@ -501,18 +501,28 @@ struct FAdjGather {
     const FaceSide ss = face_side<1>(K, F.js, 1), sn = face_side<1>(K, F.jn, 0);
 #pragma unroll
     for (int q = 0; q < 18; ++q) {
-      double ab = (4.0 / 3.0) * a.lam[q * P + c];
       double g[2] = {0.0, 0.0};
-      face_pop_back<0>(K, sw, q, a.xs[(FS_B + q) * K.xplane + F.fw], ab, g);
-      face_pop_back<0>(K, se, q, a.xs[(FS_B + q) * K.xplane + F.fe], ab, g);
-      face_pop_back<1>(K, ss, q, a.ys[(FS_B + q) * K.yplane + F.fs], ab, g);
-      face_pop_back<1>(K, sn, q, a.ys[(FS_B + q) * K.yplane + F.fn], ab, g);
-      a.ab[q * P + c] = ab;
+      face_grad_back<0>(K, sw, q, a.xs[(FS_B + q) * K.xplane + F.fw], g);
+      face_grad_back<0>(K, se, q, a.xs[(FS_B + q) * K.xplane + F.fe], g);
+      face_grad_back<1>(K, ss, q, a.ys[(FS_B + q) * K.yplane + F.fs], g);
+      face_grad_back<1>(K, sn, q, a.ys[(FS_B + q) * K.yplane + F.fn], g);
       a.gxb[q * P + c] = g[0];
       a.gyb[q * P + c] = g[1];
     }
   }
 };
+
+// The cell's bar+ adjoint: the 4/3 bar+ of tilde+ (eq. relations2) and its
+// four faces' reconstruction.
+DFN double cell_ab(const Consts &K, const AdjWork &a, const CellFaces &F, const FaceSide fs[4],
+                   i64 c, int q) {
+  double ab = (4.0 / 3.0) * a.lam[q * K.plane + c];
+  ab += face_ab_back<0>(K, fs[0], q, a.xs[(FS_B + q) * K.xplane + F.fw]);
+  ab += face_ab_back<0>(K, fs[1], q, a.xs[(FS_B + q) * K.xplane + F.fe]);
+  ab += face_ab_back<1>(K, fs[2], q, a.ys[(FS_B + q) * K.yplane + F.fs]);
+  ab += face_ab_back<1>(K, fs[3], q, a.ys[(FS_B + q) * K.yplane + F.fn]);
+  return ab;
+}
 
 // Adjoint of the population gradients and of Step 2 at a cell (eqs.
 // relations1 and relations2), one direction at a time, plus the face-field
@@ -534,13 +544,18 @@ struct FAdjCell {
     const double den = 1.0 / (2.0 * tf + K.dt);
     const double fca = (2.0 * tf - K.h) * den, fcb = 3.0 * K.h * den, fcc = 3.0 * tf * K.h * den;
     double fcab = 0.0, fcbb = 0.0, fccb = 0.0, uub = 0.0;
+    const CellFaces F = cell_faces(K, i, j);
+    const FaceSide fs[4] = {face_side<0>(K, F.iw, 1), face_side<0>(K, F.ie, 0),
+                            face_side<1>(K, F.js, 1), face_side<1>(K, F.jn, 0)};
 #pragma unroll 1
     for (int i2 = 0; i2 < 9; ++i2) {
       const int qf = i2, qg = 9 + i2;
       double feq, geq, ff, fg;
       point_eq1<double>(K, m, uu, i2, feq, geq, ff, fg);
-      const double obf = a.ab[qf * P + c] + tw_apply(tx, a.gxb + qf * P) + tw_apply(ty, a.gyb + qf * P);
-      const double obg = a.ab[qg * P + c] + tw_apply(tx, a.gxb + qg * P) + tw_apply(ty, a.gyb + qg * P);
+      const double obf = cell_ab(K, a, F, fs, c, qf) + tw_apply(tx, a.gxb + qf * P) +
+                         tw_apply(ty, a.gyb + qf * P);
+      const double obg = cell_ab(K, a, F, fs, c, qg) + tw_apply(tx, a.gxb + qg * P) +
+                         tw_apply(ty, a.gyb + qg * P);
       // tilde+ = 4/3 bar+ - 1/3 tilde: the 4/3 part is in ab
       a.out[qf * P + c] = fca * obf - (1.0 / 3.0) * a.lam[qf * P + c];
       a.out[qg * P + c] = K.gca * obg - (1.0 / 3.0) * a.lam[qg * P + c];
@@ -557,14 +572,13 @@ struct FAdjCell {
     double dtp, dtr;
     tauf_grad(K, m.phi, m.rho, dtp, dtr);
     // face-field adjoints of the four faces
-    const CellFaces F = cell_faces(K, i, j);
     double fv[12];
 #pragma unroll
     for (int e = 0; e < 12; ++e) fv[e] = 0.0;
-    face_field_back<0>(face_side<0>(K, F.iw, 1), 1, a.xs + F.fw, K.xplane, fv);
-    face_field_back<0>(face_side<0>(K, F.ie, 0), 0, a.xs + F.fe, K.xplane, fv);
-    face_field_back<1>(face_side<1>(K, F.js, 1), 1, a.ys + F.fs, K.yplane, fv);
-    face_field_back<1>(face_side<1>(K, F.jn, 0), 0, a.ys + F.fn, K.yplane, fv);
+    face_field_back<0>(fs[0], 1, a.xs + F.fw, K.xplane, fv);
+    face_field_back<0>(fs[1], 0, a.xs + F.fe, K.xplane, fv);
+    face_field_back<1>(fs[2], 1, a.ys + F.fs, K.yplane, fv);
+    face_field_back<1>(fs[3], 0, a.ys + F.fn, K.yplane, fv);
     double *fb = a.fb;
     fb[FB_MU * P + c] = fv[0] + mb.mu;
     fb[FB_D * P + c] = fv[1] + mb.D;
@@ -767,7 +781,7 @@ struct AdjLayout {
   size_t field_bytes;  // one cell plane, padded
   size_t slot_bytes;   // one tape slot: 16 fields + bar+
   size_t state_bytes;  // 18 planes
-  size_t states, tape, dummy, facex, facey, fwork, lam[2], xs, ys, ab, gxb, gyb, fb, pacc, red;
+  size_t states, tape, dummy, facex, facey, fwork, lam[2], xs, ys, gxb, gyb, fb, pacc, red;
   size_t total;
   int mseg;
 };
@@ -805,8 +819,6 @@ inline AdjLayout make_adj_layout(const Consts &K, const AxisHost &ax, const Axis
   off += align256(NFS * sizeof(double) * (size_t)K.xplane);
   L.ys = off;
   off += align256(NFS * sizeof(double) * (size_t)K.yplane);
-  L.ab = off;
-  off += L.state_bytes;
   L.gxb = off;
   off += L.state_bytes;
   L.gyb = off;
@@ -856,7 +868,6 @@ struct AdjBufs {
     a.out = lam(1 - in);
     a.xs = (double *)(base + L.xs);
     a.ys = (double *)(base + L.ys);
-    a.ab = (double *)(base + L.ab);
     a.gxb = (double *)(base + L.gxb);
     a.gyb = (double *)(base + L.gyb);
     a.fb = (double *)(base + L.fb);
