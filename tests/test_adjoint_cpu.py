@@ -106,3 +106,19 @@ def test_adjoint_linear_in_lam():
     c = _emu.adjoint(case, steps, mseg, 2.0 * l1 - 3.0 * l2)
     assert np.allclose(c[1], 2.0 * a[1] - 3.0 * b[1], rtol=1e-11, atol=1e-11 * np.abs(c[1]).max())
     assert np.allclose(c[2], 2.0 * a[2] - 3.0 * b[2], rtol=1e-10)
+
+
+def test_adjoint_of_conserved_mass():
+    """sum phi |V| is conserved exactly by the flux-form update (periodic
+    axes and bounce-back walls), so for J = sum phi(T) |V| the adjoint must
+    give dJ/dphi0 = |V| and no parameter dependence.  (A structural check of
+    the update, transform and wall adjoints; on its own it does not see
+    mistakes in the paths that this J weights by zero.)"""
+    for case, steps, m in [(W.rt_case(16, 64), 40, 10), (W.drop_case(24, radius=6.0), 30, 7),
+                           (W.poiseuille_case(4, 32), 20, 6)]:
+        V = np.outer(np.diff(case.y_faces), np.diff(case.x_faces))
+        lam = np.zeros((18, case.ny, case.nx))
+        lam[9:] = V
+        _, g0, g3 = _emu.adjoint(case, steps, m, lam)
+        assert np.max(np.abs(g0 - V) / V) <= 1e-12, case.name
+        assert np.abs(g3).max() <= 1e-12, case.name

@@ -1,0 +1,131 @@
+"""Parity at the benchmark plan's full sizes, in the launch configuration
+bench.py times (fused kernel, square tiles; batch with its tuned tile; the
+adjoint with checkpoints every 50 steps), against the oracle: bit for bit
+for FP64, within 1e-4 for the FP32 state, and the adjoint against the
+oracle's central differences on the 512 x 2048 grid."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1802_02868_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1802_02868_amd import dugks2p
+    return dugks2p
+
+
+def test_rt256x1024_fp64_bitwise(D, oracle_mod):
+    case = W.rt_case(256)
+    case.params["tile"] = D.TILE_SQUARE
+    steps = 60
+    print("full size fp64", case.name, steps, flush=True)
+    s = D.Simulation.from_case(case, precision=D.FP64)
+    s.step(steps)
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    assert np.array_equal(s.populations().cpu().numpy(), o.pops())
+
+
+def test_rt256x1024_fp32_state_within_tolerance(D, oracle_mod):
+    case = W.rt_case(256)
+    case.params["tile"] = D.TILE_SQUARE
+    steps = 60
+    print("full size fp32", case.name, steps, flush=True)
+    s = D.Simulation.from_case(case, precision=D.FP32_STATE)
+    s.step(steps)
+    m = s.moments()
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    mo = o.moments()
+    for f in ("phi", "ux", "uy"):
+        a = m[f].cpu().numpy()
+        err = np.abs(a - mo[f]).max() / np.abs(mo[f]).max()
+        print("  %s rel err %.3e" % (f, err))
+        assert err <= 1e-4, f
+
+
+def test_bubble_batch_sampled_instances(D, oracle_mod):
+    """The 48-instance bubble batch (FP32 state, tuned tile shape): sampled
+    instances against the oracle."""
+    cases = W.bubble_batch(48)
+    steps = 16
+    b = D.BatchSimulation(cases, precision=D.FP32_STATE)
+    b.step(steps)
+    for i in (0, 17, 47):
+        c = cases[i]
+        print("batch instance", i, c.name, "tile", b.tile, flush=True)
+        phi = b.populations(i).cpu().numpy()[9:].sum(0)
+        o = oracle_mod.Oracle.from_case(c)
+        o.step(steps)
+        po = o.pops()[9:].sum(0)
+        err = np.abs(phi - po).max() / np.abs(po).max()
+        print("  phi rel err %.3e" % err)
+        assert err <= 1e-4
+        assert b.monitors(i, raise_nonfinite=False)[4] == 0
+
+
+def test_adjoint_rt512x2048_against_oracle_fd(D, oracle_mod):
+    """The adjoint configuration's grid (512 x 2048, 64 interface modes,
+    checkpoints every 50 steps) over 100 steps: dJ along a seeded unit
+    direction in scaled coordinates against the oracle's central difference
+    (step 1e-4); and the exact conservation of sum phi (walls and a flux-form
+    update): for J = sum phi(T), dJ/dphi0 = 1 and dJ/d(kappa, g) = 0."""
+    import torch
+    from paper_1802_02868_amd.rollout import rollout
+    case = W.rt_case(512)
+    steps, every = 100, 50
+    a0 = W.rt_mode_amplitudes(512, 64, seed=2024)
+    sig = 1e-3 * 512
+    k0, g0 = case.params["kappa"], case.params["gy"]
+    o_ref = oracle_mod.Oracle.from_case(dataclasses.replace(
+        case, phi0=W.rt_interface_phi0(W.rt_mode_amplitudes(512, 64, seed=77), case)))
+    o_ref.step(steps)
+    ref = o_ref.pops()[9:].sum(0)
+    o_ref.close()
+    print("adjoint full size", case.name, steps, every, flush=True)
+    a = torch.tensor(a0, dtype=torch.float64, device="cuda", requires_grad=True)
+    kap = torch.tensor(k0, dtype=torch.float64, device="cuda", requires_grad=True)
+    g = torch.tensor([0.0, g0], dtype=torch.float64, device="cuda", requires_grad=True)
+    pops = rollout(W.rt_interface_phi0(a, case), kap, g, case, steps, every)
+    R = torch.from_numpy(ref).cuda()
+    J = ((pops[9:].sum(0) - R) ** 2).sum()
+    J.backward()
+    grad_s = np.concatenate([a.grad.cpu().numpy() * sig, [float(kap.grad) * k0],
+                             g.grad.cpu().numpy() * abs(g0)])
+    theta = np.concatenate([a0 / sig, [1.0], [0.0, g0 / abs(g0)]])
+    d = np.random.default_rng(31).standard_normal(theta.size)
+    d /= np.linalg.norm(d)
+    eps = 1e-4
+    out = []
+    for th in (theta + eps * d, theta - eps * d):
+        c = dataclasses.replace(case, phi0=W.rt_interface_phi0(th[:64] * sig, case))
+        o = oracle_mod.Oracle.from_case(c, kappa=th[64] * k0, gx=th[65] * abs(g0),
+                                        gy=th[66] * abs(g0))
+        o.step(steps)
+        out.append(o.pops()[9:].sum(0))
+        o.close()
+    pp, pm = out
+    fd = float(np.sum((pp - pm) * (pp + pm - 2.0 * ref))) / (2 * eps)
+    ad = float(grad_s @ d)
+    print("  direction: ad %.10e fd %.10e" % (ad, fd), flush=True)
+    assert abs(ad - fd) <= 1e-6 * abs(fd)
+    # conservation: J = sum phi(T) on the uniform mesh
+    a2 = torch.tensor(a0, dtype=torch.float64, device="cuda")
+    p0 = W.rt_interface_phi0(a2, case).requires_grad_(True)
+    k2 = torch.tensor(k0, dtype=torch.float64, device="cuda", requires_grad=True)
+    g2 = torch.tensor([0.0, g0], dtype=torch.float64, device="cuda", requires_grad=True)
+    pops2 = rollout(p0, k2, g2, case, steps, every)
+    pops2[9:].sum().backward()
+    gp = p0.grad.cpu().numpy()
+    print("  conservation: max|dJ/dphi0 - 1| %.3e, dJ/dkappa %.3e, dJ/dg %s" % (
+        np.abs(gp - 1.0).max(), float(k2.grad), g2.grad.cpu().numpy()), flush=True)
+    assert np.abs(gp - 1.0).max() <= 1e-10
+    assert abs(float(k2.grad)) * k0 <= 1e-10 and np.abs(g2.grad.cpu().numpy()).max() * abs(g0) <= 1e-10
