@@ -258,7 +258,7 @@ def main():
             "timed_launches": klaunch,
             "algorithmic_bytes_per_cell": bytes_per_cell,
             "step_effective_gbs": round(bytes_per_cell * cells / (ms_per_step / 1e3) / 1e9, 1),
-            "launches_per_step": 3 if fused else 7}
+            "launches_per_step": 2 if fused else 7}
     if (VALU["fp64_flop_per_cell"] and fused and prec == D.FP64 and sim.tile == TRAFFIC["tile"]
             and args.workload == VALU["workload"] and kernel_src_sha() == VALU["src_sha"]):
         tf = VALU["fp64_flop_per_cell"] * cells / (kernel_ms / 1e3) / 1e12

@@ -177,6 +177,7 @@ struct dugks2p {
   double *mon_part, *mon_out;
   int64_t nstep;
   KernelTimer kt;
+  bool sums_ok;  // w.phi, s0, jx, jy hold the sums of state[cur]
 };
 
 namespace {
@@ -222,9 +223,10 @@ int enqueue_step(dugks2p *h, int shape) {
     with_tile_shape(shape, h->K.unit, [&](auto sh) {
       using S = decltype(sh);
       if (h->K.unit)
-        seq_fused_step<GpuEx, IoF64, double, true, S>(ex, h->K, h->w, src, dst);
+        seq_fused_step<GpuEx, IoF64, double, true, S>(ex, h->K, h->w, src, dst, h->sums_ok);
       else
-        seq_fused_step<GpuEx, IoF64, double, false, TileSq>(ex, h->K, h->w, src, dst);
+        seq_fused_step<GpuEx, IoF64, double, false, TileSq>(ex, h->K, h->w, src, dst,
+                                                            h->sums_ok);
     });
   } else {
     const IoE32 src = io_e32(h->state[h->cur], h->K, h->L);
@@ -232,13 +234,16 @@ int enqueue_step(dugks2p *h, int shape) {
     with_tile_shape(shape, h->K.unit, [&](auto sh) {
       using S = decltype(sh);
       if (h->K.unit)
-        seq_fused_step<GpuEx, IoE32, double, true, S>(ex, h->K, h->w, src, dst);
+        seq_fused_step<GpuEx, IoE32, double, true, S>(ex, h->K, h->w, src, dst, h->sums_ok);
       else
-        seq_fused_step<GpuEx, IoE32, double, false, TileSq>(ex, h->K, h->w, src, dst);
+        seq_fused_step<GpuEx, IoE32, double, false, TileSq>(ex, h->K, h->w, src, dst,
+                                                            h->sums_ok);
     });
   }
   if (ex.err != hipSuccess)
     return fail(DUGKS2P_EHIP, std::string("kernel launch: ") + hipGetErrorString(ex.err));
+  // a fused step leaves the sums of state[cur] in w (computed or kept)
+  if (h->kernel == DUGKS2P_KERNEL_FUSED) h->sums_ok = true;
   return DUGKS2P_OK;
 }
 
@@ -248,6 +253,9 @@ int launch_step(dugks2p *h) {
   if (rc) return rc;
   h->cur = 1 - h->cur;
   h->nstep++;
+  // the tile kernel wrote the new state's sums into the spare planes
+  if (h->kernel == DUGKS2P_KERNEL_FUSED) swap_sums(h->w);
+  else h->sums_ok = false;
   return DUGKS2P_OK;
 }
 
@@ -335,6 +343,7 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
                 : DUGKS2P_TILE_SQUARE;
   h->cur = 0;
   h->nstep = 0;
+  h->sums_ok = false;
   if (P->workspace) {
     h->ws = (unsigned char *)P->workspace;
     h->own_ws = false;
@@ -457,6 +466,7 @@ int dugks2p_get_populations(dugks2p *h, double *dst) {
 
 int dugks2p_set_populations(dugks2p *h, const double *src) {
   if (!h || !src) return fail(DUGKS2P_EINVAL, "NULL argument");
+  h->sums_ok = false;
   if (h->precision == DUGKS2P_FP64)
     hipLaunchKernelGGL(k_pops_in<IoF64>, dim3(1024), dim3(256), 0, h->stream, h->K, src,
                        io_f64(h->state[h->cur], h->K));
@@ -478,6 +488,7 @@ int dugks2p_get_state(dugks2p *h, void *dst) {
 
 int dugks2p_set_state(dugks2p *h, const void *src) {
   if (!h || !src) return fail(DUGKS2P_EINVAL, "NULL argument");
+  h->sums_ok = false;
   HIPCHK(hipMemcpyAsync(h->state[h->cur], src, h->L.state_bytes, hipMemcpyDeviceToDevice,
                         h->stream));
   return DUGKS2P_OK;

@@ -840,6 +840,7 @@ struct AdjBufs {
   Work tape(int n) const {
     unsigned char *s = base + L.tape + (size_t)n * L.slot_bytes;
     Work w;
+    memset(&w, 0, sizeof w);
     double **f[TAPE_FIELDS] = {&w.phi, &w.rho, &w.mu, &w.dphx, &w.dphy, &w.dmux, &w.dmuy, &w.D,
                                &w.Fx,  &w.Fy,  &w.ux, &w.uy,   &w.p,    &w.dpx,  &w.dpy,  &w.tauf};
     for (int k = 0; k < TAPE_FIELDS; ++k) *f[k] = (double *)(s + k * L.field_bytes);

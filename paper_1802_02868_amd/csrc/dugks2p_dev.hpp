@@ -184,6 +184,9 @@ DFN double sty(const Consts &K, const double *w3, const double *F, int i, int j)
 struct Work {
   double *phi, *rho, *mu, *dphx, *dphy, *dmux, *dmuy, *D, *Fx, *Fy, *ux, *uy, *p, *dpx, *dpy,
       *tauf, *s0, *jx, *jy;
+  // phi and the f~ sums of the state a fused step writes (NULL: not kept);
+  // the host swaps them with phi, s0, jx, jy when the step is committed
+  double *phin, *s0n, *jxn, *jyn;
   double *barp;   // 18 x plane
   double *facex;  // 18 x xplane: [q][j][k]
   double *facey;  // 18 x yplane: [q][k][i]
@@ -209,6 +212,14 @@ struct IoF64 {
   DFN void load_f(i64 c, double f[9]) const {
 #pragma unroll
     for (int q = 0; q < 9; ++q) f[q] = p[q * plane + c];
+  }
+  // what phi() and load_f() return after store(c, v)
+  DFN void stored(const double v[18], double &ph, double f[9]) const {
+    ph = 0.0;
+#pragma unroll
+    for (int q = 9; q < 18; ++q) ph += v[q];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = v[q];
   }
   // eq. phi: phi = sum_i g~_i, ascending i
   DFN double phi(i64 c) const {
@@ -255,6 +266,14 @@ struct IoE32 {
   DFN void load_f(i64 c, double fo[9]) const {
 #pragma unroll
     for (int q = 0; q < 9; ++q) fo[q] = (double)f[q * plane + c];
+  }
+  // what phi() and load_f() return after store(c, v)
+  DFN void stored(const double v[18], double &phv, double fo[9]) const {
+    phv = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) phv += v[9 + i];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fo[q] = (double)(float)v[q];
   }
   DFN double phi(i64 c) const { return ph[c]; }
 };

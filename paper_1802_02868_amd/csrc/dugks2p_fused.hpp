@@ -437,6 +437,18 @@ struct FusedTile {
         tv[q] = (double)(tilp - rx * (R)K.xi0[d] * (E - W) - ry * (R)K.xi1[d] * (N - Sf));
       }
     }
+    // phi and the f~ sums of the new state, as the next step would read them
+    if (w.phin) {
+      double ph, f[9], s0 = 0.0, jx, jy;
+      dst.stored(tv, ph, f);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) s0 += f[q];
+      xi_sums<double, U>(K, f, jx, jy);
+      w.phin[c] = ph;
+      w.s0n[c] = s0;
+      w.jxn[c] = jx;
+      w.jyn[c] = jy;
+    }
     dst.store(c, tv);
   }
 };
@@ -477,11 +489,24 @@ __global__ __launch_bounds__(NTHR) void k_fused_tile(Consts K, Work w, IO src, I
 
 // One fused time step (Ex: grid(functor, n0, n1) and tiles<IO, R, U, S>(...)).
 // U: unit lattice speed (RT = 1/3), chosen by the host; S: tile shape.
+// sums_ready: phi and the f~ sums of src are already in w (written by the
+// previous step's tile kernel).
 template <class Ex, class IO, class R, bool U, class S = TileSq>
-void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const IO &src, const IO &dst) {
-  ex.grid(FPhiSums<IO, U>{K, w, src}, K.nx, K.ny);
+void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const IO &src, const IO &dst,
+                    bool sums_ready = false) {
+  if (!sums_ready) ex.grid(FPhiSums<IO, U>{K, w, src}, K.nx, K.ny);
   ex.grid(FMacF{K, w}, K.nx, K.ny);
   ex.template tiles<IO, R, U, S>(K, w, src, dst);
+}
+
+// After a committed fused step the sums written for the new state become
+// the current ones.
+inline void swap_sums(Work &w) {
+  double *t;
+  t = w.phi; w.phi = w.phin; w.phin = t;
+  t = w.s0; w.s0 = w.s0n; w.s0n = t;
+  t = w.jx; w.jx = w.jxn; w.jxn = t;
+  t = w.jy; w.jy = w.jyn; w.jyn = t;
 }
 
 // Calls f(S{}) with the tile shape of a DUGKS2P_TILE_* value (1 square,

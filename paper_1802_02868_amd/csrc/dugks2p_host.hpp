@@ -302,7 +302,7 @@ inline Layout make_layout(const Consts &K, const AxisHost &ax, const AxisHost &a
   off += align256(L.state_bytes);
   L.state[1] = off;
   off += align256(L.state_bytes);
-  L.nwork = 19;
+  L.nwork = 23;
   L.work = off;
   off += L.nwork * align256(sizeof(double) * (size_t)K.plane);
   if (staged) {
@@ -374,11 +374,11 @@ inline Axis bind_axis(const AxisHost &a, unsigned char *base) {
 inline Work bind_work(const Layout &L, const Consts &K, unsigned char *base) {
   Work w;
   memset(&w, 0, sizeof w);
-  double **f[19] = {&w.phi, &w.rho, &w.mu, &w.dphx, &w.dphy, &w.dmux, &w.dmuy,
-                    &w.D,   &w.Fx,  &w.Fy, &w.ux,   &w.uy,   &w.p,    &w.dpx,
-                    &w.dpy, &w.tauf, &w.s0, &w.jx,  &w.jy};
+  double **f[23] = {&w.phi, &w.rho, &w.mu,  &w.dphx, &w.dphy, &w.dmux, &w.dmuy, &w.D,
+                    &w.Fx,  &w.Fy,  &w.ux,  &w.uy,   &w.p,    &w.dpx,  &w.dpy,  &w.tauf,
+                    &w.s0,  &w.jx,  &w.jy,  &w.phin, &w.s0n,  &w.jxn,  &w.jyn};
   const size_t fb = align256(sizeof(double) * (size_t)K.plane);
-  for (int k = 0; k < 19; ++k) *f[k] = (double *)(base + L.work + k * fb);
+  for (int k = 0; k < 23; ++k) *f[k] = (double *)(base + L.work + k * fb);
   if (L.barp) {
     w.barp = (double *)(base + L.barp);
     w.facex = (double *)(base + L.facex);

@@ -45,19 +45,25 @@ struct CpuEx {
 };
 }  // namespace
 
+// Fused steps as the runtime runs them: the sums kernel only before the
+// first step, then the tile kernel's own sums of the state it writes.
 template <class IO>
-static void run_steps(CpuEx &ex, const Consts &K, const Work &w, IO st[2], int &cur, bool fused,
+static void run_steps(CpuEx &ex, const Consts &K, Work &w, IO st[2], int &cur, bool fused,
                       long long nsteps, int shape) {
+  bool ready = false;
   for (long long n = 0; n < nsteps; ++n) {
     if (fused)
       with_tile_shape(shape, K.unit, [&](auto sh) {
         using S = decltype(sh);
         if (K.unit)
-          seq_fused_step<CpuEx, IO, double, true, S>(ex, K, w, st[cur], st[1 - cur]);
+          seq_fused_step<CpuEx, IO, double, true, S>(ex, K, w, st[cur], st[1 - cur], ready);
         else
-          seq_fused_step<CpuEx, IO, double, false, TileSq>(ex, K, w, st[cur], st[1 - cur]);
+          seq_fused_step<CpuEx, IO, double, false, TileSq>(ex, K, w, st[cur], st[1 - cur],
+                                                           ready);
       });
     cur = 1 - cur;
+    swap_sums(w);
+    ready = true;
   }
 }
 
