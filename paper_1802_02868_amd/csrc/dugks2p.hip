@@ -67,6 +67,11 @@ struct GpuEx {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess && err == hipSuccess) err = e;
   }
+  void macros(const Consts &K, const Work &w) {
+    const dim3 g((K.nx + MBX - 1) / MBX, (K.ny + MBY - 1) / MBY), b(MBX, MBY);
+    hipLaunchKernelGGL(k_macros, g, b, 0, s, K, w);
+    note(hipGetLastError());
+  }
   template <class IO, class R, bool U, class S>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);

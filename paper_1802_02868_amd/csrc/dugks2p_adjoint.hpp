@@ -810,7 +810,7 @@ inline AdjLayout make_adj_layout(const Consts &K, const AxisHost &ax, const Axis
   L.facey = off;
   off += align256(18 * sizeof(double) * (size_t)K.yplane);
   L.fwork = off;  // cell fields of the fused step that advances the state
-  off += 19 * L.field_bytes;
+  off += 23 * L.field_bytes;
   for (int b = 0; b < 2; ++b) {
     L.lam[b] = off;
     off += L.state_bytes;
@@ -856,10 +856,10 @@ struct AdjBufs {
   Work fused_work() const {
     Work w;
     memset(&w, 0, sizeof w);
-    double **f[19] = {&w.phi, &w.rho, &w.mu, &w.dphx, &w.dphy, &w.dmux, &w.dmuy,
-                      &w.D,   &w.Fx,  &w.Fy, &w.ux,   &w.uy,   &w.p,    &w.dpx,
-                      &w.dpy, &w.tauf, &w.s0, &w.jx,  &w.jy};
-    for (int k = 0; k < 19; ++k) *f[k] = (double *)(base + L.fwork + k * L.field_bytes);
+    double **f[23] = {&w.phi, &w.rho, &w.mu,  &w.dphx, &w.dphy, &w.dmux, &w.dmuy, &w.D,
+                      &w.Fx,  &w.Fy,  &w.ux,  &w.uy,   &w.p,    &w.dpx,  &w.dpy,  &w.tauf,
+                      &w.s0,  &w.jx,  &w.jy,  &w.phin, &w.s0n,  &w.jxn,  &w.jyn};
+    for (int k = 0; k < 23; ++k) *f[k] = (double *)(base + L.fwork + k * L.field_bytes);
     return w;
   }
   double *lam(int b) const { return (double *)(base + L.lam[b]); }
@@ -899,7 +899,7 @@ void seq_adjoint_segment(Ex &ex, const Consts &K, const AdjBufs &B, const double
   const AdjWork a0 = B.adj(0);
   ex.grid(FCopyPlanes{K, nullptr, a0.pacc, 3}, K.nx, K.ny);
   ex.grid(FCopyPlanes{K, lam_end, B.lam(0), 18}, K.nx, K.ny);
-  const Work wf = B.fused_work();
+  Work wf = B.fused_work();
   for (int n = 0; n < nsteps; ++n) {
     const Work w = B.tape(n);
     const double *src = n == 0 ? pops0 : B.state(n);
@@ -909,10 +909,13 @@ void seq_adjoint_segment(Ex &ex, const Consts &K, const AdjBufs &B, const double
     // the next state, from the fused step (bitwise equal to the staged one)
     if (n + 1 < nsteps) {
       const IoF64 a{(double *)src, K.plane}, b{B.state(n + 1), K.plane};
+      // after the first step the tile kernel keeps the sums of the state
+      // it writes
       if (K.unit)
-        seq_fused_step<Ex, IoF64, double, true>(ex, K, wf, a, b);
+        seq_fused_step<Ex, IoF64, double, true>(ex, K, wf, a, b, n > 0);
       else
-        seq_fused_step<Ex, IoF64, double, false>(ex, K, wf, a, b);
+        seq_fused_step<Ex, IoF64, double, false>(ex, K, wf, a, b, n > 0);
+      swap_sums(wf);
     }
   }
   int cur = 0;

@@ -299,10 +299,21 @@ struct FPhi {
 };
 
 // eq. chemicalpotential with the App. B Laplacian of phi at cell (i, j).
-DFN double mu_at(const Consts &K, const double *phi, int i, int j) {
-  const double ph = phi[(i64)j * K.ld + i];
-  const double lap = stx(K, K.ax[0].d2, phi, i, j) + sty(K, K.ax[1].d2, phi, i, j);
+// eq. chemicalpotential from phi at a cell (ph) and at its x neighbours
+// (xl, xh) and y neighbours (yl, yh), with the App. B second-derivative
+// weights of its column (wx) and row (wy).
+DFN double mu_from(const Consts &K, double ph, double xl, double xh, double yl, double yh,
+                   const double *wx, const double *wy) {
+  const double lap = (wx[0] * xl + wx[1] * ph + wx[2] * xh) + (wy[0] * yl + wy[1] * ph + wy[2] * yh);
   return K.c4b * (ph - K.phi_a) * (ph - K.phi_b) * (ph - K.phimid) - K.kappa * lap;
+}
+
+DFN double mu_at(const Consts &K, const double *phi, int i, int j) {
+  const Axis &X = K.ax[0], &Y = K.ax[1];
+  const i64 r = (i64)j * K.ld;
+  return mu_from(K, phi[r + i], phi[r + ax_lo(X, i)], phi[r + ax_hi(X, i)],
+                 phi[(i64)ax_lo(Y, j) * K.ld + i], phi[(i64)ax_hi(Y, j) * K.ld + i],
+                 X.d2 + 3 * i, Y.d2 + 3 * j);
 }
 
 // eq. chemicalpotential; grad phi.

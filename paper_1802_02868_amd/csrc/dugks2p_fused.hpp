@@ -64,35 +64,56 @@ struct FPhiSums {
   DFN void operator()(int i, int j) const { phi_sums_at<IO, U>(K, w, st, i, j); }
 };
 
-// mu, grad mu, D, F, eq. u and eq. P at a cell.
-DFN void macros_at(const Consts &K, const Work &w, int i, int j) {
-  const i64 c = (i64)j * K.ld + i;
-  const Axis &X = K.ax[0], &Y = K.ax[1];
-  const double mc = mu_at(K, w.phi, i, j);
-  const double mxl = mu_at(K, w.phi, ax_lo(X, i), j), mxh = mu_at(K, w.phi, ax_hi(X, i), j);
-  const double myl = mu_at(K, w.phi, i, ax_lo(Y, j)), myh = mu_at(K, w.phi, i, ax_hi(Y, j));
-  const double *a1 = X.d1 + 3 * i, *a2 = X.d2 + 3 * i, *b1 = Y.d1 + 3 * j, *b2 = Y.d2 + 3 * j;
+// grad mu, D = lambda lap mu, F, eq. u and eq. P at a cell from mu and phi
+// at the cell (mc, ph) and its x / y neighbours, the f~ sums s0, jx, jy and
+// the App. B first / second derivative weights of its column (a1, a2) and
+// row (b1, b2).
+struct CellMac {
+  double D, Fx, Fy, ux, uy, p;
+};
+
+DFN CellMac macros_from(const Consts &K, double mc, double mxl, double mxh, double myl,
+                        double myh, double ph, double pxl, double pxh, double pyl, double pyh,
+                        double s0, double jx, double jy, const double *a1, const double *a2,
+                        const double *b1, const double *b2) {
+  CellMac r;
   const double dmux = a1[0] * mxl + a1[1] * mc + a1[2] * mxh;
   const double dmuy = b1[0] * myl + b1[1] * mc + b1[2] * myh;
   const double lapmu =
       (a2[0] * mxl + a2[1] * mc + a2[2] * mxh) + (b2[0] * myl + b2[1] * mc + b2[2] * myh);
-  const double D = K.mobility * lapmu;
-  const double ph = w.phi[c];
+  r.D = K.mobility * lapmu;
   const double rh = rho_of<double>(K, ph);
-  const double Fx = -ph * dmux + (rh - K.rho_ref) * K.gx;
-  const double Fy = -ph * dmuy + (rh - K.rho_ref) * K.gy;
+  r.Fx = -ph * dmux + (rh - K.rho_ref) * K.gx;
+  r.Fy = -ph * dmuy + (rh - K.rho_ref) * K.gy;
   const double icr = 1.0 / (K.cs2 * rh);
-  const double ux = (w.jx[c] + K.hdtcs2 * Fx) * icr;
-  const double uy = (w.jy[c] + K.hdtcs2 * Fy) * icr;
-  const double grx = K.drho * stx(K, X.d1, w.phi, i, j);
-  const double gry = K.drho * sty(K, Y.d1, w.phi, i, j);
+  r.ux = (jx + K.hdtcs2 * r.Fx) * icr;
+  r.uy = (jy + K.hdtcs2 * r.Fy) * icr;
+  const double grx = K.drho * (a1[0] * pxl + a1[1] * ph + a1[2] * pxh);
+  const double gry = K.drho * (b1[0] * pyl + b1[1] * ph + b1[2] * pyh);
+  r.p = s0 + K.hdtcs2 * (r.ux * grx + r.uy * gry - K.gam * rh * r.D);
+  return r;
+}
+
+// mu, grad mu, D, F, eq. u and eq. P at a cell (global fields).
+DFN void macros_at(const Consts &K, const Work &w, int i, int j) {
+  const i64 c = (i64)j * K.ld + i;
+  const Axis &X = K.ax[0], &Y = K.ax[1];
+  const int il = ax_lo(X, i), ih = ax_hi(X, i), jl = ax_lo(Y, j), jh = ax_hi(Y, j);
+  const double mc = mu_at(K, w.phi, i, j);
+  const double mxl = mu_at(K, w.phi, il, j), mxh = mu_at(K, w.phi, ih, j);
+  const double myl = mu_at(K, w.phi, i, jl), myh = mu_at(K, w.phi, i, jh);
+  const i64 r = (i64)j * K.ld;
+  const CellMac m = macros_from(K, mc, mxl, mxh, myl, myh, w.phi[c], w.phi[r + il],
+                                w.phi[r + ih], w.phi[(i64)jl * K.ld + i],
+                                w.phi[(i64)jh * K.ld + i], w.s0[c], w.jx[c], w.jy[c],
+                                X.d1 + 3 * i, X.d2 + 3 * i, Y.d1 + 3 * j, Y.d2 + 3 * j);
   w.mu[c] = mc;
-  w.D[c] = D;
-  w.Fx[c] = Fx;
-  w.Fy[c] = Fy;
-  w.ux[c] = ux;
-  w.uy[c] = uy;
-  w.p[c] = w.s0[c] + K.hdtcs2 * (ux * grx + uy * gry - K.gam * rh * D);
+  w.D[c] = m.D;
+  w.Fx[c] = m.Fx;
+  w.Fy[c] = m.Fy;
+  w.ux[c] = m.ux;
+  w.uy[c] = m.uy;
+  w.p[c] = m.p;
 }
 
 struct FMacF {
@@ -100,6 +121,74 @@ struct FMacF {
   Work w;
   DFN void operator()(int i, int j) const { macros_at(K, w, i, j); }
 };
+
+DFN int wrapi(int g, int n);
+
+// The same cell macros over a 64 x 4 block of cells: mu once on the block
+// and a one-cell ring in LDS (instead of at every cell's four neighbours),
+// then grad mu, D, F, u and p of the block's cells.  Two phases separated by
+// a workgroup barrier.
+enum { MBX = 64, MBY = 4 };
+struct MacLds {
+  double mu[MBY + 2][MBX + 2];
+};
+
+struct MacBlock {
+  const Consts &K;
+  const Work &w;
+  int x0, y0;
+  MacLds *L;
+  // global index of window offset g along an axis, or -1 outside a wall domain
+  DFN int gcol(int g, int n, int bc) const {
+    if (bc == 0) return wrapi(g, n);
+    return (g >= 0 && g < n) ? g : -1;
+  }
+  DFN void p0(int tid) const {
+    for (int e = tid; e < (MBX + 2) * (MBY + 2); e += MBX * MBY) {
+      const int lx = e % (MBX + 2), ly = e / (MBX + 2);
+      const int gx = gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
+      const int gy = gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
+      if (gx < 0 || gy < 0) continue;
+      L->mu[ly][lx] = mu_at(K, w.phi, gx, gy);
+    }
+  }
+  DFN void p1(int tid) const {
+    const int tx = tid % MBX, ty = tid / MBX;
+    const int i = x0 + tx, j = y0 + ty;
+    if (i >= K.nx || j >= K.ny) return;
+    const Axis &X = K.ax[0], &Y = K.ax[1];
+    // neighbours: the adjacent window positions, or the cell itself at a wall
+    const int sxl = (X.bc != 0 && i == 0) ? 0 : 1, sxh = (X.bc != 0 && i == X.n - 1) ? 0 : 1;
+    const int syl = (Y.bc != 0 && j == 0) ? 0 : 1, syh = (Y.bc != 0 && j == Y.n - 1) ? 0 : 1;
+    const int mx = tx + 1, my = ty + 1;
+    const i64 c = (i64)j * K.ld + i, r = (i64)j * K.ld;
+    const int il = ax_lo(X, i), ih = ax_hi(X, i), jl = ax_lo(Y, j), jh = ax_hi(Y, j);
+    const double mc = L->mu[my][mx];
+    const CellMac m = macros_from(
+        K, mc, L->mu[my][mx - sxl], L->mu[my][mx + sxh], L->mu[my - syl][mx],
+        L->mu[my + syh][mx], w.phi[c], w.phi[r + il], w.phi[r + ih], w.phi[(i64)jl * K.ld + i],
+        w.phi[(i64)jh * K.ld + i], w.s0[c], w.jx[c], w.jy[c], X.d1 + 3 * i, X.d2 + 3 * i,
+        Y.d1 + 3 * j, Y.d2 + 3 * j);
+    w.mu[c] = mc;
+    w.D[c] = m.D;
+    w.Fx[c] = m.Fx;
+    w.Fy[c] = m.Fy;
+    w.ux[c] = m.ux;
+    w.uy[c] = m.uy;
+    w.p[c] = m.p;
+  }
+};
+
+#if defined(__HIPCC__)
+__global__ __launch_bounds__(MBX * MBY) void k_macros(Consts K, Work w) {
+  __shared__ MacLds L;
+  const MacBlock mb{K, w, (int)blockIdx.x * MBX, (int)blockIdx.y * MBY, &L};
+  const int tid = threadIdx.y * MBX + threadIdx.x;
+  mb.p0(tid);
+  __syncthreads();
+  mb.p1(tid);
+}
+#endif
 
 // LDS of one tile.  A (bar+ on the tile and its ring) is dead once the faces
 // are computed; the face fluxes then reuse its space.
@@ -495,7 +584,7 @@ template <class Ex, class IO, class R, bool U, class S = TileSq>
 void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const IO &src, const IO &dst,
                     bool sums_ready = false) {
   if (!sums_ready) ex.grid(FPhiSums<IO, U>{K, w, src}, K.nx, K.ny);
-  ex.grid(FMacF{K, w}, K.nx, K.ny);
+  ex.macros(K, w);
   ex.template tiles<IO, R, U, S>(K, w, src, dst);
 }
 
@@ -527,7 +616,7 @@ void with_tile_shape(int shape, bool unit, F &&f) {
 template <class Ex, class IO>
 void seq_moments(Ex &ex, const Consts &K, const Work &w, const IO &src) {
   ex.grid(FPhiSums<IO, false>{K, w, src}, K.nx, K.ny);
-  ex.grid(FMacF{K, w}, K.nx, K.ny);
+  ex.macros(K, w);
 }
 
 }  // namespace dg
