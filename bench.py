@@ -23,8 +23,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # 256 x 1024 workload, from FETCH_SIZE / WRITE_SIZE counters scaled by a
 # plain copy (profiles/fused_rt256x1024_fp64_traffic.md).  Valid only while
 # the kernel sources hash to the measured version.
-TRAFFIC = {"workload": "rt256x1024", "precision": "fp64", "tile": 1, "src_sha": "9c8c740ac4c9136a",
-           "bytes_per_launch": 150.99e6}
+TRAFFIC = {"workload": "rt256x1024", "precision": "fp64", "tile": 1, "src_sha": "40ec090069603dda",
+           "bytes_per_launch": 160.85e6}
 
 FP64_VEC_PEAK_TF = 78.6    # MI355X FP64 vector
 FP32_VEC_PEAK_TF = 157.3
@@ -34,7 +34,7 @@ FP32_VEC_PEAK_TF = 157.3
 # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters on the same workload
 # (profiles/fused_rt256x1024_fp64_valu.md); valid for the same sources.
 VALU = {"workload": "rt256x1024", "precision": "fp64", "src_sha": TRAFFIC["src_sha"],
-        "fp64_flop_per_cell": 2716.9}
+        "fp64_flop_per_cell": 2755.0}
 FP64_NOFMA_PEAK_TF = FP64_VEC_PEAK_TF / 2  # one add or multiply per instruction
 
 
