@@ -13,18 +13,20 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle_dugks2p.so")
+CS_LIB_PATH = os.path.join(_HERE, "liboracle_dugks2p_cs.so")
 SRC_PATH = os.path.join(_HERE, "dugks2p_oracle.c")
 
 
 def build(openmp: bool = True) -> str:
-    """Compile the oracle with gcc: -O2, no fast-math, no FMA contraction."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+    """Compile the oracle with gcc: -O2, no fast-math, no FMA contraction;
+    also its complex-step build (the same source with ORC_COMPLEX_STEP)."""
+    base = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+            "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter"]
     if openmp:
-        cmd.append("-fopenmp")
-    cmd += ["-o", LIB_PATH + ".tmp", SRC_PATH, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+        base.append("-fopenmp")
+    for extra, out in (([], LIB_PATH), (["-DORC_COMPLEX_STEP"], CS_LIB_PATH)):
+        subprocess.run(base + extra + ["-o", out + ".tmp", SRC_PATH, "-lm"], check=True)
+        os.replace(out + ".tmp", out)
     return LIB_PATH
 
 
@@ -180,3 +182,59 @@ class Oracle:
         fy = np.empty((18, self.ny + 1, self.nx))
         lib().orc_face_dists(self._h, _ptr(fx), _ptr(fy))
         return fx, fy
+
+
+_cs_lib = None
+
+
+def cs_lib():
+    global _cs_lib
+    if _cs_lib is None:
+        if (not os.path.exists(CS_LIB_PATH)
+                or os.path.getmtime(CS_LIB_PATH) < os.path.getmtime(SRC_PATH)):
+            build()
+        L = ctypes.CDLL(CS_LIB_PATH)
+        P = ctypes.POINTER
+        d = ctypes.c_double
+        L.orc_cs_create.restype = ctypes.c_void_p
+        L.orc_cs_create.argtypes = [P(OrcParams), P(d), P(d), P(d), P(d), P(d), d, d, d, d]
+        L.orc_cs_get_pops.argtypes = [ctypes.c_void_p, P(d), P(d)]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+        L.orc_last_error.restype = ctypes.c_char_p
+        _cs_lib = L
+    return _cs_lib
+
+
+def complex_step_jvp(case, steps, dphi0=None, dkappa=0.0, dgx=0.0, dgy=0.0, h=1e-30, **over):
+    """Directional derivative of the populations after Step 1 and `steps`
+    steps, along (dphi0, dkappa, dgx, dgy), by the complex step: the oracle
+    run in complex arithmetic from phi0 + i h dphi0 (kappa + i h dkappa,
+    g + i h dg); the imaginary part divided by h is the derivative of the
+    FP64 scheme to rounding (no difference quotient).  Returns
+    (populations, derivative), both [18, ny, nx]."""
+    L = cs_lib()
+    p = dict(case.params)
+    p.update(over)
+    xf, yf = _f64(case.x_faces), _f64(case.y_faces)
+    P = OrcParams()
+    for name, _ in OrcParams._fields_:
+        if name in ("x_faces", "y_faces"):
+            continue
+        setattr(P, name, p[name])
+    P.x_faces, P.y_faces = _ptr(xf), _ptr(yf)
+    shape = (case.ny, case.nx)
+    arrs = [_f64(a).reshape(shape) for a in (case.phi0, case.ux0, case.uy0, case.p0)]
+    dp = _f64(np.zeros(shape) if dphi0 is None else dphi0).reshape(shape)
+    s = L.orc_cs_create(ctypes.byref(P), *[_ptr(a) for a in arrs], _ptr(dp),
+                        float(dkappa), float(dgx), float(dgy), float(h))
+    if not s:
+        raise ValueError(L.orc_last_error().decode())
+    try:
+        L.orc_step(s, int(steps))
+        re = np.empty((18,) + shape)
+        im = np.empty((18,) + shape)
+        L.orc_cs_get_pops(s, _ptr(re), _ptr(im))
+    finally:
+        L.orc_destroy(s)
+    return re, im / h

@@ -34,6 +34,12 @@
  *       kineticandmobility, mixvis) unless a uniform tau_f is given.
  *   R10 UPWIND reconstruction (optional): expand from the upwind cell with its
  *       cell gradient; a direction tangential to the face uses CENTRAL.
+ *
+ * Values that depend on the state are of type `real`: double here, or
+ * double _Complex when the file is compiled with ORC_COMPLEX_STEP for
+ * complex-step differentiation (derivatives of the FP64 scheme to rounding,
+ * used to check adjoints).  Mesh weights and the other parameters stay
+ * double; kappa and the body force g are real so that they can be perturbed.
  */
 #include "dugks2p_oracle.h"
 
@@ -41,6 +47,15 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+#ifdef ORC_COMPLEX_STEP
+#include <complex.h>
+typedef double _Complex real;
+#define RE(x) creal(x)
+#else
+typedef double real;
+#define RE(x) (x)
+#endif
 
 /* R2 */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -176,12 +191,13 @@ struct orc_sim {
   double dt, h, hdt, hh, cs2, c, eta, gam, inv_dphi, drho, mumu, c4b, phimid;
   double lo_phi, hi_phi, k1, k2, k3;
   double xi[9][2], w9[9];
-  double *pop;
+  real kappa, gx, gy; /* the parameters of the same names */
+  real *pop;
   /* cell work arrays (Steps 2 and 7) */
-  double *phi, *rho, *mu, *dphx, *dphy, *dmux, *dmuy, *D, *Fx, *Fy, *ux, *uy, *p;
-  double *dpx, *dpy, *tauf;
-  double *barp, *tilp, *gbx, *gby;
-  double *facex, *facey; /* 18 x ny x nfx, 18 x nfy x nx */
+  real *phi, *rho, *mu, *dphx, *dphy, *dmux, *dmuy, *D, *Fx, *Fy, *ux, *uy, *p;
+  real *dpx, *dpy, *tauf;
+  real *barp, *tilp, *gbx, *gby;
+  real *facex, *facey; /* 18 x ny x nfx, 18 x nfy x nx */
 };
 
 static void sim_free(orc_sim *s) {
@@ -199,52 +215,56 @@ double orc_dt(const orc_sim *s) { return s->dt; }
 long orc_step_count(const orc_sim *s) { return s->nstep; }
 
 /* eq. oderrho, with the optional clamp of phi inside rho() only */
-static double rho_of(const orc_sim *s, double phi) {
-  double ph = phi;
-  if (s->P.phi_clamp) ph = ph < s->lo_phi ? s->lo_phi : (ph > s->hi_phi ? s->hi_phi : ph);
+static real clamp_phi(const orc_sim *s, real ph) {
+  if (!s->P.phi_clamp) return ph;
+  return RE(ph) < s->lo_phi ? s->lo_phi : (RE(ph) > s->hi_phi ? s->hi_phi : ph);
+}
+
+static real rho_of(const orc_sim *s, real phi) {
+  const real ph = clamp_phi(s, phi);
   return ((ph - s->P.phi_b) * s->P.rho_a + (s->P.phi_a - ph) * s->P.rho_b) * s->inv_dphi;
 }
 
 /* eqs. kineticandmobility and mixvis: tau_f = mu_d / (rho c_s^2) (R9) */
-static double tauf_of(const orc_sim *s, double phi, double rho) {
+static real tauf_of(const orc_sim *s, real phi, real rho) {
   if (s->P.tau_f > 0.0) return s->P.tau_f;
-  double ph = phi;
-  if (s->P.phi_clamp) ph = ph < s->lo_phi ? s->lo_phi : (ph > s->hi_phi ? s->hi_phi : ph);
+  const real ph = clamp_phi(s, phi);
   double mu_a = s->P.rho_a * s->P.nu_a, mu_b = s->P.rho_b * s->P.nu_b;
-  double mud = s->mumu / ((ph - s->P.phi_b) * mu_b + (s->P.phi_a - ph) * mu_a);
+  real mud = s->mumu / ((ph - s->P.phi_b) * mu_b + (s->P.phi_a - ph) * mu_a);
   return mud / (rho * s->cs2);
 }
 
 /* Macroscopic state at one point, input of the equilibria and sources. */
 typedef struct {
-  double phi, rho, ux, uy, p, mu, grx, gry, D, Fx, Fy, gpx, gpy, icr;
+  real phi, rho, ux, uy, p, mu, grx, gry, D, Fx, Fy, gpx, gpy, icr;
 } macro_t;
 
 /* eqs. feq, geq, su, Hi, F, G at one point. */
-static void point_eq(const orc_sim *s, const macro_t *m, double feq[9], double geq[9],
-                     double ff[9], double fg[9]) {
+static void point_eq(const orc_sim *s, const macro_t *m, real feq[9], real geq[9],
+                     real ff[9], real fg[9]) {
   const double cs2 = s->cs2;
-  const double uu = m->ux * m->ux + m->uy * m->uy;
+  const real uu = m->ux * m->ux + m->uy * m->uy;
   for (int i = 0; i < 9; ++i) {
     const double wi = s->w9[i], xx = s->xi[i][0], xy = s->xi[i][1];
-    const double eu = xx * m->ux + xy * m->uy;
+    const real eu = xx * m->ux + xy * m->uy;
     /* eq. su: s_i = w_i [xi.u / cs2 + (xi.u)^2 / (2 cs2^2) - u^2 / (2 cs2)] */
-    const double si = wi * (eu * s->k1 + eu * eu * s->k2 - uu * s->k3);
+    const real si = wi * (eu * s->k1 + eu * eu * s->k2 - uu * s->k3);
     /* eq. feq */
     feq[i] = wi * m->p + cs2 * m->rho * si;
     /* eqs. geq, Hi */
-    const double Hi = (i == 0) ? m->phi - (1.0 - s->w9[0]) * s->eta * m->mu
-                               : wi * s->eta * m->mu;
+    const real Hi = (i == 0) ? m->phi - (1.0 - s->w9[0]) * s->eta * m->mu
+                             : wi * s->eta * m->mu;
     geq[i] = Hi + m->phi * si;
     /* eqs. F, G with Gamma_i = w_i + s_i */
-    const double G = wi + si;
-    const double cx = xx - m->ux, cy = xy - m->uy;
+    const real G = wi + si;
+    const real cx = xx - m->ux, cy = xy - m->uy;
     ff[i] = cx * (m->Fx * G + si * cs2 * m->grx) + cy * (m->Fy * G + si * cs2 * m->gry) -
             wi * cs2 * m->rho * s->gam * m->D;
     fg[i] = m->phi * m->icr * (cx * (m->Fx - m->gpx) + cy * (m->Fy - m->gpy)) * G;
   }
 }
 
+#ifndef ORC_COMPLEX_STEP
 void orc_point_eq(const orc_sim *s, const double in[13], double feq[9], double geq[9],
                   double ff[9], double fg[9]) {
   macro_t m;
@@ -254,15 +274,16 @@ void orc_point_eq(const orc_sim *s, const double in[13], double feq[9], double g
   m.icr = 1.0 / (s->cs2 * m.rho);
   point_eq(s, &m, feq, geq, ff, fg);
 }
+#endif
 
 /* Three-point stencil along x / y of a cell field, weights w (3 per cell). */
-static double sx(const orc_sim *s, const double *w3, const double *F, int i, int j) {
+static real sx(const orc_sim *s, const double *w3, const real *F, int i, int j) {
   const axis_t *a = &s->ax[0];
   const double *w = w3 + 3 * i;
   const long r = (long)j * s->nx;
   return w[0] * F[r + a->lo[i]] + w[1] * F[r + i] + w[2] * F[r + a->hi[i]];
 }
-static double sy(const orc_sim *s, const double *w3, const double *F, int i, int j) {
+static real sy(const orc_sim *s, const double *w3, const real *F, int i, int j) {
   const axis_t *a = &s->ax[1];
   const double *w = w3 + 3 * j;
   return w[0] * F[(long)a->lo[j] * s->nx + i] + w[1] * F[(long)j * s->nx + i] +
@@ -275,10 +296,10 @@ static double sy(const orc_sim *s, const double *w3, const double *F, int i, int
 static void cell_macros(orc_sim *s) {
   const int nx = s->nx, ny = s->ny;
   const long N = s->N;
-  const double *f = s->pop, *g = s->pop + 9 * N;
+  const real *f = s->pop, *g = s->pop + 9 * N;
 #pragma omp parallel for schedule(static)
   for (long c = 0; c < N; ++c) {
-    double acc = 0.0;
+    real acc = 0.0;
     for (int i = 0; i < 9; ++i) acc += g[i * N + c]; /* eq. phi, R3 */
     s->phi[c] = acc;
     s->rho[c] = rho_of(s, acc);
@@ -287,11 +308,11 @@ static void cell_macros(orc_sim *s) {
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const long c = (long)j * nx + i;
-      const double ph = s->phi[c];
-      const double lap = sx(s, s->ax[0].d2, s->phi, i, j) + sy(s, s->ax[1].d2, s->phi, i, j);
+      const real ph = s->phi[c];
+      const real lap = sx(s, s->ax[0].d2, s->phi, i, j) + sy(s, s->ax[1].d2, s->phi, i, j);
       /* eq. chemicalpotential */
       s->mu[c] = s->c4b * (ph - s->P.phi_a) * (ph - s->P.phi_b) * (ph - s->phimid) -
-                 s->P.kappa * lap;
+                 s->kappa * lap;
       s->dphx[c] = sx(s, s->ax[0].d1, s->phi, i, j);
       s->dphy[c] = sy(s, s->ax[1].d1, s->phi, i, j);
     }
@@ -301,22 +322,22 @@ static void cell_macros(orc_sim *s) {
       const long c = (long)j * nx + i;
       s->dmux[c] = sx(s, s->ax[0].d1, s->mu, i, j);
       s->dmuy[c] = sy(s, s->ax[1].d1, s->mu, i, j);
-      const double lapmu = sx(s, s->ax[0].d2, s->mu, i, j) + sy(s, s->ax[1].d2, s->mu, i, j);
+      const real lapmu = sx(s, s->ax[0].d2, s->mu, i, j) + sy(s, s->ax[1].d2, s->mu, i, j);
       s->D[c] = s->P.mobility * lapmu; /* div(lambda grad mu), lambda constant */
-      const double ph = s->phi[c], rh = s->rho[c];
+      const real ph = s->phi[c], rh = s->rho[c];
       /* F = F_s + F_b, F_s = -phi grad mu (Sec. 2.1), F_b by R8 */
-      s->Fx[c] = -ph * s->dmux[c] + (rh - s->P.rho_ref) * s->P.gx;
-      s->Fy[c] = -ph * s->dmuy[c] + (rh - s->P.rho_ref) * s->P.gy;
-      double s0 = 0.0, jx = 0.0, jy = 0.0;
+      s->Fx[c] = -ph * s->dmux[c] + (rh - s->P.rho_ref) * s->gx;
+      s->Fy[c] = -ph * s->dmuy[c] + (rh - s->P.rho_ref) * s->gy;
+      real s0 = 0.0, jx = 0.0, jy = 0.0;
       for (int i2 = 0; i2 < 9; ++i2) s0 += f[i2 * N + c];
       for (int i2 = 0; i2 < 9; ++i2) jx += s->xi[i2][0] * f[i2 * N + c];
       for (int i2 = 0; i2 < 9; ++i2) jy += s->xi[i2][1] * f[i2 * N + c];
-      const double icr = 1.0 / (s->cs2 * rh);
+      const real icr = 1.0 / (s->cs2 * rh);
       /* eq. u */
       s->ux[c] = (jx + s->hdt * s->cs2 * s->Fx[c]) * icr;
       s->uy[c] = (jy + s->hdt * s->cs2 * s->Fy[c]) * icr;
       /* eq. P, with grad rho = (rho_A - rho_B)/(phi_A - phi_B) grad phi */
-      const double grx = s->drho * s->dphx[c], gry = s->drho * s->dphy[c];
+      const real grx = s->drho * s->dphx[c], gry = s->drho * s->dphy[c];
       s->p[c] = s0 + s->hdt * s->cs2 * (s->ux[c] * grx + s->uy[c] * gry - s->gam * rh * s->D[c]);
     }
 #pragma omp parallel for schedule(static)
@@ -345,20 +366,20 @@ static void cell_transforms(orc_sim *s) {
 #pragma omp parallel for schedule(static)
   for (long c = 0; c < N; ++c) {
     macro_t m;
-    double feq[9], geq[9], ff[9], fg[9];
+    real feq[9], geq[9], ff[9], fg[9];
     cell_macro_at(s, c, &m);
     point_eq(s, &m, feq, geq, ff, fg);
     for (int half = 0; half < 2; ++half) {
-      const double tau = half ? s->P.tau_g : s->tauf[c];
-      const double den = 1.0 / (2.0 * tau + dt);
-      const double ca = (2.0 * tau - h) * den; /* eq. relations1 */
-      const double cb = 3.0 * h * den;
-      const double cc = 3.0 * tau * h * den;
-      const double *eq = half ? geq : feq, *src = half ? fg : ff;
+      const real tau = half ? s->P.tau_g : s->tauf[c];
+      const real den = 1.0 / (2.0 * tau + dt);
+      const real ca = (2.0 * tau - h) * den; /* eq. relations1 */
+      const real cb = 3.0 * h * den;
+      const real cc = 3.0 * tau * h * den;
+      const real *eq = half ? geq : feq, *src = half ? fg : ff;
       for (int i = 0; i < 9; ++i) {
         const long q = (long)(9 * half + i) * N + c;
-        const double til = s->pop[q];
-        const double bp = ca * til + cb * eq[i] + cc * src[i];
+        const real til = s->pop[q];
+        const real bp = ca * til + cb * eq[i] + cc * src[i];
         s->barp[q] = bp;
         s->tilp[q] = (4.0 / 3.0) * bp - (1.0 / 3.0) * til; /* eq. relations2 */
       }
@@ -367,7 +388,7 @@ static void cell_transforms(orc_sim *s) {
 }
 
 /* Cell gradients of bar+ for the face reconstruction (R6, R7). */
-static void pop_gradients(const orc_sim *s, const double *barp, double *gbx, double *gby) {
+static void pop_gradients(const orc_sim *s, const real *barp, real *gbx, real *gby) {
   const int nx = s->nx, ny = s->ny;
   const long N = s->N;
 #pragma omp parallel for schedule(static)
@@ -383,12 +404,12 @@ static void pop_gradients(const orc_sim *s, const double *barp, double *gbx, dou
 /* Step 3 at one face: bar(x_b, t+h) for the 18 populations (eqs. fbar, fbar_h).
  * a = axis normal to the face, k = face index along a, t = cell index along
  * the other axis. */
-static void face_reconstruct(const orc_sim *s, const double *barp, const double *gbx,
-                             const double *gby, int a, int k, int t, double bar[18]) {
+static void face_reconstruct(const orc_sim *s, const real *barp, const real *gbx,
+                             const real *gby, int a, int k, int t, real bar[18]) {
   const axis_t *A = &s->ax[a];
   const long N = s->N;
   const double h = s->h;
-  const double *gn = a == 0 ? gbx : gby, *gt = a == 0 ? gby : gbx;
+  const real *gn = a == 0 ? gbx : gby, *gt = a == 0 ? gby : gbx;
   const int cl = A->fl[k], cr = A->fr[k];
 #define CELL_ID(ia) (a == 0 ? (long)t * s->nx + (ia) : (long)(ia) * s->nx + t)
   if (cl < 0 || cr < 0) {
@@ -402,9 +423,9 @@ static void face_reconstruct(const orc_sim *s, const double *barp, const double 
       const int i = q % 9;
       const int en = a == 0 ? EX[i] : EY[i];
       if (en * nout < 0) continue;
-      const double Ac = barp[q * N + C], Gn = gn[q * N + C], Gt = gt[q * N + C];
-      const double val = Ac + off * Gn;
-      const double sgx = a == 0 ? Gn : Gt, sgy = a == 0 ? Gt : Gn;
+      const real Ac = barp[q * N + C], Gn = gn[q * N + C], Gt = gt[q * N + C];
+      const real val = Ac + off * Gn;
+      const real sgx = a == 0 ? Gn : Gt, sgy = a == 0 ? Gt : Gn;
       bar[q] = val - h * (s->xi[i][0] * sgx + s->xi[i][1] * sgy);
     }
     for (int q = 0; q < 18; ++q) {
@@ -419,8 +440,8 @@ static void face_reconstruct(const orc_sim *s, const double *barp, const double 
   for (int q = 0; q < 18; ++q) {
     const int i = q % 9;
     const int en = a == 0 ? EX[i] : EY[i];
-    const double AL = barp[q * N + L], AR = barp[q * N + R];
-    double val, sn, st;
+    const real AL = barp[q * N + L], AR = barp[q * N + R];
+    real val, sn, st;
     if (s->P.recon == ORC_RECON_UPWIND && en > 0) {
       val = AL + A->foffl[k] * gn[q * N + L];
       sn = gn[q * N + L];
@@ -435,15 +456,15 @@ static void face_reconstruct(const orc_sim *s, const double *barp, const double 
       sn = (AR - AL) * inv;
       st = wl * gt[q * N + L] + wr * gt[q * N + R];
     }
-    const double sgx = a == 0 ? sn : st, sgy = a == 0 ? st : sn;
+    const real sgx = a == 0 ? sn : st, sgy = a == 0 ? st : sn;
     bar[q] = val - h * (s->xi[i][0] * sgx + s->xi[i][1] * sgy);
   }
 #undef CELL_ID
 }
 
 /* R5: value, normal and tangential derivative of a cell field at a face. */
-static void face_field(const orc_sim *s, int a, int k, int t, const double *F,
-                       const double *Ft, double *v, double *dn, double *dtn) {
+static void face_field(const orc_sim *s, int a, int k, int t, const real *F,
+                       const real *Ft, real *v, real *dn, real *dtn) {
   const axis_t *A = &s->ax[a];
   const int cl = A->fl[k], cr = A->fr[k];
 #define CELL_ID(ia) (a == 0 ? (long)t * s->nx + (ia) : (long)(ia) * s->nx + t)
@@ -463,24 +484,24 @@ static void face_field(const orc_sim *s, int a, int k, int t, const double *F,
 
 /* Step 4 at one face: macros from bar (R4), equilibria and sources at the
  * face, then eq. original-function. */
-static void face_dist(const orc_sim *s, int a, int k, int t, const double bar[18],
-                      double out[18]) {
+static void face_dist(const orc_sim *s, int a, int k, int t, const real bar[18],
+                      real out[18]) {
   const axis_t *A = &s->ax[a];
   const int is_wall = A->fl[k] < 0 || A->fr[k] < 0;
-  const double *Tmu = a == 0 ? s->dmuy : s->dmux;
-  const double *Tph = a == 0 ? s->dphy : s->dphx;
-  const double *Tp = a == 0 ? s->dpy : s->dpx;
-  double mu_b, D_b, tmp, gmn, gmt, gfn, gft, gpn, gpt;
+  const real *Tmu = a == 0 ? s->dmuy : s->dmux;
+  const real *Tph = a == 0 ? s->dphy : s->dphx;
+  const real *Tp = a == 0 ? s->dpy : s->dpx;
+  real mu_b, D_b, tmp, gmn, gmt, gfn, gft, gpn, gpt;
   face_field(s, a, k, t, s->mu, Tmu, &mu_b, &gmn, &gmt);
   face_field(s, a, k, t, s->D, s->D, &D_b, &tmp, &tmp);
   face_field(s, a, k, t, s->phi, Tph, &tmp, &gfn, &gft);
   face_field(s, a, k, t, s->p, Tp, &tmp, &gpn, &gpt);
-  const double gmx = a == 0 ? gmn : gmt, gmy = a == 0 ? gmt : gmn;
-  const double gfx = a == 0 ? gfn : gft, gfy = a == 0 ? gft : gfn;
-  const double gpx = a == 0 ? gpn : gpt, gpy = a == 0 ? gpt : gpn;
+  const real gmx = a == 0 ? gmn : gmt, gmy = a == 0 ? gmt : gmn;
+  const real gfx = a == 0 ? gfn : gft, gfy = a == 0 ? gft : gfn;
+  const real gpx = a == 0 ? gpn : gpt, gpy = a == 0 ? gpt : gpn;
 
   macro_t m;
-  double phib = 0.0;
+  real phib = 0.0;
   for (int i = 0; i < 9; ++i) phib += bar[9 + i];
   m.phi = phib;
   m.rho = rho_of(s, phib);
@@ -490,10 +511,10 @@ static void face_dist(const orc_sim *s, int a, int k, int t, const double bar[18
   m.gry = s->drho * gfy;
   m.gpx = gpx;
   m.gpy = gpy;
-  m.Fx = -phib * gmx + (m.rho - s->P.rho_ref) * s->P.gx;
-  m.Fy = -phib * gmy + (m.rho - s->P.rho_ref) * s->P.gy;
+  m.Fx = -phib * gmx + (m.rho - s->P.rho_ref) * s->gx;
+  m.Fy = -phib * gmy + (m.rho - s->P.rho_ref) * s->gy;
   m.icr = 1.0 / (s->cs2 * m.rho);
-  double s0 = 0.0, jx = 0.0, jy = 0.0;
+  real s0 = 0.0, jx = 0.0, jy = 0.0;
   for (int i = 0; i < 9; ++i) s0 += bar[i];
   for (int i = 0; i < 9; ++i) jx += s->xi[i][0] * bar[i];
   for (int i = 0; i < 9; ++i) jy += s->xi[i][1] * bar[i];
@@ -501,14 +522,14 @@ static void face_dist(const orc_sim *s, int a, int k, int t, const double bar[18
   m.uy = (jy + s->hh * s->cs2 * m.Fy) * m.icr;
   m.p = s0 + s->hh * s->cs2 * (m.ux * m.grx + m.uy * m.gry - s->gam * m.rho * m.D);
 
-  double feq[9], geq[9], ff[9], fg[9];
+  real feq[9], geq[9], ff[9], fg[9];
   point_eq(s, &m, feq, geq, ff, fg);
   const double h = s->h;
   for (int half = 0; half < 2; ++half) {
-    const double tau = half ? s->P.tau_g : tauf_of(s, phib, m.rho);
-    const double den = 1.0 / (2.0 * tau + h);
-    const double k1 = 2.0 * tau * den, k2 = h * den, k3 = tau * h * den;
-    const double *eq = half ? geq : feq, *src = half ? fg : ff;
+    const real tau = half ? s->P.tau_g : tauf_of(s, phib, m.rho);
+    const real den = 1.0 / (2.0 * tau + h);
+    const real k1 = 2.0 * tau * den, k2 = h * den, k3 = tau * h * den;
+    const real *eq = half ? geq : feq, *src = half ? fg : ff;
     for (int i = 0; i < 9; ++i)
       out[9 * half + i] = k1 * bar[9 * half + i] + k2 * eq[i] + k3 * src[i];
   }
@@ -528,7 +549,7 @@ static void all_faces(orc_sim *s) {
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int k = 0; k < nfx; ++k) {
-      double bar[18], out[18];
+      real bar[18], out[18];
       face_reconstruct(s, s->barp, s->gbx, s->gby, 0, k, j, bar);
       face_dist(s, 0, k, j, bar, out);
       for (int q = 0; q < 18; ++q) s->facex[q * NX + (long)j * nfx + k] = out[q];
@@ -536,7 +557,7 @@ static void all_faces(orc_sim *s) {
 #pragma omp parallel for schedule(static)
   for (int k = 0; k < nfy; ++k)
     for (int i = 0; i < nx; ++i) {
-      double bar[18], out[18];
+      real bar[18], out[18];
       face_reconstruct(s, s->barp, s->gbx, s->gby, 1, k, i, bar);
       face_dist(s, 1, k, i, bar, out);
       for (int q = 0; q < 18; ++q) s->facey[q * NY + (long)k * nx + i] = out[q];
@@ -559,10 +580,10 @@ static void update(orc_sim *s) {
       const double rx = s->ax[0].rdt[i], ry = s->ax[1].rdt[j];
       for (int q = 0; q < 18; ++q) {
         const int d = q % 9;
-        const double W = s->facex[q * NX + (long)j * nfx + i];
-        const double E = s->facex[q * NX + (long)j * nfx + ie];
-        const double S = s->facey[q * NY + (long)j * nx + i];
-        const double Nn = s->facey[q * NY + (long)jn * nx + i];
+        const real W = s->facex[q * NX + (long)j * nfx + i];
+        const real E = s->facex[q * NX + (long)j * nfx + ie];
+        const real S = s->facey[q * NY + (long)j * nx + i];
+        const real Nn = s->facey[q * NY + (long)jn * nx + i];
         s->pop[q * N + c] =
             s->tilp[q * N + c] - rx * s->xi[d][0] * (E - W) - ry * s->xi[d][1] * (Nn - S);
       }
@@ -588,8 +609,11 @@ static int check_faces(const double *f, int n) {
   return 0;
 }
 
-orc_sim *orc_create(const orc_params *P, const double *phi0, const double *ux0,
-                    const double *uy0, const double *p0) {
+/* Step 1 from phi0 (+ i h dphi0 in the complex-step build), u0, p0 with
+ * kappa and g (+ i h dkappa, i h dg). */
+static orc_sim *create(const orc_params *P, const double *phi0, const double *ux0,
+                       const double *uy0, const double *p0, const double *dphi0,
+                       double dkappa, double dgx, double dgy, double hcs) {
   if (!P || !phi0 || !ux0 || !uy0 || !p0) { set_err("null argument"); return NULL; }
   if (P->nx < 1 || P->ny < 1) { set_err("nx, ny must be >= 1"); return NULL; }
   if ((P->bc_x != ORC_BC_PERIODIC && P->bc_x != ORC_BC_WALL) ||
@@ -617,6 +641,16 @@ orc_sim *orc_create(const orc_params *P, const double *phi0, const double *ux0,
   orc_sim *s = calloc(1, sizeof *s);
   if (!s) { set_err("out of memory"); return NULL; }
   s->P = *P;
+  s->kappa = P->kappa;
+  s->gx = P->gx;
+  s->gy = P->gy;
+#ifdef ORC_COMPLEX_STEP
+  s->kappa += I * hcs * dkappa;
+  s->gx += I * hcs * dgx;
+  s->gy += I * hcs * dgy;
+#else
+  (void)dphi0; (void)dkappa; (void)dgx; (void)dgy; (void)hcs;
+#endif
   s->nx = P->nx; s->ny = P->ny; s->N = (long)P->nx * P->ny;
   if (axis_init(&s->ax[0], P->nx, P->bc_x, P->x_faces) ||
       axis_init(&s->ax[1], P->ny, P->bc_y, P->y_faces)) {
@@ -663,20 +697,20 @@ orc_sim *orc_create(const orc_params *P, const double *phi0, const double *ux0,
 
   const long N = s->N;
   const long NX = (long)P->ny * s->ax[0].nf, NY = (long)s->ax[1].nf * P->nx;
-  double **cells[] = {&s->phi, &s->rho, &s->mu, &s->dphx, &s->dphy, &s->dmux, &s->dmuy,
-                      &s->D, &s->Fx, &s->Fy, &s->ux, &s->uy, &s->p, &s->dpx, &s->dpy,
-                      &s->tauf};
+  real **cells[] = {&s->phi, &s->rho, &s->mu, &s->dphx, &s->dphy, &s->dmux, &s->dmuy,
+                    &s->D, &s->Fx, &s->Fy, &s->ux, &s->uy, &s->p, &s->dpx, &s->dpy,
+                    &s->tauf};
   for (size_t k = 0; k < sizeof cells / sizeof cells[0]; ++k) {
-    *cells[k] = calloc(N, sizeof(double));
+    *cells[k] = calloc(N, sizeof(real));
     if (!*cells[k]) { set_err("out of memory"); sim_free(s); return NULL; }
   }
-  s->pop = calloc(18 * N, sizeof(double));
-  s->barp = calloc(18 * N, sizeof(double));
-  s->tilp = calloc(18 * N, sizeof(double));
-  s->gbx = calloc(18 * N, sizeof(double));
-  s->gby = calloc(18 * N, sizeof(double));
-  s->facex = calloc(18 * NX, sizeof(double));
-  s->facey = calloc(18 * NY, sizeof(double));
+  s->pop = calloc(18 * N, sizeof(real));
+  s->barp = calloc(18 * N, sizeof(real));
+  s->tilp = calloc(18 * N, sizeof(real));
+  s->gbx = calloc(18 * N, sizeof(real));
+  s->gby = calloc(18 * N, sizeof(real));
+  s->facex = calloc(18 * NX, sizeof(real));
+  s->facey = calloc(18 * NY, sizeof(real));
   if (!s->pop || !s->barp || !s->tilp || !s->gbx || !s->gby || !s->facex || !s->facey) {
     set_err("out of memory"); sim_free(s); return NULL;
   }
@@ -685,17 +719,22 @@ orc_sim *orc_create(const orc_params *P, const double *phi0, const double *ux0,
    * given rather than taken from populations; then f = f^eq, g = g^eq and
    * eq. auxf(a) gives tilde = eq - (dt/2) F. */
   const int nx = P->nx, ny = P->ny;
-  memcpy(s->phi, phi0, sizeof(double) * N);
-  memcpy(s->ux, ux0, sizeof(double) * N);
-  memcpy(s->uy, uy0, sizeof(double) * N);
-  memcpy(s->p, p0, sizeof(double) * N);
+  for (long c = 0; c < N; ++c) {
+    s->phi[c] = phi0[c];
+#ifdef ORC_COMPLEX_STEP
+    if (dphi0) s->phi[c] += I * hcs * dphi0[c];
+#endif
+    s->ux[c] = ux0[c];
+    s->uy[c] = uy0[c];
+    s->p[c] = p0[c];
+  }
   for (long c = 0; c < N; ++c) s->rho[c] = rho_of(s, s->phi[c]);
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const long c = (long)j * nx + i;
-      const double ph = s->phi[c];
-      const double lap = sx(s, s->ax[0].d2, s->phi, i, j) + sy(s, s->ax[1].d2, s->phi, i, j);
-      s->mu[c] = s->c4b * (ph - P->phi_a) * (ph - P->phi_b) * (ph - s->phimid) - P->kappa * lap;
+      const real ph = s->phi[c];
+      const real lap = sx(s, s->ax[0].d2, s->phi, i, j) + sy(s, s->ax[1].d2, s->phi, i, j);
+      s->mu[c] = s->c4b * (ph - P->phi_a) * (ph - P->phi_b) * (ph - s->phimid) - s->kappa * lap;
       s->dphx[c] = sx(s, s->ax[0].d1, s->phi, i, j);
       s->dphy[c] = sy(s, s->ax[1].d1, s->phi, i, j);
     }
@@ -704,16 +743,16 @@ orc_sim *orc_create(const orc_params *P, const double *phi0, const double *ux0,
       const long c = (long)j * nx + i;
       s->dmux[c] = sx(s, s->ax[0].d1, s->mu, i, j);
       s->dmuy[c] = sy(s, s->ax[1].d1, s->mu, i, j);
-      const double lapmu = sx(s, s->ax[0].d2, s->mu, i, j) + sy(s, s->ax[1].d2, s->mu, i, j);
+      const real lapmu = sx(s, s->ax[0].d2, s->mu, i, j) + sy(s, s->ax[1].d2, s->mu, i, j);
       s->D[c] = P->mobility * lapmu;
-      s->Fx[c] = -s->phi[c] * s->dmux[c] + (s->rho[c] - P->rho_ref) * P->gx;
-      s->Fy[c] = -s->phi[c] * s->dmuy[c] + (s->rho[c] - P->rho_ref) * P->gy;
+      s->Fx[c] = -s->phi[c] * s->dmux[c] + (s->rho[c] - P->rho_ref) * s->gx;
+      s->Fy[c] = -s->phi[c] * s->dmuy[c] + (s->rho[c] - P->rho_ref) * s->gy;
       s->dpx[c] = sx(s, s->ax[0].d1, s->p, i, j);
       s->dpy[c] = sy(s, s->ax[1].d1, s->p, i, j);
     }
   for (long c = 0; c < N; ++c) {
     macro_t m;
-    double feq[9], geq[9], ff[9], fg[9];
+    real feq[9], geq[9], ff[9], fg[9];
     cell_macro_at(s, c, &m);
     point_eq(s, &m, feq, geq, ff, fg);
     for (int i = 0; i < 9; ++i) {
@@ -722,6 +761,25 @@ orc_sim *orc_create(const orc_params *P, const double *phi0, const double *ux0,
     }
   }
   return s;
+}
+
+#ifdef ORC_COMPLEX_STEP
+orc_sim *orc_cs_create(const orc_params *P, const double *phi0, const double *ux0,
+                       const double *uy0, const double *p0, const double *dphi0,
+                       double dkappa, double dgx, double dgy, double h) {
+  return create(P, phi0, ux0, uy0, p0, dphi0, dkappa, dgx, dgy, h);
+}
+
+void orc_cs_get_pops(const orc_sim *s, double *re, double *im) {
+  for (long k = 0; k < 18 * s->N; ++k) {
+    re[k] = creal(s->pop[k]);
+    im[k] = cimag(s->pop[k]);
+  }
+}
+#else
+orc_sim *orc_create(const orc_params *P, const double *phi0, const double *ux0,
+                    const double *uy0, const double *p0) {
+  return create(P, phi0, ux0, uy0, p0, NULL, 0.0, 0.0, 0.0, 0.0);
 }
 
 void orc_moments(orc_sim *s, double *phi, double *rho, double *ux, double *uy, double *p,
@@ -851,3 +909,4 @@ void orc_face_dists(orc_sim *s, double *xface, double *yface) {
   all_faces(s);
   copy_faces_out(s, s->facex, s->facey, xface, yface);
 }
+#endif /* ORC_COMPLEX_STEP */

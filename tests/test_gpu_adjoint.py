@@ -166,3 +166,42 @@ def test_gpu_rollout_gradient_rt64x256(D, oracle_mod):
     o.step(steps)
     phi_o = o.pops()[9:].sum(0)
     assert np.max(np.abs(pops[9:].sum(0).detach().cpu().numpy() - phi_o)) <= 1e-13
+
+
+def test_gpu_rollout_gradient_exact_jvp_rt64x256(D, oracle_mod):
+    """The same rollout's gradient against the oracle's complex-step
+    directional derivatives (exact to rounding, no difference quotient):
+    dJ . d = 2 sum (phi(T) - phi_ref) (d phi(T)) for 6 seeded directions in
+    (a_1..a_64, kappa, gx, gy), to 1e-11 of the sum of the terms' magnitudes."""
+    import torch
+    from paper_1802_02868_amd.rollout import rollout
+    case = W.rt_case(64)
+    steps, every = 120, 50
+    print("rollout gradient vs complex step:", case.name, steps, every, flush=True)
+    a0 = W.rt_mode_amplitudes(64, 64, seed=2024)
+    ref = oracle_mod.Oracle.from_case(dataclasses.replace(
+        case, phi0=W.rt_interface_phi0(W.rt_mode_amplitudes(64, 64, seed=77), case)))
+    ref.step(steps)
+    ref = ref.pops()[9:].sum(0)
+    a = torch.tensor(a0, dtype=torch.float64, device="cuda", requires_grad=True)
+    kap = torch.tensor(case.params["kappa"], dtype=torch.float64, device="cuda", requires_grad=True)
+    g = torch.tensor([case.params["gx"], case.params["gy"]], dtype=torch.float64, device="cuda",
+                     requires_grad=True)
+    pops = rollout(W.rt_interface_phi0(a, case), kap, g, case, steps, every)
+    J = ((pops[9:].sum(0) - torch.from_numpy(ref).cuda()) ** 2).sum()
+    J.backward()
+    ga, gk, gg = a.grad.cpu().numpy(), float(kap.grad), g.grad.cpu().numpy()
+    c = dataclasses.replace(case, phi0=W.rt_interface_phi0(a0, case))
+    rng = np.random.default_rng(41)
+    for _ in range(6):
+        da = rng.standard_normal(64) * 1e-3 * 64
+        dk, dgx, dgy = rng.standard_normal(3) * np.array(
+            [case.params["kappa"], abs(case.params["gy"]), abs(case.params["gy"])])
+        _, dphi0 = torch.func.jvp(lambda x: W.rt_interface_phi0(x, case),
+                                  (torch.from_numpy(a0),), (torch.from_numpy(da),))
+        re, jv = oracle_mod.complex_step_jvp(c, steps, dphi0.numpy(), dk, dgx, dgy)
+        terms = 2.0 * (re[9:].sum(0) - ref) * jv[9:].sum(0)
+        exact = float(terms.sum())
+        ad = float(ga @ da) + gk * dk + float(gg @ np.array([dgx, dgy]))
+        print("  direction: ad %.15e exact %.15e" % (ad, exact), flush=True)
+        assert abs(ad - exact) <= 1e-11 * float(np.abs(terms).sum())
