@@ -221,6 +221,8 @@ struct IoF64 {
 #pragma unroll
     for (int q = 0; q < 9; ++q) f[q] = v[q];
   }
+  // v as load() would return it after store(c, v)
+  DFN static void roundtrip(double v[18]) { (void)v; }
   // eq. phi: phi = sum_i g~_i, ascending i
   DFN double phi(i64 c) const {
     double a = 0.0;
@@ -274,6 +276,23 @@ struct IoE32 {
     for (int i = 0; i < 9; ++i) phv += v[9 + i];
 #pragma unroll
     for (int q = 0; q < 9; ++q) fo[q] = (double)(float)v[q];
+  }
+  // v as load() would return it after store(c, v)
+  DFN static void roundtrip(double v[18]) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) v[q] = (double)(float)v[q];
+    double phi = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) phi += v[9 + i];
+    double d[9], s = 0.0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      d[i] = (double)(float)(v[9 + i] - w9_lit(i) * phi);
+      s += d[i];
+    }
+    d[0] = -s;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[9 + i] = w9_lit(i) * phi + d[i];
   }
   DFN double phi(i64 c) const { return ph[c]; }
 };

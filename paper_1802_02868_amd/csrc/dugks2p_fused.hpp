@@ -202,11 +202,17 @@ struct TileLds {
     } f;
   } u;
   double phi[S::SY][S::SX], mu[S::SY][S::SX], p[S::SY][S::SX];
+  // tilde+ of the tile's cells (Step 2 output kept for Step 6) and D over the
+  // bar+ window
+  double T[18][S::TY][S::TX];
+  double D[S::WY][S::WX];
   // App. B weights (population gradient, first derivative) of the tile's
   // columns (axis 0) and rows (axis 1) at the scalar-window positions, and
   // the geometry of the tile's faces (local face 0..TX along x, 0..TY along y)
   double pgw[2][S::SM][3], d1w[2][S::SM][3];
   double fwl[2][S::FM], fwr[2][S::FM], finv[2][S::FM], foffl[2][S::FM], foffr[2][S::FM];
+  // dt / |V| factors of the tile's columns and rows
+  double rdt[2][S::FM];
 };
 
 // Accessor of the face code over the tile's LDS (bar+, phi, mu, p) and the
@@ -332,7 +338,7 @@ struct LAcc {
   DFN double mu(const H &h) const { return (&L->mu[0][0])[chk(h.o2, NW2)]; }
   DFN double phi(const H &h) const { return (&L->phi[0][0])[chk(h.o2, NW2)]; }
   DFN double p(const H &h) const { return (&L->p[0][0])[chk(h.o2, NW2)]; }
-  DFN double D(const H &h) const { return w->D[(i64)h.y * K->ld + h.x]; }
+  DFN double D(const H &h) const { return (&L->D[0][0])[chk(h.o1, NW1)]; }
   DFN double dmu(int a, const H &h) const { return d1(a, h, &L->mu[0][0]); }
   DFN double dphi(int a, const H &h) const { return d1(a, h, &L->phi[0][0]); }
   DFN double dp(int a, const H &h) const { return d1(a, h, &L->p[0][0]); }
@@ -357,11 +363,35 @@ struct FusedTile {
     R fx[12], fy[12];
     bool hx, hy;
   };
+  // global inputs of a window cell's Step 2, loaded ahead of P0 so that their
+  // latency overlaps P0's loads
+  struct Pre {
+    double tv[18], ux, uy, D, Fx, Fy;
+  };
 
   // global index along an axis of window offset o, or -1 outside a wall domain
   DFN int gcol(int g, int n, int bc) const {
     if (bc == 0) return wrapi(g, n);
     return (g >= 0 && g < n) ? g : -1;
+  }
+
+  // window cell of thread tid: global column and row (-1 outside a wall domain)
+  DFN void p1_cell(int tid, int &gx, int &gy) const {
+    const int lx = tid % S::WX, ly = tid / S::WX;
+    gx = gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
+    gy = gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
+  }
+  DFN void p1_load(int tid, Pre &pr) const {
+    int gx, gy;
+    p1_cell(tid, gx, gy);
+    if (gx < 0 || gy < 0) return;
+    const i64 c = (i64)gy * K.ld + gx;
+    src.load(c, pr.tv);
+    pr.ux = w.ux[c];
+    pr.uy = w.uy[c];
+    pr.D = w.D[c];
+    pr.Fx = w.Fx[c];
+    pr.Fy = w.Fy[c];
   }
 
   // P0: phi, mu, p on the tile and a two-cell ring.
@@ -400,16 +430,16 @@ struct FusedTile {
       L->finv[a][f] = X.finv[k];
       L->foffl[a][f] = X.foffl[k];
       L->foffr[a][f] = X.foffr[k];
+      if (f < (a == 0 ? S::TX : S::TY) && k < X.n) L->rdt[a][f] = X.rdt[k];
     }
   }
 
   // P1: Step 2 on the tile and a one-cell ring; tilde+ kept for the tile.
-  DFN void p1(int tid, TS &ts) const {
+  DFN void p1(int tid, const Pre &pr) const {
     const int lx = tid % S::WX, ly = tid / S::WX;
-    const int gx = gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
-    const int gy = gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
+    int gx, gy;
+    p1_cell(tid, gx, gy);
     if (gx < 0 || gy < 0) return;
-    const i64 c = (i64)gy * K.ld + gx;
     const LAcc<S> acc{&K, &w, L, x0, y0};
     const typename LAcc<S>::H hc = acc.cell(gx, gy);
     const double ph = acc.phi(hc);
@@ -417,34 +447,37 @@ struct FusedTile {
     Mac<R> m;
     m.phi = (R)ph;
     m.rho = (R)rh;
-    m.ux = (R)w.ux[c];
-    m.uy = (R)w.uy[c];
+    m.ux = (R)pr.ux;
+    m.uy = (R)pr.uy;
     m.p = (R)acc.p(hc);
     m.mu = (R)acc.mu(hc);
     m.grx = (R)(K.drho * acc.dphi(0, hc));
     m.gry = (R)(K.drho * acc.dphi(1, hc));
-    m.D = (R)w.D[c];
-    m.Fx = (R)w.Fx[c];
-    m.Fy = (R)w.Fy[c];
+    m.D = (R)pr.D;
+    m.Fx = (R)pr.Fx;
+    m.Fy = (R)pr.Fy;
+    L->D[ly][lx] = pr.D;
     m.gpx = (R)acc.dp(0, hc);
     m.gpy = (R)acc.dp(1, hc);
     m.icr = (R)1.0 / ((R)K.cs2 * m.rho);
     const R tf = tauf_of<R>(K, (R)ph, (R)rh);
     R til[18], out[18];
-    double tv[18];
-    src.load(c, tv);
 #pragma unroll
-    for (int q = 0; q < 18; ++q) til[q] = (R)tv[q];
+    for (int q = 0; q < 18; ++q) til[q] = (R)pr.tv[q];
     cell_barp<R, U>(K, m, tf, til, out);
 #pragma unroll
     for (int q = 0; q < 18; ++q) L->u.A[q][ly][lx] = (double)out[q];
-    // tilde+ of the tile's own cells waits in the output buffer for P4
+    // tilde+ of the tile's own cells waits in LDS for P4, rounded as the
+    // state encoding would round it
     if (lx >= 1 && lx <= S::TX && ly >= 1 && ly <= S::TY && x0 + lx - 1 < K.nx &&
         y0 + ly - 1 < K.ny) {
+      double tv[18];
 #pragma unroll
       for (int q = 0; q < 18; ++q)
         tv[q] = (double)((R)(4.0 / 3.0) * (R)(double)out[q] - (R)(1.0 / 3.0) * til[q]);
-      dst.store(c, tv);
+      IO::roundtrip(tv);
+#pragma unroll
+      for (int q = 0; q < 18; ++q) L->T[q][ly - 1][lx - 1] = tv[q];
     }
   }
 
@@ -493,17 +526,36 @@ struct FusedTile {
       for (int s = 0; s < 12; ++s) L->u.f.Y[s][ty][tx] = (double)ts.fy[s];
   }
 
+#if defined(__HIPCC__)
+  // the phases in order, a workgroup barrier between them
+  __device__ void run(int tid) const {
+    Pre pr;
+    TS ts;
+    p1_load(tid, pr);
+    p0(tid);
+    __syncthreads();
+    p1(tid, pr);
+    __syncthreads();
+    p2(tid, ts);
+    __syncthreads();
+    p3(tid, ts);
+    __syncthreads();
+    p4(tid);
+  }
+#endif
+
   // P4: Steps 5-6 (eq. updatef) for the tile's cells.
-  DFN void p4(int tid, const TS &ts) const {
+  DFN void p4(int tid) const {
     const int lx = tid % S::WX, ly = tid / S::WX;
     if (lx < 1 || lx > S::TX || ly < 1 || ly > S::TY) return;
     const int cx = lx - 1, cy = ly - 1;
     const int gx = x0 + cx, gy = y0 + cy;
     if (gx >= K.nx || gy >= K.ny) return;
     const i64 c = (i64)gy * K.ld + gx;
-    const R rx = (R)K.ax[0].rdt[gx], ry = (R)K.ax[1].rdt[gy];
+    const R rx = (R)L->rdt[0][cx], ry = (R)L->rdt[1][cy];
     double tv[18];
-    dst.load(c, tv);
+#pragma unroll
+    for (int q = 0; q < 18; ++q) tv[q] = L->T[q][cy][cx];
 #pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int d = q % 9, sx = xslot(d), sy = yslot(d);
@@ -562,17 +614,7 @@ __global__ __launch_bounds__(NTHR) void k_fused_tile(Consts K, Work w, IO src, I
   __shared__ TileLds<S> L;
   const int tile = xcd_tile(blockIdx.x, ntiles);
   FusedTile<IO, R, U, S> ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY, &L};
-  typename FusedTile<IO, R, U, S>::TS ts;
-  const int tid = threadIdx.x;
-  ft.p0(tid);
-  __syncthreads();
-  ft.p1(tid, ts);
-  __syncthreads();
-  ft.p2(tid, ts);
-  __syncthreads();
-  ft.p3(tid, ts);
-  __syncthreads();
-  ft.p4(tid, ts);
+  ft.run(threadIdx.x);
 }
 #endif
 
