@@ -394,43 +394,102 @@ struct FusedTile {
     pr.Fy = w.Fy[c];
   }
 
-  // P0: phi, mu, p on the tile and a two-cell ring.
-  DFN void p0(int tid) const {
-    for (int e = tid; e < S::SX * S::SY; e += NTHR) {
-      const int lx = e % S::SX, ly = e / S::SX;
-      const int gx = gcol(x0 - 2 + lx, K.nx, K.ax[0].bc);
-      const int gy = gcol(y0 - 2 + ly, K.ny, K.ax[1].bc);
-      if (gx < 0 || gy < 0) continue;
-      const i64 c = (i64)gy * K.ld + gx;
-      L->phi[ly][lx] = w.phi[c];
-      L->mu[ly][lx] = w.mu[c];
-      L->p[ly][lx] = w.p[c];
-    }
-    // weight tables of the window's columns and rows
-    for (int e = tid; e < S::SX + S::SY; e += NTHR) {
-      const int a = e < S::SX ? 0 : 1, pos = a == 0 ? e : e - S::SX;
-      const Axis &X = K.ax[a];
-      const int g = gcol((a == 0 ? x0 : y0) - 2 + pos, X.n, X.bc);
-      if (g < 0) continue;
+  // P0: phi, mu, p on the tile and a two-cell ring, the App. B weight rows
+  // of the window's columns and rows, and the geometry of the tile's faces.
+  // All of the phase's global loads are issued (p0_load) before its first
+  // LDS store (p0_store), so that they share one memory round trip.  Roles:
+  // every thread loads window elements tid and tid + NTHR; the last SX + SY
+  // threads a weight row each, the TX + TY + 2 threads below them a face.
+  static_assert(S::SX * S::SY <= 2 * NTHR, "scalar window exceeds two elements per thread");
+  static_assert(S::SX + S::SY + S::TX + S::TY + 2 <= NTHR, "table roles exceed the workgroup");
+  struct Pre0 {
+    double v[2][3];  // phi, mu, p
+    double t[6];     // pg and d1 weights, or fwl fwr finv foffl foffr rdt
+  };
+  // window element e: its global cell c, false outside the window or domain
+  DFN bool win_elem(int e, i64 &c) const {
+    if (e >= S::SX * S::SY) return false;
+    const int gx = gcol(x0 - 2 + e % S::SX, K.nx, K.ax[0].bc);
+    const int gy = gcol(y0 - 2 + e / S::SX, K.ny, K.ax[1].bc);
+    if (gx < 0 || gy < 0) return false;
+    c = (i64)gy * K.ld + gx;
+    return true;
+  }
+  // weight-row role r: axis a, window position pos, global index g
+  DFN bool wt_role(int r, int &a, int &pos, int &g) const {
+    if (r < 0 || r >= S::SX + S::SY) return false;
+    a = r < S::SX ? 0 : 1;
+    pos = a == 0 ? r : r - S::SX;
+    const Axis &X = K.ax[a];
+    g = gcol((a == 0 ? x0 : y0) - 2 + pos, X.n, X.bc);
+    return g >= 0;
+  }
+  // face role r: axis a, local face f, global face k
+  DFN bool face_role(int r, int &a, int &f, int &k) const {
+    if (r < 0 || r >= S::TX + S::TY + 2) return false;
+    a = r <= S::TX ? 0 : 1;
+    f = a == 0 ? r : r - S::TX - 1;
+    const Axis &X = K.ax[a];
+    k = (a == 0 ? x0 : y0) + f;
+    if (X.bc == 0 && k == X.n) k = 0;
+    return k < X.nf;
+  }
+  DFN void p0_load(int tid, Pre0 &r) const {
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        L->pgw[a][pos][m] = X.pg[3 * g + m];
-        L->d1w[a][pos][m] = X.d1[3 * g + m];
+    for (int j = 0; j < 2; ++j) {
+      i64 c;
+      if (win_elem(tid + j * NTHR, c)) {
+        r.v[j][0] = w.phi[c];
+        r.v[j][1] = w.mu[c];
+        r.v[j][2] = w.p[c];
       }
     }
-    // geometry of the tile's faces
-    for (int e = tid; e < S::TX + S::TY + 2; e += NTHR) {
-      const int a = e <= S::TX ? 0 : 1, f = a == 0 ? e : e - S::TX - 1;
+    const int rw = NTHR - 1 - tid, rf = rw - (S::SX + S::SY);
+    int a, pos, g, f, k;
+    if (wt_role(rw, a, pos, g)) {
       const Axis &X = K.ax[a];
-      int k = (a == 0 ? x0 : y0) + f;
-      if (X.bc == 0 && k == X.n) k = 0;
-      if (k >= X.nf) continue;
-      L->fwl[a][f] = X.fwl[k];
-      L->fwr[a][f] = X.fwr[k];
-      L->finv[a][f] = X.finv[k];
-      L->foffl[a][f] = X.foffl[k];
-      L->foffr[a][f] = X.foffr[k];
-      if (f < (a == 0 ? S::TX : S::TY) && k < X.n) L->rdt[a][f] = X.rdt[k];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        r.t[m] = X.pg[3 * g + m];
+        r.t[3 + m] = X.d1[3 * g + m];
+      }
+    } else if (face_role(rf, a, f, k)) {
+      const Axis &X = K.ax[a];
+      r.t[0] = X.fwl[k];
+      r.t[1] = X.fwr[k];
+      r.t[2] = X.finv[k];
+      r.t[3] = X.foffl[k];
+      r.t[4] = X.foffr[k];
+      if (f < (a == 0 ? S::TX : S::TY) && k < X.n) r.t[5] = X.rdt[k];
+    }
+  }
+  DFN void p0_store(int tid, const Pre0 &r) const {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      i64 c;
+      const int e = tid + j * NTHR;
+      if (win_elem(e, c)) {
+        const int lx = e % S::SX, ly = e / S::SX;
+        L->phi[ly][lx] = r.v[j][0];
+        L->mu[ly][lx] = r.v[j][1];
+        L->p[ly][lx] = r.v[j][2];
+      }
+    }
+    const int rw = NTHR - 1 - tid, rf = rw - (S::SX + S::SY);
+    int a, pos, g, f, k;
+    if (wt_role(rw, a, pos, g)) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        L->pgw[a][pos][m] = r.t[m];
+        L->d1w[a][pos][m] = r.t[3 + m];
+      }
+    } else if (face_role(rf, a, f, k)) {
+      L->fwl[a][f] = r.t[0];
+      L->fwr[a][f] = r.t[1];
+      L->finv[a][f] = r.t[2];
+      L->foffl[a][f] = r.t[3];
+      L->foffr[a][f] = r.t[4];
+      if (f < (a == 0 ? S::TX : S::TY) && k < K.ax[a].n) L->rdt[a][f] = r.t[5];
     }
   }
 
@@ -529,10 +588,12 @@ struct FusedTile {
 #if defined(__HIPCC__)
   // the phases in order, a workgroup barrier between them
   __device__ void run(int tid) const {
+    Pre0 r0;
     Pre pr;
     TS ts;
+    p0_load(tid, r0);
     p1_load(tid, pr);
-    p0(tid);
+    p0_store(tid, r0);
     __syncthreads();
     p1(tid, pr);
     __syncthreads();

@@ -29,6 +29,10 @@ class DugksError(RuntimeError):
 
 
 def _load():
+    # torch brings its own HIP runtime; loading it first makes this library
+    # bind to the same one, so that torch's device memory and streams are
+    # valid handles here whatever the caller imported first
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libdugks2p.so is not built (run __graft_entry__.build() or "
                           "python -m paper_1802_02868_amd.build)")

@@ -42,15 +42,18 @@ struct CpuEx {
     std::vector<TileLds<S>> L(1);
     std::vector<typename FusedTile<IO, R, U, S>::TS> ts(NTHR);
     std::vector<typename FusedTile<IO, R, U, S>::Pre> pre(NTHR);
+    std::vector<typename FusedTile<IO, R, U, S>::Pre0> pre0(NTHR);
     for (int b = 0; b < nt; ++b) {
       const int tile = xcd_tile(b, nt);
       memset((void *)L.data(), 0xff, sizeof(TileLds<S>));  // NaN poison: stray reads show
       memset((void *)pre.data(), 0xff, pre.size() * sizeof(pre[0]));
+      memset((void *)pre0.data(), 0xff, pre0.size() * sizeof(pre0[0]));
       FusedTile<IO, R, U, S> ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY,
                                 L.data()};
-      // the kernel's order: Step 2 inputs, P0, barrier, P1, ... P4
+      // the kernel's order: P0 and Step 2 loads, P0 stores, barrier, P1, ... P4
+      for (int t = 0; t < NTHR; ++t) ft.p0_load(t, pre0[t]);
       for (int t = 0; t < NTHR; ++t) ft.p1_load(t, pre[t]);
-      for (int t = 0; t < NTHR; ++t) ft.p0(t);
+      for (int t = 0; t < NTHR; ++t) ft.p0_store(t, pre0[t]);
       for (int t = 0; t < NTHR; ++t) ft.p1(t, pre[t]);
       for (int t = 0; t < NTHR; ++t) ft.p2(t, ts[t]);
       for (int t = 0; t < NTHR; ++t) ft.p3(t, ts[t]);
