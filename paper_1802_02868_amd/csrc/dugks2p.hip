@@ -29,11 +29,15 @@ int fail(int code, const std::string &msg) {
       return fail(DUGKS2P_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
   } while (0)
 
-// One thread per (i, j) in a 64 x 4 block.
+// One thread per (i, j) in a 64 x 4 block.  The grid is one-dimensional:
+// workgroups are dealt to the 8 XCDs round robin, and xcd_tile gives each
+// XCD a contiguous run of blocks (a band of rows), so that the rows a
+// stencil reads above and below a block sit in the same XCD's L2.
 template <class F>
-__global__ __launch_bounds__(256) void k_grid(F f, int n0, int n1) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
+__global__ __launch_bounds__(256) void k_grid(F f, int n0, int n1, int gx, int nb) {
+  const int b = xcd_tile(blockIdx.x, nb);
+  const int i = (b % gx) * 64 + threadIdx.x;
+  const int j = (b / gx) * 4 + threadIdx.y;
   if (i < n0 && j < n1) f(i, j);
 }
 
@@ -62,14 +66,14 @@ struct GpuEx {
   template <class F>
   void grid(const F &f, int n0, int n1) {
     if (n0 <= 0 || n1 <= 0) return;
-    const dim3 b(64, 4), g((n0 + 63) / 64, (n1 + 3) / 4);
-    hipLaunchKernelGGL(k_grid<F>, g, b, 0, s, f, n0, n1);
+    const int gx = (n0 + 63) / 64, nb = gx * ((n1 + 3) / 4);
+    hipLaunchKernelGGL(k_grid<F>, dim3(nb), dim3(64, 4), 0, s, f, n0, n1, gx, nb);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess && err == hipSuccess) err = e;
   }
   void macros(const Consts &K, const Work &w) {
-    const dim3 g((K.nx + MBX - 1) / MBX, (K.ny + MBY - 1) / MBY), b(MBX, MBY);
-    hipLaunchKernelGGL(k_macros, g, b, 0, s, K, w);
+    const int gx = (K.nx + MBX - 1) / MBX, nb = gx * ((K.ny + MBY - 1) / MBY);
+    hipLaunchKernelGGL(k_macros, dim3(nb), dim3(MBX, MBY), 0, s, K, w, gx, nb);
     note(hipGetLastError());
   }
   template <class IO, class R, bool U, class S>

@@ -123,6 +123,7 @@ struct FMacF {
 };
 
 DFN int wrapi(int g, int n);
+DFN int xcd_tile(int b, int n);
 
 // The same cell macros over a 64 x 4 block of cells: mu once on the block
 // and a one-cell ring in LDS (instead of at every cell's four neighbours),
@@ -180,9 +181,12 @@ struct MacBlock {
 };
 
 #if defined(__HIPCC__)
-__global__ __launch_bounds__(MBX * MBY) void k_macros(Consts K, Work w) {
+// one-dimensional grid of nb blocks, gx per block row, in the XCD-aware
+// order of xcd_tile (an XCD takes a band of rows)
+__global__ __launch_bounds__(MBX * MBY) void k_macros(Consts K, Work w, int gx, int nb) {
   __shared__ MacLds L;
-  const MacBlock mb{K, w, (int)blockIdx.x * MBX, (int)blockIdx.y * MBY, &L};
+  const int b = xcd_tile(blockIdx.x, nb);
+  const MacBlock mb{K, w, (b % gx) * MBX, (b / gx) * MBY, &L};
   const int tid = threadIdx.y * MBX + threadIdx.x;
   mb.p0(tid);
   __syncthreads();
