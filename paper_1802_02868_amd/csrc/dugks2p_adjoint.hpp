@@ -903,12 +903,18 @@ void seq_adjoint_segment(Ex &ex, const Consts &K, const AdjBufs &B, const double
   for (int n = 0; n < nsteps; ++n) {
     const Work w = B.tape(n);
     const double *src = n == 0 ? pops0 : B.state(n);
-    // the tape: cell fields and bar+ of the step (staged stages up to Step 2)
+    // the tape: cell fields of the step and bar+.  bar+ is written by the
+    // fused step's tile kernel, which computes it with the same arithmetic
+    // (FCell only for the segment's last step, which has no fused step)
     seq_staged_macros(ex, K, w, src);
-    ex.grid(FCell<double, double>{K, w, src}, K.nx, K.ny);
+    if (n + 1 == nsteps)
+      ex.grid(FCell<double, double>{K, w, src}, K.nx, K.ny);
+    else
+      ex.grid(FCellFields<double>{K, w}, K.nx, K.ny);
     // the next state, from the fused step (bitwise equal to the staged one)
     if (n + 1 < nsteps) {
       const IoF64 a{(double *)src, K.plane}, b{B.state(n + 1), K.plane};
+      wf.barp = w.barp;
       // after the first step the tile kernel keeps the sums of the state
       // it writes
       if (K.unit)

@@ -444,6 +444,20 @@ struct FCell {
   }
 };
 
+// The cell fields FCell writes besides bar+ (grad p and tau_f), for a tape
+// whose bar+ comes from the tile kernel.
+template <class R>
+struct FCellFields {
+  Consts K;
+  Work w;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    w.dpx[c] = stx(K, K.ax[0].d1, w.p, i, j);
+    w.dpy[c] = sty(K, K.ax[1].d1, w.p, i, j);
+    w.tauf[c] = (double)tauf_of<R>(K, (R)w.phi[c], (R)w.rho[c]);
+  }
+};
+
 // R5: value, normal derivative and tangential derivative of a cell field at
 // an interior face between cells L and R (weights of the face).
 struct FaceW {

@@ -531,9 +531,15 @@ struct FusedTile {
 #pragma unroll
     for (int q = 0; q < 18; ++q) L->u.A[q][ly][lx] = (double)out[q];
     // tilde+ of the tile's own cells waits in LDS for P4, rounded as the
-    // state encoding would round it
+    // state encoding would round it; bar+ of those cells also goes to
+    // w.barp when it is set (the adjoint's tape)
     if (lx >= 1 && lx <= S::TX && ly >= 1 && ly <= S::TY && x0 + lx - 1 < K.nx &&
         y0 + ly - 1 < K.ny) {
+      if (w.barp) {
+        const i64 c = (i64)gy * K.ld + gx;
+#pragma unroll
+        for (int q = 0; q < 18; ++q) w.barp[q * K.plane + c] = (double)out[q];
+      }
       double tv[18];
 #pragma unroll
       for (int q = 0; q < 18; ++q)
