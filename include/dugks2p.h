@@ -165,9 +165,10 @@ int dugks2p_kernel(const dugks2p *h);
  * staged form reports DUGKS2P_TILE_SQUARE). */
 int dugks2p_tile(const dugks2p *h);
 
-/* Measurement aid.  While enabled, each step records a HIP event before and
- * after its tile kernel (the fused form's Steps 2-6 kernel) on the handle's
- * stream, which adds a small gap between launches.  dugks2p_profile(h, 1)
+/* Measurement aid.  While enabled, each step's tile kernel (the fused
+ * form's Steps 2-6 kernel) is launched with a pair of HIP events that the
+ * launch itself sets to the kernel's start and end on the handle's stream
+ * (no marker packets between launches).  dugks2p_profile(h, 1)
  * enables and clears the record, (h, 0) disables it.  dugks2p_profile_read
  * synchronises the stream, writes the summed kernel time in milliseconds
  * (host *ms) and the number of timed launches (host *launches; 0 for the

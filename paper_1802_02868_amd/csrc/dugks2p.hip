@@ -1,5 +1,6 @@
 // dugks2p.hip -- C-ABI runtime of the MI355X two-phase DUGKS library
 // (declarations and argument contracts in include/dugks2p.h).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <stdio.h>
@@ -41,21 +42,25 @@ __global__ __launch_bounds__(256) void k_grid(F f, int n0, int n1, int gx, int n
   if (i < n0 && j < n1) f(i, j);
 }
 
-// Event pairs recorded around the tile-kernel launches of a handle while
-// timing is enabled (dugks2p_profile); events are created on first use and
-// reused.
+// Event pairs of the tile-kernel launches of a handle while timing is
+// enabled (dugks2p_profile).  The launch itself sets them to the kernel's
+// start and end (hipExtLaunchKernelGGL), so no marker packets are timed.
+// Events are created on first use and reused.
 struct KernelTimer {
   std::vector<hipEvent_t> ev;
   size_t used = 0;
   bool on = false;
-  hipError_t record(hipStream_t s) {
-    if (used == ev.size()) {
+  hipError_t pair(hipEvent_t &a, hipEvent_t &b) {
+    while (ev.size() < used + 2) {
       hipEvent_t e;
       const hipError_t r = hipEventCreate(&e);
       if (r != hipSuccess) return r;
       ev.push_back(e);
     }
-    return hipEventRecord(ev[used++], s);
+    a = ev[used];
+    b = ev[used + 1];
+    used += 2;
+    return hipSuccess;
   }
 };
 
@@ -79,12 +84,15 @@ struct GpuEx {
   template <class IO, class R, bool U, class S>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
-    const bool timed = kt && kt->on;
-    if (timed) note(kt->record(s));
-    hipLaunchKernelGGL((k_fused_tile<IO, R, U, S>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst,
-                       ntx, nt);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (kt && kt->on) note(kt->pair(e0, e1));
+    if (e0)
+      hipExtLaunchKernelGGL((k_fused_tile<IO, R, U, S>), dim3(nt), dim3(NTHR), 0, s, e0, e1, 0, K,
+                            w, src, dst, ntx, nt);
+    else
+      hipLaunchKernelGGL((k_fused_tile<IO, R, U, S>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst,
+                         ntx, nt);
     note(hipGetLastError());
-    if (timed) note(kt->record(s));
   }
   void note(hipError_t e) {
     if (e != hipSuccess && err == hipSuccess) err = e;
