@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "dugks2p_adjoint.hpp"
 #include "dugks2p_fused.hpp"
 #include "dugks2p_host.hpp"
 
@@ -92,6 +93,12 @@ struct GpuEx {
     else
       hipLaunchKernelGGL((k_fused_tile<IO, R, U, S>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst,
                          ntx, nt);
+    note(hipGetLastError());
+  }
+  // the adjoint's face stage over square tiles
+  void adj_faces(const Consts &K, const Work &w, const AdjWork &a) {
+    const int ntx = tiles_x<TileSq>(K), nt = ntx * tiles_y<TileSq>(K);
+    hipLaunchKernelGGL(k_adj_faces<TileSq>, dim3(nt), dim3(NTHR), 0, s, K, w, a, ntx, nt);
     note(hipGetLastError());
   }
   void note(hipError_t e) {

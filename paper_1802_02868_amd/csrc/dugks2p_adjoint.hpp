@@ -269,132 +269,222 @@ DFN FaceBack face_dist_vjp(const Consts &K, const FaceFields<double> &fl, const 
 // Face stage: adjoint of the face distributions from the update (eq.
 // updatef), then of Step 4 and of the bounce-back copies; the adjoint of bar
 // and of the face fields go to the face record.
-template <int A>
-struct FAdjFace {
-  Consts K;
-  Work w;
-  AdjWork a;
-  DFN void operator()(int p0, int p1) const {
-    const int k = A == 0 ? p0 : p1, t = A == 0 ? p1 : p0;
-    const Axis &ax = K.ax[A];
-    const int cl = ax_fl(ax, k), cr = ax_fr(ax, k);
-    const GAcc acc{&K, &w};
-    const int TA = 1 - A;
-    const i64 fpl = A == 0 ? K.xplane : K.yplane;
-    double *rec = (A == 0 ? a.xs + (i64)t * K.nfx + k : a.ys + (i64)k * K.ld + t);
-    const bool wall = cl < 0 || cr < 0;
-    const int nout = cl < 0 ? -1 : 1;  // outward normal of the fluid cell (walls)
-    const i64 P = K.plane;
-    const i64 cL = cl >= 0 ? (A == 0 ? (i64)t * K.ld + cl : (i64)cl * K.ld + t) : 0;
-    const i64 cR = cr >= 0 ? (A == 0 ? (i64)t * K.ld + cr : (i64)cr * K.ld + t) : 0;
-    const double rL = cl >= 0 ? ax.rdt[cl] : 0.0, rR = cr >= 0 ? ax.rdt[cr] : 0.0;
-    const double *lam = a.lam;
-    // the face value enters the update of cell L with -r_L xi_n and of
-    // cell R with +r_R xi_n; at a wall the entering values are copies of
-    // the outgoing opposite ones, so their adjoint folds onto those
-    auto ob_raw = [&](int q) {
-      const double xn = A == 0 ? K.xi0[q % 9] : K.xi1[q % 9];
-      double v = 0.0;
-      if (cl >= 0) v += -(rL * xn) * lam[q * P + cL];
-      if (cr >= 0) v += (rR * xn) * lam[q * P + cR];
-      return v;
-    };
-    auto en_of = [&](int q) { return A == 0 ? ex_of(q % 9) : ey_of(q % 9); };
-    auto ob = [&](int q) {
-      const int en = en_of(q);
-      if (wall && en * nout < 0) return 0.0;
-      double v = ob_raw(q);
-      if (wall && en * nout > 0) v += ob_raw(q - q % 9 + opp_of(q % 9));
-      return v;
-    };
-    const double h = K.h;
-    double bar[18];
-    FaceFields<double> fl, fb;
-    fb.mu = fb.D = fb.gmx = fb.gmy = fb.gfx = fb.gfy = fb.gpx = fb.gpy = 0.0;
-    double gxb = 0.0, gyb = 0.0;
-    if (wall) {
-      const int cc = cl < 0 ? cr : cl;
-      const double off = cl < 0 ? ax.foffr[k] : ax.foffl[k];
-      const GAcc::H HC = acc.cell(A == 0 ? cc : t, A == 0 ? t : cc);
-#pragma unroll
-      for (int q = 0; q < 18; ++q) {
-        const int i = q % 9;
-        if (en_of(q) * nout < 0) continue;
-        const double Gn = acc.pgrad(A, q, HC), Gt = acc.pgrad(TA, q, HC);
-        const double val = acc.A(q, HC) + off * Gn;
-        const double sgx = A == 0 ? Gn : Gt, sgy = A == 0 ? Gt : Gn;
-        bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
-      }
-#pragma unroll
-      for (int q = 0; q < 18; ++q)
-        if (en_of(q) * nout < 0) bar[q] = bar[q - q % 9 + opp_of(q % 9)];
-      fl.mu = acc.mu(HC);
-      fl.D = acc.D(HC);
-      const double tmu = acc.dmu(TA, HC), tph = acc.dphi(TA, HC), tp = acc.dp(TA, HC);
-      fl.gmx = A == 0 ? 0.0 : tmu;
-      fl.gmy = A == 0 ? tmu : 0.0;
-      fl.gfx = A == 0 ? 0.0 : tph;
-      fl.gfy = A == 0 ? tph : 0.0;
-      fl.gpx = A == 0 ? 0.0 : tp;
-      fl.gpy = A == 0 ? tp : 0.0;
-    } else {
-      const GAcc::H HL = acc.cell(A == 0 ? cl : t, A == 0 ? t : cl);
-      const GAcc::H HR = acc.cell(A == 0 ? cr : t, A == 0 ? t : cr);
-      const FaceW fw{ax.fwl[k], ax.fwr[k], ax.finv[k]};
-#pragma unroll
-      for (int q = 0; q < 18; ++q) {
-        const int i = q % 9;
-        const double AL = acc.A(q, HL), AR = acc.A(q, HR);
-        const double val = fw.wl * AL + fw.wr * AR;
-        const double sn = (AR - AL) * fw.inv;
-        const double st = fw.wl * acc.pgrad(TA, q, HL) + fw.wr * acc.pgrad(TA, q, HR);
-        const double sgx = A == 0 ? sn : st, sgy = A == 0 ? st : sn;
-        bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
-      }
-      double v, tmp, gn, gt;
-      face_field(fw, acc.mu(HL), acc.mu(HR), acc.dmu(TA, HL), acc.dmu(TA, HR), v, gn, gt);
-      fl.mu = v;
-      fl.gmx = A == 0 ? gn : gt;
-      fl.gmy = A == 0 ? gt : gn;
-      face_field(fw, acc.D(HL), acc.D(HR), 0.0, 0.0, v, tmp, tmp);
-      fl.D = v;
-      face_field(fw, acc.phi(HL), acc.phi(HR), acc.dphi(TA, HL), acc.dphi(TA, HR), tmp, gn, gt);
-      fl.gfx = A == 0 ? gn : gt;
-      fl.gfy = A == 0 ? gt : gn;
-      face_field(fw, acc.p(HL), acc.p(HR), acc.dp(TA, HL), acc.dp(TA, HR), tmp, gn, gt);
-      fl.gpx = A == 0 ? gn : gt;
-      fl.gpy = A == 0 ? gt : gn;
-    }
-    const FaceBack r = face_dist_vjp(K, fl, bar, ob, fb, gxb, gyb);
-    auto barb = [&](int q) {
-      const int i = q % 9;
-      return q < 9 ? r.fk1 * ob(q) + (r.s0b + K.xi0[i] * r.jxb + K.xi1[i] * r.jyb)
-                   : K.gk1 * ob(q) + r.phibb;
-    };
+// Face k of axis A at tangential index t (0: x-face between cells (k-1, t)
+// and (k, t); 1: y-face between (t, k-1) and (t, k)).  Acc provides the
+// tape's bar+ and cell fields with their derivatives (GAcc from the global
+// tape, LAcc from a tile window in LDS: the same values).
+template <int A, class Acc>
+DFN void adj_face(const Consts &K, const Acc &acc, const AdjWork &a, int k, int t) {
+  const Axis &ax = K.ax[A];
+  const int cl = ax_fl(ax, k), cr = ax_fr(ax, k);
+  const int TA = 1 - A;
+  const i64 fpl = A == 0 ? K.xplane : K.yplane;
+  double *rec = (A == 0 ? a.xs + (i64)t * K.nfx + k : a.ys + (i64)k * K.ld + t);
+  const bool wall = cl < 0 || cr < 0;
+  const int nout = cl < 0 ? -1 : 1;  // outward normal of the fluid cell (walls)
+  const i64 P = K.plane;
+  const i64 cL = cl >= 0 ? (A == 0 ? (i64)t * K.ld + cl : (i64)cl * K.ld + t) : 0;
+  const i64 cR = cr >= 0 ? (A == 0 ? (i64)t * K.ld + cr : (i64)cr * K.ld + t) : 0;
+  const double rL = cl >= 0 ? ax.rdt[cl] : 0.0, rR = cr >= 0 ? ax.rdt[cr] : 0.0;
+  const double *lam = a.lam;
+  // the face value enters the update of cell L with -r_L xi_n and of
+  // cell R with +r_R xi_n; at a wall the entering values are copies of
+  // the outgoing opposite ones, so their adjoint folds onto those
+  auto ob_raw = [&](int q) {
+    const double xn = A == 0 ? K.xi0[q % 9] : K.xi1[q % 9];
+    double v = 0.0;
+    if (cl >= 0) v += -(rL * xn) * lam[q * P + cL];
+    if (cr >= 0) v += (rR * xn) * lam[q * P + cR];
+    return v;
+  };
+  auto en_of = [&](int q) { return A == 0 ? ex_of(q % 9) : ey_of(q % 9); };
+  auto ob = [&](int q) {
+    const int en = en_of(q);
+    if (wall && en * nout < 0) return 0.0;
+    double v = ob_raw(q);
+    if (wall && en * nout > 0) v += ob_raw(q - q % 9 + opp_of(q % 9));
+    return v;
+  };
+  const double h = K.h;
+  double bar[18];
+  FaceFields<double> fl, fb;
+  fb.mu = fb.D = fb.gmx = fb.gmy = fb.gfx = fb.gfy = fb.gpx = fb.gpy = 0.0;
+  double gxb = 0.0, gyb = 0.0;
+  if (wall) {
+    const int cc = cl < 0 ? cr : cl;
+    const double off = cl < 0 ? ax.foffr[k] : ax.foffl[k];
+    const typename Acc::H HC = acc.cell(A == 0 ? cc : t, A == 0 ? t : cc);
 #pragma unroll
     for (int q = 0; q < 18; ++q) {
-      const int en = en_of(q);
-      double v;
-      if (wall && en * nout < 0)
-        v = 0.0;
-      else if (wall && en * nout > 0)
-        v = barb(q) + barb(q - q % 9 + opp_of(q % 9));
-      else
-        v = barb(q);
-      rec[(FS_B + q) * fpl] = v;
+      const int i = q % 9;
+      if (en_of(q) * nout < 0) continue;
+      const double Gn = acc.pgrad(A, q, HC), Gt = acc.pgrad(TA, q, HC);
+      const double val = acc.A(q, HC) + off * Gn;
+      const double sgx = A == 0 ? Gn : Gt, sgy = A == 0 ? Gt : Gn;
+      bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
     }
-    rec[FS_MU * fpl] = fb.mu;
-    rec[FS_D * fpl] = fb.D;
-    rec[FS_GMX * fpl] = fb.gmx;
-    rec[FS_GMY * fpl] = fb.gmy;
-    rec[FS_GFX * fpl] = fb.gfx;
-    rec[FS_GFY * fpl] = fb.gfy;
-    rec[FS_GPX * fpl] = fb.gpx;
-    rec[FS_GPY * fpl] = fb.gpy;
-    rec[FS_GX * fpl] = gxb;
-    rec[FS_GY * fpl] = gyb;
+#pragma unroll
+    for (int q = 0; q < 18; ++q)
+      if (en_of(q) * nout < 0) bar[q] = bar[q - q % 9 + opp_of(q % 9)];
+    fl.mu = acc.mu(HC);
+    fl.D = acc.D(HC);
+    const double tmu = acc.dmu(TA, HC), tph = acc.dphi(TA, HC), tp = acc.dp(TA, HC);
+    fl.gmx = A == 0 ? 0.0 : tmu;
+    fl.gmy = A == 0 ? tmu : 0.0;
+    fl.gfx = A == 0 ? 0.0 : tph;
+    fl.gfy = A == 0 ? tph : 0.0;
+    fl.gpx = A == 0 ? 0.0 : tp;
+    fl.gpy = A == 0 ? tp : 0.0;
+  } else {
+    const typename Acc::H HL = acc.cell(A == 0 ? cl : t, A == 0 ? t : cl);
+    const typename Acc::H HR = acc.cell(A == 0 ? cr : t, A == 0 ? t : cr);
+    const FaceW fw{ax.fwl[k], ax.fwr[k], ax.finv[k]};
+#pragma unroll
+    for (int q = 0; q < 18; ++q) {
+      const int i = q % 9;
+      const double AL = acc.A(q, HL), AR = acc.A(q, HR);
+      const double val = fw.wl * AL + fw.wr * AR;
+      const double sn = (AR - AL) * fw.inv;
+      const double st = fw.wl * acc.pgrad(TA, q, HL) + fw.wr * acc.pgrad(TA, q, HR);
+      const double sgx = A == 0 ? sn : st, sgy = A == 0 ? st : sn;
+      bar[q] = val - h * (K.xi0[i] * sgx + K.xi1[i] * sgy);
+    }
+    double v, tmp, gn, gt;
+    face_field(fw, acc.mu(HL), acc.mu(HR), acc.dmu(TA, HL), acc.dmu(TA, HR), v, gn, gt);
+    fl.mu = v;
+    fl.gmx = A == 0 ? gn : gt;
+    fl.gmy = A == 0 ? gt : gn;
+    face_field(fw, acc.D(HL), acc.D(HR), 0.0, 0.0, v, tmp, tmp);
+    fl.D = v;
+    face_field(fw, acc.phi(HL), acc.phi(HR), acc.dphi(TA, HL), acc.dphi(TA, HR), tmp, gn, gt);
+    fl.gfx = A == 0 ? gn : gt;
+    fl.gfy = A == 0 ? gt : gn;
+    face_field(fw, acc.p(HL), acc.p(HR), acc.dp(TA, HL), acc.dp(TA, HR), tmp, gn, gt);
+    fl.gpx = A == 0 ? gn : gt;
+    fl.gpy = A == 0 ? gt : gn;
+  }
+  const FaceBack r = face_dist_vjp(K, fl, bar, ob, fb, gxb, gyb);
+  auto barb = [&](int q) {
+    const int i = q % 9;
+    return q < 9 ? r.fk1 * ob(q) + (r.s0b + K.xi0[i] * r.jxb + K.xi1[i] * r.jyb)
+                 : K.gk1 * ob(q) + r.phibb;
+  };
+#pragma unroll
+  for (int q = 0; q < 18; ++q) {
+    const int en = en_of(q);
+    double v;
+    if (wall && en * nout < 0)
+      v = 0.0;
+    else if (wall && en * nout > 0)
+      v = barb(q) + barb(q - q % 9 + opp_of(q % 9));
+    else
+      v = barb(q);
+    rec[(FS_B + q) * fpl] = v;
+  }
+  rec[FS_MU * fpl] = fb.mu;
+  rec[FS_D * fpl] = fb.D;
+  rec[FS_GMX * fpl] = fb.gmx;
+  rec[FS_GMY * fpl] = fb.gmy;
+  rec[FS_GFX * fpl] = fb.gfx;
+  rec[FS_GFY * fpl] = fb.gfy;
+  rec[FS_GPX * fpl] = fb.gpx;
+  rec[FS_GPY * fpl] = fb.gpy;
+  rec[FS_GX * fpl] = gxb;
+  rec[FS_GY * fpl] = gyb;
+}
+
+// The face stage over the forward's tiles.  P0 and the tape's bar+ and D on
+// the bar+ window go to LDS (the forward's window layout), then each thread
+// takes the x-face west of its column and the y-face south of its row, as
+// the forward's P2 does, reading the window through LAcc.  A face between
+// two tiles is written once: by the tile whose cells lie east (north) of it,
+// or for the far wall face by the last tile.
+// LDS of the face stage: the forward tile's bar+, scalar and D windows and
+// tables, without tilde+ and the face values (about 49 KB for 14 x 14
+// tiles, so three workgroups fit a CU).
+template <class S>
+struct AdjLds {
+  struct {
+    double A[18][S::WY][S::WX];
+  } u;
+  double phi[S::SY][S::SX], mu[S::SY][S::SX], p[S::SY][S::SX];
+  double D[S::WY][S::WX];
+  double pgw[2][S::SM][3], d1w[2][S::SM][3];
+  double fwl[2][S::FM], fwr[2][S::FM], finv[2][S::FM], foffl[2][S::FM], foffr[2][S::FM];
+  double rdt[2][S::FM];
+};
+
+template <class S>
+struct AdjFaceTile {
+  const Consts &K;
+  const Work &w;  // the step's tape
+  const AdjWork &a;
+  int x0, y0;
+  AdjLds<S> *L;
+  struct PreA {
+    double b[18], D;
+  };
+  using Win = TileP0<S, AdjLds<S>>;
+  DFN Win win() const { return Win{K, w, x0, y0, L}; }
+  // window cell of thread tid and its global index, false outside a wall domain
+  DFN bool cell_of(int tid, int &lx, int &ly, i64 &c) const {
+    lx = tid % S::WX;
+    ly = tid / S::WX;
+    const Win p = win();
+    const int gx = p.gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
+    const int gy = p.gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
+    if (gx < 0 || gy < 0) return false;
+    c = (i64)gy * K.ld + gx;
+    return true;
+  }
+  DFN void a_load(int tid, PreA &r) const {
+    int lx, ly;
+    i64 c;
+    if (!cell_of(tid, lx, ly, c)) return;
+#pragma unroll
+    for (int q = 0; q < 18; ++q) r.b[q] = w.barp[q * K.plane + c];
+    r.D = w.D[c];
+  }
+  DFN void a_store(int tid, const PreA &r) const {
+    int lx, ly;
+    i64 c;
+    if (!cell_of(tid, lx, ly, c)) return;
+#pragma unroll
+    for (int q = 0; q < 18; ++q) L->u.A[q][ly][lx] = r.b[q];
+    L->D[ly][lx] = r.D;
+  }
+  DFN void faces(int tid) const {
+    const int tx = tid % S::WX, ty = tid / S::WX;
+    const LAcc<S, AdjLds<S>> acc{&K, &w, L, x0, y0};
+    if (tx <= S::TX && ty < S::TY) {
+      const int k = x0 + tx, t = y0 + ty;
+      if (t < K.ny && k < K.nfx && (tx < S::TX || k == K.nx)) adj_face<0>(K, acc, a, k, t);
+    }
+    if (tx < S::TX && ty <= S::TY) {
+      const int k = y0 + ty, t = x0 + tx;
+      if (t < K.nx && k < K.nfy && (ty < S::TY || k == K.ny)) adj_face<1>(K, acc, a, k, t);
+    }
   }
 };
+
+#if defined(__HIPCC__)
+template <class S>
+__global__ __launch_bounds__(NTHR) void k_adj_faces(Consts K, Work w, AdjWork a, int ntx,
+                                                    int ntiles) {
+  __shared__ AdjLds<S> L;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const AdjFaceTile<S> ft{K, w, a, (tile % ntx) * S::TX, (tile / ntx) * S::TY, &L};
+  const int tid = threadIdx.x;
+  typename AdjFaceTile<S>::Win::Pre0 r0;
+  typename AdjFaceTile<S>::PreA ra;
+  ft.win().p0_load(tid, r0);
+  ft.a_load(tid, ra);
+  ft.win().p0_store(tid, r0);
+  ft.a_store(tid, ra);
+  __syncthreads();
+  ft.faces(tid);
+}
+#endif
 
 // Geometry of one face of axis A as seen from the cell on side s (0: low
 // side L, 1: high side R): reverse of the face reconstruction of bar (eq.
@@ -740,8 +830,7 @@ struct FAdjInit {
 template <class Ex>
 void seq_adjoint_step(Ex &ex, const Consts &K, const Work &w, const AdjWork &a,
                       const double *st) {
-  ex.grid(FAdjFace<0>{K, w, a}, K.nfx, K.ny);
-  ex.grid(FAdjFace<1>{K, w, a}, K.nx, K.nfy);
+  ex.adj_faces(K, w, a);
   ex.grid(FAdjGather{K, a}, K.nx, K.ny);
   ex.grid(FAdjCell{K, w, a, st}, K.nx, K.ny);
   ex.grid(FAdjMacro{K, w, a, 0}, K.nx, K.ny);

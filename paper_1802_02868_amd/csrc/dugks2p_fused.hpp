@@ -224,11 +224,11 @@ struct TileLds {
 // folded back; a window position holding another image of the same cell
 // holds the same value.  A handle carries the LDS offsets of the cell and of
 // its stencil neighbours, computed once per face.
-template <class S>
+template <class S, class Lds = TileLds<S>>
 struct LAcc {
   const Consts *K;
   const Work *w;
-  const TileLds<S> *L;
+  const Lds *L;
   int x0, y0;
   struct H {
     int x, y;
@@ -353,53 +353,20 @@ DFN int wrapi(int g, int n) {
   return r < 0 ? r + n : r;
 }
 
-// One tile of shape S with origin (x0, y0).
-template <class IO, class R, bool U = false, class S = TileSq>
-struct FusedTile {
+// P0 of a tile with origin (x0, y0): phi, mu, p on the tile and a two-cell
+// ring, the App. B weight rows of the window's columns and rows, and the
+// geometry and dt/|V| factors of the tile's faces and cells, into LDS.
+template <class S, class Lds = TileLds<S>>
+struct TileP0 {
   const Consts &K;
   const Work &w;
-  IO src;
-  IO dst;
   int x0, y0;
-  TileLds<S> *L;
-
-  struct TS {
-    R fx[12], fy[12];
-    bool hx, hy;
-  };
-  // global inputs of a window cell's Step 2, loaded ahead of P0 so that their
-  // latency overlaps P0's loads
-  struct Pre {
-    double tv[18], ux, uy, D, Fx, Fy;
-  };
-
+  Lds *L;
   // global index along an axis of window offset o, or -1 outside a wall domain
   DFN int gcol(int g, int n, int bc) const {
     if (bc == 0) return wrapi(g, n);
     return (g >= 0 && g < n) ? g : -1;
   }
-
-  // window cell of thread tid: global column and row (-1 outside a wall domain)
-  DFN void p1_cell(int tid, int &gx, int &gy) const {
-    const int lx = tid % S::WX, ly = tid / S::WX;
-    gx = gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
-    gy = gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
-  }
-  DFN void p1_load(int tid, Pre &pr) const {
-    int gx, gy;
-    p1_cell(tid, gx, gy);
-    if (gx < 0 || gy < 0) return;
-    const i64 c = (i64)gy * K.ld + gx;
-    src.load(c, pr.tv);
-    pr.ux = w.ux[c];
-    pr.uy = w.uy[c];
-    pr.D = w.D[c];
-    pr.Fx = w.Fx[c];
-    pr.Fy = w.Fy[c];
-  }
-
-  // P0: phi, mu, p on the tile and a two-cell ring, the App. B weight rows
-  // of the window's columns and rows, and the geometry of the tile's faces.
   // All of the phase's global loads are issued (p0_load) before its first
   // LDS store (p0_store), so that they share one memory round trip.  Roles:
   // every thread loads window elements tid and tid + NTHR; the last SX + SY
@@ -496,6 +463,58 @@ struct FusedTile {
       if (f < (a == 0 ? S::TX : S::TY) && k < K.ax[a].n) L->rdt[a][f] = r.t[5];
     }
   }
+};
+
+// One tile of shape S with origin (x0, y0).
+template <class IO, class R, bool U = false, class S = TileSq>
+struct FusedTile {
+  const Consts &K;
+  const Work &w;
+  IO src;
+  IO dst;
+  int x0, y0;
+  TileLds<S> *L;
+
+  struct TS {
+    R fx[12], fy[12];
+    bool hx, hy;
+  };
+  // global inputs of a window cell's Step 2, loaded ahead of P0 so that their
+  // latency overlaps P0's loads
+  struct Pre {
+    double tv[18], ux, uy, D, Fx, Fy;
+  };
+
+  // global index along an axis of window offset o, or -1 outside a wall domain
+  DFN int gcol(int g, int n, int bc) const {
+    if (bc == 0) return wrapi(g, n);
+    return (g >= 0 && g < n) ? g : -1;
+  }
+
+  // window cell of thread tid: global column and row (-1 outside a wall domain)
+  DFN void p1_cell(int tid, int &gx, int &gy) const {
+    const int lx = tid % S::WX, ly = tid / S::WX;
+    gx = gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
+    gy = gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
+  }
+  DFN void p1_load(int tid, Pre &pr) const {
+    int gx, gy;
+    p1_cell(tid, gx, gy);
+    if (gx < 0 || gy < 0) return;
+    const i64 c = (i64)gy * K.ld + gx;
+    src.load(c, pr.tv);
+    pr.ux = w.ux[c];
+    pr.uy = w.uy[c];
+    pr.D = w.D[c];
+    pr.Fx = w.Fx[c];
+    pr.Fy = w.Fy[c];
+  }
+
+  // P0 (see TileP0)
+  using Pre0 = typename TileP0<S>::Pre0;
+  DFN TileP0<S> win() const { return TileP0<S>{K, w, x0, y0, L}; }
+  DFN void p0_load(int tid, Pre0 &r) const { win().p0_load(tid, r); }
+  DFN void p0_store(int tid, const Pre0 &r) const { win().p0_store(tid, r); }
 
   // P1: Step 2 on the tile and a one-cell ring; tilde+ kept for the tile.
   DFN void p1(int tid, const Pre &pr) const {

@@ -36,6 +36,26 @@ struct CpuEx {
         for (int t = 0; t < MBX * MBY; ++t) mb.p1(t);
       }
   }
+  // the adjoint's face stage: every workgroup in turn, phase by phase
+  void adj_faces(const Consts &K, const Work &w, const AdjWork &a) {
+    using S = TileSq;
+    const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
+    std::vector<AdjLds<S>> L(1);
+    std::vector<typename AdjFaceTile<S>::Win::Pre0> r0(NTHR);
+    std::vector<typename AdjFaceTile<S>::PreA> ra(NTHR);
+    for (int b = 0; b < nt; ++b) {
+      const int tile = xcd_tile(b, nt);
+      memset((void *)L.data(), 0xff, sizeof(AdjLds<S>));  // NaN poison: stray reads show
+      memset((void *)r0.data(), 0xff, r0.size() * sizeof(r0[0]));
+      memset((void *)ra.data(), 0xff, ra.size() * sizeof(ra[0]));
+      const AdjFaceTile<S> ft{K, w, a, (tile % ntx) * S::TX, (tile / ntx) * S::TY, L.data()};
+      for (int t = 0; t < NTHR; ++t) ft.win().p0_load(t, r0[t]);
+      for (int t = 0; t < NTHR; ++t) ft.a_load(t, ra[t]);
+      for (int t = 0; t < NTHR; ++t) ft.win().p0_store(t, r0[t]);
+      for (int t = 0; t < NTHR; ++t) ft.a_store(t, ra[t]);
+      for (int t = 0; t < NTHR; ++t) ft.faces(t);
+    }
+  }
   template <class IO, class R, bool U, class S>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);

@@ -102,3 +102,29 @@ def test_adjoint_dot_product_longer_rollout(oracle_mod):
     lhs = float(np.sum(lam * jv))
     rhs = float(np.sum(g0 * d)) + float(g3 @ dp)
     assert abs(lhs - rhs) <= 1e-12 * float(np.sum(np.abs(lam * jv))), (lhs, rhs)
+
+
+def _tile_edge_cases():
+    from paper_1802_02868_amd import workloads as W
+    out = []
+    for case in [W.bubble_case(14, 28, 30.0, 1e-3), W.bubble_case(15, 29, 30.0, 1e-3),
+                 W.drop_case(14, radius=4.0), W.drop_case(15, radius=4.0), W.rt_case(28, 42)]:
+        case.params.update(phi_clamp=0, gx=1e-5)
+        out.append(case)
+    return out
+
+
+@pytest.mark.parametrize("case", _tile_edge_cases(), ids=lambda c: c.name)
+def test_adjoint_dot_product_tile_edges(oracle_mod, case):
+    """Grids of exactly one or two 14 x 14 tiles, one cell over, walls on one
+    or both axes: every face record is written by exactly one tile (a
+    missing one would read the host build's NaN-poisoned workspace)."""
+    rng = np.random.default_rng(3)
+    lam = rng.standard_normal((18, case.ny, case.nx))
+    _, g0, g3 = _emu.adjoint(case, 4, 3, lam)
+    d = rng.standard_normal((case.ny, case.nx))
+    dp = rng.standard_normal(3)
+    _, jv = oracle_mod.complex_step_jvp(case, 4, d, *dp)
+    lhs = float(np.sum(lam * jv))
+    rhs = float(np.sum(g0 * d)) + float(g3 @ dp)
+    assert abs(lhs - rhs) <= 1e-13 * float(np.sum(np.abs(lam * jv))), (lhs, rhs)
