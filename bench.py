@@ -57,7 +57,22 @@ def workload(name: str):
         return W.rt_case(nx)
     if name == "drop64":
         return W.drop_case()
+    if name == "poiseuille4x128":
+        return W.poiseuille_case(4, 128)
+    if name.startswith("bubble"):
+        nx, ny = (int(v) for v in name[6:].split("x"))
+        return W.bubble_case(nx, ny, 30.0, 1e-3)
     raise SystemExit("unknown workload %s" % name)
+
+
+def describe(name: str) -> str:
+    if name.startswith("rt"):
+        return "Rayleigh-Taylor, periodic x, walls in y"
+    if name.startswith("drop"):
+        return "stationary drop, periodic"
+    if name.startswith("poiseuille"):
+        return "layered Poiseuille, stretched y mesh, walls in y"
+    return "rising bubble, Eo 30, Mo 1e-3, four walls"
 
 
 def cpu_baseline(case, seconds=10.0):
@@ -283,8 +298,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == D.FP64 else "f32-state",
         "data": "synthetic",
-        "config": {"workload": "%s %s (%dx%d cells, Rayleigh-Taylor, walls in y)" % (
-            case.name, args.precision, case.nx, case.ny), "cells": cells,
+        "config": {"workload": "%s %s (%dx%d cells, %s)" % (
+            case.name, args.precision, case.nx, case.ny, describe(args.workload)), "cells": cells,
             "kernel": args.kernel, "tile": ["auto", "14x14", "30x6", "6x30"][sim.tile], "dt": sim.dt},
         "roofline": roof,
         "roofline_alu": roof_alu,
