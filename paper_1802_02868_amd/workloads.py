@@ -281,7 +281,8 @@ def table1_initial_phi(radius, n=100, width=4.0):
 
 
 def config(name: str) -> Case:
-    """The five named workloads of the benchmark plan."""
+    """Named workloads: the drop (Sec. 3.1), the layered channel (Sec. 3.2)
+    and Rayleigh-Taylor (Sec. 3.4) at 256 x 1024 and 512 x 2048."""
     if name == "drop64":
         return drop_case()
     if name == "poiseuille4x128":

@@ -1,4 +1,5 @@
-"""Parity at the benchmark plan's full sizes, in the launch configuration
+"""Parity at full workload sizes (RT 256 x 1024, 48 bubbles, RT 512 x 2048),
+in the launch configuration
 bench.py times (fused kernel, square tiles; batch with its tuned tile; the
 adjoint with checkpoints every 50 steps), against the oracle: bit for bit
 for FP64, within 1e-4 for the FP32 state, and the adjoint against the
