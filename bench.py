@@ -252,6 +252,13 @@ def main():
     ms_per_step = ms / max(args.steps, 1)
     mlups = cells * args.steps / (ms / 1e3) / 1e6
     mon = sim.monitors(raise_nonfinite=False)
+    # interface observables (median-level mass, phase-A centroid and velocity,
+    # front and tip): one synchronous call each, after the timed region
+    sim.observables()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        obs = sim.observables()
+    obs_ms = (time.perf_counter() - t0) / 20 * 1e3
 
     # populations read + written once: 18 doubles, or the 76-byte FP32 state
     bytes_per_cell = 288 if prec == D.FP64 else 152
@@ -305,6 +312,9 @@ def main():
         "roofline_alu": roof_alu,
         "wall_s": round(wall, 3),
         "monitor_nonfinite": int(mon[4]),
+        "observables": {"ms_per_call": round(obs_ms, 4), "median_level_cells": int(obs[0]),
+                        "front_y": None if obs[6] != obs[6] else float(obs[6]),
+                        "tip_y": None if obs[7] != obs[7] else float(obs[7])},
     }
     if not args.no_batched:
         out["batched"] = batched_vs_plain(args.batched_steps, D.FP32_STATE)

@@ -145,6 +145,22 @@ int dugks2p_moments(dugks2p *h, double *phi, double *rho, double *ux, double *uy
  * filled). */
 int dugks2p_monitors(dugks2p *h, double out[6]);
 
+/* Interface observables at the current time, host out[8]:
+ *   out[0]  number of cells with phi above the median level
+ *           (phi_A + phi_B)/2: the droplet mass of Sec. 3.1 (Table 1);
+ *   out[1]  the area (sum |V|) of those cells;
+ *   out[2], out[3]  centroid (x, y) of phase A and
+ *   out[4], out[5]  its mean velocity (u_x, u_y), weighted by c |V| with
+ *           c = (phi - phi_B)/(phi_A - phi_B) (the rising bubble, Sec. 3.3);
+ *   out[6], out[7]  highest and lowest y at which the median level is
+ *           crossed between a cell and the cell above it, by linear
+ *           interpolation between the two centres: the bubble front and
+ *           spike tip of Sec. 3.4 (NaN when the level is not crossed).
+ * Positions are in the coordinates of x_faces / y_faces.  Reductions are
+ * FP64 with a fixed order (deterministic); the crossings are exact maxima
+ * and minima.  Syncs the stream. */
+int dugks2p_observables(dugks2p *h, double out[8]);
+
 /* The 18 populations (q = 0..8 f~, 9..17 g~) converted to FP64,
  * [18][ny][nx], into / from device memory. */
 int dugks2p_get_populations(dugks2p *h, double *dst);

@@ -102,6 +102,7 @@ class Oracle:
         if not h:
             raise ValueError(L.orc_last_error().decode())
         self._h = h
+        self._phi_a, self._phi_b = float(params["phi_a"]), float(params["phi_b"])
 
     @classmethod
     def from_case(cls, case, **over):
@@ -141,6 +142,47 @@ class Oracle:
     def monitors(self):
         out = np.empty(6)
         lib().orc_monitors(self._h, _ptr(out))
+        return out
+
+    def observables(self):
+        """Interface observables of the current state, from its moments.
+
+        [0] the number of cells with phi above the median level
+            m = (phi_A + phi_B) / 2: the droplet mass of Sec. 3.1 (Table 1);
+        [1] the area of those cells;
+        [2], [3] the centroid (x, y) of phase A and [4], [5] its mean
+            velocity (u_x, u_y), weighted by c |V| with
+            c = (phi - phi_B) / (phi_A - phi_B);
+        [6], [7] the highest and lowest y at which the median level is
+            crossed between vertically adjacent cell centres, by linear
+            interpolation: the bubble front and spike tip of Sec. 3.4
+            (NaN when the level is not crossed).
+        Plain numpy over the whole grid, in the order written."""
+        m = self.moments()
+        phi, ux, uy = m["phi"], m["ux"], m["uy"]
+        xc = 0.5 * (self._xf[:-1] + self._xf[1:])
+        yc = 0.5 * (self._yf[:-1] + self._yf[1:])
+        V = np.outer(np.diff(self._yf), np.diff(self._xf))
+        mid = 0.5 * (self._phi_a + self._phi_b)
+        above = phi > mid
+        c = (phi - self._phi_b) / (self._phi_a - self._phi_b)
+        wgt = np.sum(c * V)
+        out = np.empty(8)
+        out[0] = np.count_nonzero(above)
+        out[1] = np.sum(V[above])
+        out[2] = np.sum(c * V * xc[None, :]) / wgt
+        out[3] = np.sum(c * V * yc[:, None]) / wgt
+        out[4] = np.sum(c * V * ux) / wgt
+        out[5] = np.sum(c * V * uy) / wgt
+        # rows j and j + 1 of every column; one side above the level, one not
+        p0, p1 = phi[:-1, :], phi[1:, :]
+        cross = (p0 > mid) != (p1 > mid)
+        y0 = np.broadcast_to(yc[:-1, None], p0.shape)[cross]
+        y1 = np.broadcast_to(yc[1:, None], p0.shape)[cross]
+        a, b = p0[cross], p1[cross]
+        ys = y0 + (mid - a) / (b - a) * (y1 - y0)
+        out[6] = ys.max() if ys.size else np.nan
+        out[7] = ys.min() if ys.size else np.nan
         return out
 
     def pops(self):

@@ -163,6 +163,82 @@ __global__ __launch_bounds__(256) void k_mon_final(const double *part, long long
     for (int m = 0; m < 5; ++m) out[m] = sh[m][0];
 }
 
+// Observables (dugks2p_observables): per 64 x 4 block of cells, the sums
+// (cells above the median level, their area, c|V|, c|V| x, c|V| y, c|V| u_x,
+// c|V| u_y with c = (phi - phi_B)/(phi_A - phi_B)) and the largest and
+// smallest y of the median-level crossings between each cell and the cell
+// above it; then one workgroup adds the partials in block order (the sums
+// are deterministic; max and min are exact).
+enum { NOBS = 9 };
+__global__ __launch_bounds__(256) void k_obs_partial(Consts K, Work w, const double *xc,
+                                                     const double *yc, double *part) {
+  __shared__ double sh[NOBS][256];
+  const int t = threadIdx.y * 64 + threadIdx.x;
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
+  double v[NOBS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, INFINITY};
+  if (i < K.nx && j < K.ny) {
+    const i64 c = (i64)j * K.ld + i;
+    const double V = K.ax[0].w[i] * K.ax[1].w[j];
+    const double ph = w.phi[c], mid = 0.5 * (K.phi_a + K.phi_b);
+    const double cv = (ph - K.phi_b) / (K.phi_a - K.phi_b) * V;
+    if (ph > mid) {
+      v[0] = 1.0;
+      v[1] = V;
+    }
+    v[2] = cv;
+    v[3] = cv * xc[i];
+    v[4] = cv * yc[j];
+    v[5] = cv * w.ux[c];
+    v[6] = cv * w.uy[c];
+    if (j + 1 < K.ny) {
+      const double p1 = w.phi[c + K.ld];
+      if ((ph > mid) != (p1 > mid)) {
+        const double y = yc[j] + (mid - ph) / (p1 - ph) * (yc[j + 1] - yc[j]);
+        v[7] = y;
+        v[8] = y;
+      }
+    }
+  }
+  for (int m = 0; m < NOBS; ++m) sh[m][t] = v[m];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      for (int m = 0; m < NOBS; ++m) {
+        const double a = sh[m][t], b = sh[m][t + s];
+        sh[m][t] = m == 7 ? (a > b ? a : b) : (m == 8 ? (a < b ? a : b) : a + b);
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    for (int m = 0; m < NOBS; ++m) part[NOBS * b + m] = sh[m][0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_obs_final(const double *part, long long nb, double *out) {
+  __shared__ double sh[NOBS][256];
+  const int t = threadIdx.x;
+  double v[NOBS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, INFINITY};
+  for (long long b = t; b < nb; b += 256)
+    for (int m = 0; m < NOBS; ++m) {
+      const double x = part[NOBS * b + m];
+      v[m] = m == 7 ? (v[m] > x ? v[m] : x) : (m == 8 ? (v[m] < x ? v[m] : x) : v[m] + x);
+    }
+  for (int m = 0; m < NOBS; ++m) sh[m][t] = v[m];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s)
+      for (int m = 0; m < NOBS; ++m) {
+        const double a = sh[m][t], b = sh[m][t + s];
+        sh[m][t] = m == 7 ? (a > b ? a : b) : (m == 8 ? (a < b ? a : b) : a + b);
+      }
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int m = 0; m < NOBS; ++m) out[m] = sh[m][0];
+}
+
 // State <-> FP64 [18][ny][nx], one thread per cell.
 template <class IO>
 __global__ __launch_bounds__(256) void k_pops_out(Consts K, IO st, double *dst) {
@@ -199,6 +275,7 @@ struct dugks2p {
   int cur;
   Work w;
   double *mon_part, *mon_out;
+  double *xc, *yc;  // cell centres (device)
   int64_t nstep;
   KernelTimer kt;
   bool sums_ok;  // w.phi, s0, jx, jy hold the sums of state[cur]
@@ -399,7 +476,19 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
     h->state[0] = h->ws + pr.L.state[0];
     h->state[1] = h->ws + pr.L.state[1];
     h->mon_part = (double *)(h->ws + pr.L.mon);
-    h->mon_out = h->mon_part + 5 * pr.L.mon_blocks;
+    h->mon_out = h->mon_part + NOBS * pr.L.mon_blocks;
+    h->xc = (double *)(h->ws + pr.L.centres);
+    h->yc = h->xc + pr.K.nx;
+    {
+      std::vector<double> cc(pr.ax.c);
+      cc.insert(cc.end(), pr.ay.c.begin(), pr.ay.c.end());
+      if (hipMemcpyAsync(h->xc, cc.data(), sizeof(double) * cc.size(), hipMemcpyHostToDevice,
+                         h->stream) != hipSuccess ||
+          hipStreamSynchronize(h->stream) != hipSuccess) {
+        rc = fail(DUGKS2P_EHIP, "centre upload");
+        break;
+      }
+    }
     if (hipMemsetAsync(h->state[0], 0, pr.L.state_bytes, h->stream) != hipSuccess ||
         hipMemsetAsync(h->state[1], 0, pr.L.state_bytes, h->stream) != hipSuccess) {
       rc = fail(DUGKS2P_EHIP, "state clear");
@@ -473,6 +562,32 @@ int dugks2p_monitors(dugks2p *h, double out[6]) {
   out[4] = v[4];
   out[5] = (double)h->nstep;
   if (v[4] > 0.0) return fail(DUGKS2P_ENONFINITE, "non-finite populations in the state");
+  return DUGKS2P_OK;
+}
+
+int dugks2p_observables(dugks2p *h, double out[8]) {
+  if (!h || !out) return fail(DUGKS2P_EINVAL, "NULL argument");
+  const int rc = launch_macros(h);
+  if (rc) return rc;
+  const dim3 b(64, 4), g((h->K.nx + 63) / 64, (h->K.ny + 3) / 4);
+  const long long nb = (long long)g.x * g.y;
+  if (nb > (long long)h->L.mon_blocks) return fail(DUGKS2P_EHIP, "partial buffer too small");
+  hipLaunchKernelGGL(k_obs_partial, g, b, 0, h->stream, h->K, h->w, (const double *)h->xc,
+                     (const double *)h->yc, h->mon_part);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, h->stream, h->mon_part, nb, h->mon_out);
+  HIPCHK(hipGetLastError());
+  double v[NOBS];
+  HIPCHK(hipMemcpyAsync(v, h->mon_out, sizeof v, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out[0] = v[0];
+  out[1] = v[1];
+  out[2] = v[3] / v[2];
+  out[3] = v[4] / v[2];
+  out[4] = v[5] / v[2];
+  out[5] = v[6] / v[2];
+  out[6] = v[7] == -INFINITY ? NAN : v[7];
+  out[7] = v[8] == INFINITY ? NAN : v[8];
   return DUGKS2P_OK;
 }
 

@@ -266,7 +266,8 @@ struct Layout {
   size_t state[2];   // ping-pong population buffers
   size_t work;       // 13 cell fields (+3 for the staged kernels)
   size_t barp, facex, facey;  // staged kernels only
-  size_t mon;        // monitor partials
+  size_t mon;        // monitor and observable partials (9 per 64 x 4 block)
+  size_t centres;    // cell centres of both axes (nx + ny doubles)
   size_t total;
   size_t state_bytes;
   size_t f32_planes;  // byte offset of the FP64 phi plane in an FP32 state
@@ -315,9 +316,11 @@ inline Layout make_layout(const Consts &K, const AxisHost &ax, const AxisHost &a
   } else {
     L.barp = L.facex = L.facey = 0;
   }
-  L.mon_blocks = ((size_t)K.ny * ((K.nx + 63) / 64) + 3) / 4 + 1;
+  L.mon_blocks = (size_t)((K.nx + 63) / 64) * ((K.ny + 3) / 4);
   L.mon = off;
-  off += align256(sizeof(double) * (5 * L.mon_blocks + 8));
+  off += align256(sizeof(double) * (9 * L.mon_blocks + 16));
+  L.centres = off;
+  off += align256(sizeof(double) * ((size_t)K.nx + K.ny));
   L.total = off;
   return L;
 }

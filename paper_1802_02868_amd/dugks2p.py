@@ -49,6 +49,8 @@ def _load():
     L.dugks2p_moments.argtypes = [vp, vp, vp, vp, vp, vp]
     L.dugks2p_monitors.restype = ctypes.c_int
     L.dugks2p_monitors.argtypes = [vp, P(d)]
+    L.dugks2p_observables.restype = ctypes.c_int
+    L.dugks2p_observables.argtypes = [vp, P(d)]
     L.dugks2p_get_populations.restype = ctypes.c_int
     L.dugks2p_get_populations.argtypes = [vp, vp]
     L.dugks2p_set_populations.restype = ctypes.c_int
@@ -108,7 +110,8 @@ def _load():
 lib = _load()
 
 EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2p_moments",
-            "dugks2p_monitors", "dugks2p_get_populations", "dugks2p_set_populations",
+            "dugks2p_monitors", "dugks2p_observables", "dugks2p_get_populations",
+            "dugks2p_set_populations",
             "dugks2p_state_bytes", "dugks2p_get_state", "dugks2p_set_state", "dugks2p_dt",
             "dugks2p_step_count", "dugks2p_kernel", "dugks2p_tile", "dugks2p_destroy",
             "dugks2p_last_error",
@@ -242,6 +245,13 @@ class Simulation:
         rc = lib.dugks2p_monitors(self._h, out)
         if rc != OK and (raise_nonfinite or rc != ENONFINITE):
             _check(rc)
+        return np.array(out[:])
+
+    def observables(self):
+        """[droplet cells, their area, phase-A centroid x, y, mean u_x, u_y,
+        highest and lowest median-level y] (include/dugks2p.h)."""
+        out = (ctypes.c_double * 8)()
+        _check(lib.dugks2p_observables(self._h, out))
         return np.array(out[:])
 
     def populations(self):

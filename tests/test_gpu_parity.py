@@ -79,6 +79,40 @@ def test_monitors_match_oracle(D, oracle_mod):
     assert g[4] == 0 and g[5] == 50
 
 
+OBS_CASES = [("drop48", lambda: W.drop_case(n=48, radius=12.0), 40),
+             ("rt32x128", lambda: W.rt_case(32, ny=128, amp_frac=0.2), 60),
+             ("bubble40x80", lambda: W.bubble_case(40, 80, 20.0, 1e-3), 30),
+             ("rt130x5", lambda: W.rt_case(130, ny=5), 3)]
+
+
+@pytest.mark.parametrize("name", [c[0] for c in OBS_CASES])
+def test_observables_match_oracle(D, oracle_mod, name):
+    """Interface observables on the GPU against the oracle's, after some fused
+    FP64 steps: the median-level count and the crossings exactly (phi is the
+    oracle's bit for bit), the weighted sums to rounding.  130 x 5 has three
+    64-wide block columns and a partial row block (partial buffer sizing)."""
+    make, steps = [(m, s) for n, m, s in OBS_CASES if n == name][0]
+    case = make()
+    print("observables:", name, steps, flush=True)
+    sim = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)
+    sim.step(steps)
+    g = sim.observables()
+    mon = sim.monitors()
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    r = o.observables()
+    assert g[0] == r[0] and g[1] == pytest.approx(r[1], rel=1e-13)
+    for k in (2, 3):
+        assert abs(g[k] - r[k]) <= 1e-12 * max(abs(r[k]), 1.0), (k, g[k], r[k])
+    # mean velocities: sums with cancellation, so to rounding of max |u|
+    umax = o.monitors()[3]
+    for k in (4, 5):
+        assert abs(g[k] - r[k]) <= 1e-12 * umax, (k, g[k], r[k], umax)
+    for k in (6, 7):
+        assert (np.isnan(g[k]) and np.isnan(r[k])) or g[k] == r[k], (k, g[k], r[k])
+    assert mon[4] == 0
+
+
 def test_checkpoint_resume_bitwise(D):
     case = W.rt_case(32, ny=64, amp_frac=0.2)
     a = D.Simulation.from_case(case, kernel=D.KERNEL_STAGED)

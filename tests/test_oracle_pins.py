@@ -7,6 +7,7 @@ linear reconstruction, invariants (conservation, symmetries, fixed points),
 printed numbers (Table 1, the rising-bubble triples) and an independent
 brute-force reconstruction on a 4 x 4 mesh.
 """
+import dataclasses
 import math
 import os
 
@@ -587,3 +588,56 @@ def test_invalid_parameters_rejected(oracle_mod):
         _oracle(oracle_mod, dict(bc_x=1), n=(1, 4), faces=(W.uniform_faces(1), W.uniform_faces(4)))
     with pytest.raises(ValueError):
         _oracle(oracle_mod, dict(), faces=(np.array([0, 1, 1, 2, 3.0]), W.uniform_faces(4)))
+
+
+# ---------------------------------------------------------------------------
+# Interface observables (droplet mass, phase-A centroid and velocity, the
+# highest and lowest crossing of the median level).
+# ---------------------------------------------------------------------------
+def test_observables_table1_mass(oracle_mod):
+    """The median-level cell count of the initial drops of Table 1 is the
+    printed M_ini (cell centres at integer coordinates, drop at (50, 50)).
+    Cells exactly on the level (r = R0, phi0 = 0.5) are not counted in phi0;
+    after Step 1 their phi = sum g~ may round either way, so they are the
+    only allowed difference."""
+    for r0, m_ini in _golden("table1_initial_mass.txt"):
+        c = W.drop_case(n=100, radius=r0, noise=0)
+        f = W.uniform_faces(100, x0=-0.5)
+        phi0 = W.table1_initial_phi(r0)
+        c = dataclasses.replace(c, x_faces=f, y_faces=f, phi0=phi0)
+        o = oracle_mod.Oracle.from_case(c)
+        obs = o.observables()
+        ties = int(np.count_nonzero(np.abs(phi0 - 0.5) < 1e-12))
+        assert m_ini <= obs[0] <= m_ini + ties, (r0, obs[0], m_ini, ties)
+        assert obs[1] == obs[0]  # unit cells
+        assert obs[0] == W.drop_mass_median(o.moments()["phi"])
+        assert abs(obs[2] - 50.0) < 1e-6 and abs(obs[3] - 50.0) < 1e-6
+
+
+def test_observables_linear_interface_crossing(oracle_mod):
+    """A profile linear in y through the median level at y0 in every column:
+    the highest and lowest crossings are y0 (linear interpolation is exact)."""
+    c = W.rt_case(8, 32)
+    yc = W.centres(c.y_faces)
+    y0 = 13.3
+    phi = np.clip(0.5 + 0.02 * (yc - y0), 0.0, 1.0)[:, None] * np.ones((1, 8))
+    c = dataclasses.replace(c, phi0=np.ascontiguousarray(phi))
+    obs = oracle_mod.Oracle.from_case(c).observables()
+    assert abs(obs[6] - y0) < 1e-12 and abs(obs[7] - y0) < 1e-12
+    # no crossing at all: NaN
+    c2 = dataclasses.replace(c, phi0=np.full((32, 8), 0.9))
+    obs2 = oracle_mod.Oracle.from_case(c2).observables()
+    assert np.isnan(obs2[6]) and np.isnan(obs2[7])
+    assert obs2[0] == 32 * 8
+
+
+def test_observables_uniform_phase_a_flow(oracle_mod):
+    """Phase A everywhere moving uniformly: the centroid is the domain centre
+    and the mean velocity is the imposed one."""
+    c = W.drop_case(n=12, radius=3.0, noise=0)
+    u0, v0 = 0.01, -0.02
+    c = dataclasses.replace(c, phi0=np.ones((12, 12)), ux0=np.full((12, 12), u0),
+                            uy0=np.full((12, 12), v0))
+    obs = oracle_mod.Oracle.from_case(c).observables()
+    assert abs(obs[2] - 6.0) < 1e-12 and abs(obs[3] - 6.0) < 1e-12
+    assert abs(obs[4] - u0) < 1e-15 and abs(obs[5] - v0) < 1e-15
