@@ -50,6 +50,8 @@ def kernel_src_sha():
 
 def workload(name: str):
     from paper_1802_02868_amd import workloads as W
+    if name in W.PAPER_CASES:
+        return W.PAPER_CASES[name]()
     if name == "rt256x1024":
         return W.rt_case(256)
     if name.startswith("rt"):
@@ -66,6 +68,8 @@ def workload(name: str):
 
 
 def describe(name: str) -> str:
+    if name.startswith("paper_"):
+        return "the paper's own parameter set"
     if name.startswith("rt"):
         return "Rayleigh-Taylor, periodic x, walls in y"
     if name.startswith("drop"):

@@ -140,6 +140,30 @@ def drop_case(n=64, radius=16.0, width=4.0, sigma=1e-3, rho_a=1.0, rho_b=0.1, nu
                 z.copy(), steps, dict(radius=radius, sigma=sigma, width=width))
 
 
+def tensor_drop_case(nx=32, ny=24, eps_x=1.5, eps_y=1.0, bc_x=1, bc_y=0, radius=None,
+                     width=4.0, sigma=1e-3, rho_a=1.0, rho_b=0.1, nu=0.1, mobility=0.1,
+                     cfl=0.4, gx=0.0, gy=0.0, steps=200) -> Case:
+    """A drop on a general tensor mesh: both axes tanh-stretched like the
+    layered-channel mesh (clustered at the ends and the middle), with walls
+    or periodic ends per axis (default: walls in x, periodic in y).  Unit
+    cells on average (half widths nx/2 and ny/2); the drop sits off-centre
+    so that it meets fine and coarse cells."""
+    xf = stretched_faces(nx, eps_x, nx / 2.0)
+    yf = stretched_faces(ny, eps_y, ny / 2.0)
+    xc, yc = centres(xf), centres(yf)
+    r0 = min(nx, ny) / 5.0 if radius is None else radius
+    X, Y = np.meshgrid(xc, yc)
+    r = np.sqrt((X - 0.15 * nx) ** 2 + (Y + 0.1 * ny) ** 2)
+    phi = tanh_profile(r0 - r, width)
+    beta, kappa = beta_kappa(sigma, width)
+    p = base_params(nx=nx, ny=ny, bc_x=bc_x, bc_y=bc_y, cfl=cfl, beta=beta, kappa=kappa,
+                    rho_a=rho_a, rho_b=rho_b, nu_a=nu, nu_b=nu, mobility=mobility, gx=gx,
+                    gy=gy, rho_ref=rho_b)
+    z = np.zeros_like(phi)
+    return Case("tensor%dx%d" % (nx, ny), p, xf, yf, np.ascontiguousarray(phi), z.copy(),
+                z.copy(), z.copy(), steps, dict(radius=r0, sigma=sigma, width=width))
+
+
 def poiseuille_case(nx=4, ny=128, eps=1.5, half=1.0, nu_a=0.01, nu_b=1.0, gx=1e-6,
                     width_cells=4.0, sigma=1e-4, mobility=1e-2, cfl=0.5, steps=1000,
                     stretched=True, recon=0) -> Case:
@@ -278,6 +302,88 @@ def table1_initial_phi(radius, n=100, width=4.0):
     X, Y = np.meshgrid(c, c)
     r = np.sqrt((X - 50.0) ** 2 + (Y - 50.0) ** 2)
     return tanh_profile(radius - r, width)
+
+
+def paper_drop_case(radius=25.0, cfl=0.4, mobility=0.1, steps=20000) -> Case:
+    """The stationary drop as Sec. 3.1 sets it up: 100 x 100 periodic cells,
+    rho_A = 1, rho_B = 0.2, tau_f = tau_g = 0.5, W = 4, sigma = 1e-3, CFL 0.4
+    (C_max = sqrt(6 RT)); radius 10-40, mobility and CFL varied there."""
+    c = drop_case(n=100, radius=radius, rho_a=1.0, rho_b=0.2, tau_f=0.5, mobility=mobility,
+                  cfl=cfl, c_max=0.0, noise=0.0, steps=steps)
+    c.name = "paper_drop100_r%g" % radius
+    return c
+
+
+def paper_channel_case(ratio=30.0, eps=None, mu_a=0.1, u_c=5e-5, steps=200000) -> Case:
+    """The layered channel of Sec. 3.2: 10 x 200 cells between walls at
+    y = -H, H (H = 100), fluid A above y = 0, mu_A / mu_B = ratio (3, 30, 100,
+    1000 there), rho_A = rho_B = 1, W = 4, CFL 0.5, centre velocity
+    u_c = G H^2 / (mu_A + mu_B) = 5e-5.  eps: the stretched mesh of the same
+    section (2.5 there), else uniform.  The paper gives only the ratio, so
+    mu_A = 0.1 is a reading."""
+    half, ny, nx = 100.0, 200, 10
+    yf = uniform_faces(ny, -half, 1.0) if eps is None else stretched_faces(ny, eps, half)
+    xf = uniform_faces(nx)
+    mu_b = mu_a / ratio
+    g = u_c * (mu_a + mu_b) / half ** 2
+    width = 4.0 * float(np.min(np.diff(yf)))
+    beta, kappa = beta_kappa(1e-4, width)
+    yc = centres(yf)
+    phi = np.ascontiguousarray(np.tile(tanh_profile(yc, width)[:, None], (1, nx)))
+    p = base_params(nx=nx, ny=ny, bc_x=0, bc_y=1, cfl=0.5, beta=beta, kappa=kappa,
+                    rho_a=1.0, rho_b=1.0, nu_a=mu_a, nu_b=mu_b, mobility=1e-2, gx=g,
+                    rho_ref=0.0)
+    z = np.zeros_like(phi)
+    name = "paper_channel10x200_ratio%g%s" % (ratio, "" if eps is None else "_eps%g" % eps)
+    return Case(name, p, xf, yf, phi, z.copy(), z.copy(), z.copy(), steps,
+                dict(half=half, gx=g, mu_a=mu_a, mu_b=mu_b, width=width))
+
+
+def paper_bubble_case(ratio=2, steps=20000) -> Case:
+    """The rising bubble as Sec. 3.3 sets it up: an L0 x 3 L0 periodic box,
+    L0 = 160, a light bubble (fluid A) of diameter D = 2 L0 / 5 at
+    (L0/2, L0/2), buoyancy -(rho - rho_B) G_y with G_y = 1e-5, sigma = 1e-3,
+    eta = 2.0, tau_f = tau_g = 0.5 (viscosity ratio 1), W = 4, CFL 0.354.
+    rho_B / rho_A = 2 or 5; the absolute densities are the reading that
+    reproduces the Eo, Mo, Re printed for the two runs."""
+    l0 = 160
+    rho_b, rho_a = {2: (1.0, 0.5), 5: (1.2, 0.24)}[int(ratio)]
+    xf, yf = uniform_faces(l0), uniform_faces(3 * l0)
+    xc, yc = centres(xf), centres(yf)
+    X, Y = np.meshgrid(xc, yc)
+    r = np.sqrt((X - l0 / 2.0) ** 2 + (Y - l0 / 2.0) ** 2)
+    phi = np.ascontiguousarray(tanh_profile(l0 / 5.0 - r, 4.0))
+    beta, kappa = beta_kappa(1e-3, 4.0)
+    tau_g = 0.5
+    p = base_params(nx=l0, ny=3 * l0, bc_x=0, bc_y=0, cfl=0.354, beta=beta, kappa=kappa,
+                    rho_a=rho_a, rho_b=rho_b, tau_f=0.5, tau_g=tau_g,
+                    mobility=RT_DEFAULT * tau_g * 2.0, gx=0.0, gy=-1e-5, rho_ref=rho_b)
+    z = np.zeros_like(phi)
+    return Case("paper_bubble160x480_ratio%d" % ratio, p, xf, yf, phi, z.copy(), z.copy(),
+                z.copy(), steps, dict(diameter=2 * l0 / 5.0, g=1e-5))
+
+
+def paper_rt_case(atwood=0.1, steps=20000) -> Case:
+    """Rayleigh-Taylor as Sec. 3.4 sets it up: d = L = 256 on [0, d] x
+    [-2d, 2d], walls top and bottom, periodic sides, interface
+    2d + 0.05 d cos(2 pi x / L), Re = 3000, sqrt(g L) = 0.04, W = 4,
+    sigma = 5e-5; At = 0.1 with CFL 0.35, or At = 0.5 with CFL 0.283."""
+    cfl = 0.35 if atwood < 0.3 else 0.283
+    c = rt_case(256, atwood=atwood, re=3000.0, amp_frac=0.05, cfl=cfl, steps=steps)
+    c.name = "paper_rt256x1024_at%g" % atwood
+    return c
+
+
+PAPER_CASES = {
+    "paper_drop100_r25": lambda: paper_drop_case(25.0),
+    "paper_drop100_r10": lambda: paper_drop_case(10.0),
+    "paper_channel10x200_ratio3": lambda: paper_channel_case(3.0),
+    "paper_channel10x200_ratio1000": lambda: paper_channel_case(1000.0),
+    "paper_channel10x200_ratio30_eps2.5": lambda: paper_channel_case(30.0, eps=2.5),
+    "paper_bubble160x480_ratio2": lambda: paper_bubble_case(2),
+    "paper_bubble160x480_ratio5": lambda: paper_bubble_case(5),
+    "paper_rt256x1024_at0.1": lambda: paper_rt_case(0.1),
+}
 
 
 def config(name: str) -> Case:

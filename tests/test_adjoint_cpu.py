@@ -34,7 +34,8 @@ def _cases():
     bub.params.update(phi_clamp=0, gx=2e-5)
     ragged = W.rt_case(7, 13)
     ragged.params.update(gx=1e-5)
-    return [(drop, 3, 2), (rt, 7, 3), (pz, 5, 5), (bub, 6, 4), (ragged, 4, 3)]
+    tensor = W.tensor_drop_case(18, 16, 1.5, 1.0, bc_x=1, bc_y=0, gx=1e-5, gy=-2e-5)
+    return [(drop, 3, 2), (rt, 7, 3), (pz, 5, 5), (bub, 6, 4), (ragged, 4, 3), (tensor, 5, 2)]
 
 
 CASES = _cases()

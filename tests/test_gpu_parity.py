@@ -57,6 +57,9 @@ CASES = {
     "drop48_upwind": (lambda: W.drop_case(n=48, radius=12.0, recon=1), 200),
     "rt_ragged_70x45": (lambda: W.rt_case(70, ny=45, amp_frac=0.05), 50),
     "single_row_periodic": (lambda: W.drop_case(n=1, radius=0.3, noise=1e-3), 5),
+    # general tensor meshes: both axes stretched, walls in x (in both axes)
+    "tensor40x30_walls_x": (lambda: W.tensor_drop_case(40, 30), 200),
+    "tensor46x30_walls_xy": (lambda: W.tensor_drop_case(46, 30, 2.5, 0.5, bc_y=1, gx=2e-5), 150),
 }
 
 
@@ -111,6 +114,15 @@ def test_observables_match_oracle(D, oracle_mod, name):
     for k in (6, 7):
         assert (np.isnan(g[k]) and np.isnan(r[k])) or g[k] == r[k], (k, g[k], r[k])
     assert mon[4] == 0
+
+
+@pytest.mark.parametrize("name", sorted(W.PAPER_CASES))
+def test_paper_parameter_sets_match_oracle(D, oracle_mod, name):
+    """The paper's own setups (Secs. 3.1-3.4 as printed there) on the fused
+    FP64 kernel: the oracle's populations bit for bit after 20 steps."""
+    case = W.PAPER_CASES[name]()
+    print("paper set:", name, flush=True)
+    _compare(D, oracle_mod, case, 20, D.KERNEL_FUSED, "fused")
 
 
 def test_checkpoint_resume_bitwise(D):

@@ -43,6 +43,11 @@ def test_workspace_query_validates_parameters():
     assert D.workspace_bytes(c.params, xf, c.y_faces, kernel=D.KERNEL_STAGED) == 0
 
 
+def _upwind(case):
+    case.params["recon"] = 1
+    return case
+
+
 CASES = {
     "drop": (lambda: W.drop_case(n=32, radius=8.0), 20),
     "rt_walls": (lambda: W.rt_case(16, ny=64, amp_frac=0.2), 20),
@@ -50,6 +55,10 @@ CASES = {
     "bubble_four_walls": (lambda: W.bubble_case(32, 48, eo=20.0, mo=1e-3), 20),
     "upwind": (lambda: W.drop_case(n=16, radius=5.0, recon=1), 10),
     "upwind_walls": (lambda: W.rt_case(16, ny=32, amp_frac=0.2, recon=1), 10),
+    # tensor meshes stretched on both axes: walls in x, in y, on both
+    "tensor_walls_x": (lambda: W.tensor_drop_case(), 20),
+    "tensor_walls_y": (lambda: W.tensor_drop_case(bc_x=0, bc_y=1, gy=-1e-5), 20),
+    "tensor_walls_xy_upwind": (lambda: _upwind(W.tensor_drop_case(bc_x=1, bc_y=1, gx=2e-5)), 10),
 }
 
 
@@ -73,6 +82,9 @@ FUSED_CASES = {
     "bubble_four_walls": (lambda: W.bubble_case(32, 48, eo=20.0, mo=1e-3), 10),
     "single_cell": (lambda: W.drop_case(n=1, radius=0.3, noise=1e-3), 3),
     "tile_plus_one": (lambda: W.drop_case(n=15, radius=4.0), 5),
+    "tensor_walls_x": (lambda: W.tensor_drop_case(), 10),
+    "tensor_walls_y": (lambda: W.tensor_drop_case(bc_x=0, bc_y=1, gy=-1e-5), 10),
+    "tensor_strong_stretch": (lambda: W.tensor_drop_case(30, 46, 2.5, 0.5, bc_y=1, gx=2e-5), 10),
 }
 
 
@@ -130,3 +142,14 @@ def test_fp32_state_kernel_logic_within_tolerance(oracle_mod):
         for k, f in ((0, "phi"), (2, "ux"), (3, "uy")):
             err = np.abs(mac[k] - m[f]).max() / np.abs(m[f]).max()
             assert err < 1e-4, (case.name, f, err)
+
+
+@pytest.mark.parametrize("name", sorted(W.PAPER_CASES))
+def test_paper_parameter_sets_kernel_logic(oracle_mod, name):
+    """The paper's own setups (Secs. 3.1-3.4 as printed there) through the
+    fused kernel's host build: the oracle's results bit for bit."""
+    case = W.PAPER_CASES[name]()
+    pops, _ = _emu.run(case, 2, kernel=2)
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(2)
+    assert np.array_equal(pops, o.pops())
