@@ -161,6 +161,14 @@ int dugks2p_monitors(dugks2p *h, double out[6]);
  * and minima.  Syncs the stream. */
 int dugks2p_observables(dugks2p *h, double out[8]);
 
+/* The pressure P of the Laplace test (Sec. 3.1) at the current time:
+ * P = p0 - kappa phi lap(phi) + kappa |grad phi|^2 / 2 + p with
+ * p0 = phi dpsi/dphi - psi, the derivatives by the App. B stencils; written
+ * to P (device, FP64, [ny][nx], caller-owned).  Its jump across a drop's
+ * interface is sigma / R for the Laplace law.  Enqueued on the handle's
+ * stream. */
+int dugks2p_laplace_pressure(dugks2p *h, double *P);
+
 /* The 18 populations (q = 0..8 f~, 9..17 g~) converted to FP64,
  * [18][ny][nx], into / from device memory. */
 int dugks2p_get_populations(dugks2p *h, double *dst);

@@ -103,6 +103,7 @@ class Oracle:
             raise ValueError(L.orc_last_error().decode())
         self._h = h
         self._phi_a, self._phi_b = float(params["phi_a"]), float(params["phi_b"])
+        self._beta, self._kappa = float(params["beta"]), float(params["kappa"])
 
     @classmethod
     def from_case(cls, case, **over):
@@ -184,6 +185,20 @@ class Oracle:
         out[6] = ys.max() if ys.size else np.nan
         out[7] = ys.min() if ys.size else np.nan
         return out
+
+    def laplace_pressure(self):
+        """The pressure P of the Laplace test (Sec. 3.1):
+        P = p0 - kappa phi lap(phi) + kappa |grad phi|^2 / 2 + p with
+        p0 = phi dpsi/dphi - psi and psi = beta (phi - phi_A)^2 (phi - phi_B)^2
+        (eq. freeenergyfunction), the derivatives by the App. B stencils."""
+        m = self.moments()
+        phi = m["phi"]
+        b, k, pa, pb = self._beta, self._kappa, self._phi_a, self._phi_b
+        psi = b * (phi - pa) ** 2 * (phi - pb) ** 2
+        dpsi = 2 * b * (phi - pa) * (phi - pb) * (2 * phi - pa - pb)
+        d1x, d2x = self.deriv(0, phi)
+        d1y, d2y = self.deriv(1, phi)
+        return phi * dpsi - psi - k * phi * (d2x + d2y) + 0.5 * k * (d1x ** 2 + d1y ** 2) + m["p"]
 
     def pops(self):
         out = np.empty((18, self.ny, self.nx))

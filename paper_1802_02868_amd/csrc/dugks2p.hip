@@ -239,6 +239,26 @@ __global__ __launch_bounds__(256) void k_obs_final(const double *part, long long
     for (int m = 0; m < NOBS; ++m) out[m] = sh[m][0];
 }
 
+// The Laplace-test pressure P = p0 - kappa phi lap(phi) + kappa |grad phi|^2 / 2
+// + p, p0 = phi dpsi/dphi - psi (Sec. 3.1), in the order the oracle writes
+// it, into a dense [ny][nx] field.
+struct FLaplaceP {
+  Consts K;
+  Work w;
+  double *P;
+  DFN void operator()(int i, int j) const {
+    const i64 c = (i64)j * K.ld + i;
+    const double ph = w.phi[c], b = K.beta, k = K.kappa, pa = K.phi_a, pb = K.phi_b;
+    const double a1 = ph - pa, b1 = ph - pb;
+    const double psi = b * (a1 * a1) * (b1 * b1);
+    const double dpsi = 2.0 * b * a1 * b1 * (2.0 * ph - pa - pb);
+    const double d1x = stx(K, K.ax[0].d1, w.phi, i, j), d2x = stx(K, K.ax[0].d2, w.phi, i, j);
+    const double d1y = sty(K, K.ax[1].d1, w.phi, i, j), d2y = sty(K, K.ax[1].d2, w.phi, i, j);
+    P[(i64)j * K.nx + i] = ph * dpsi - psi - k * ph * (d2x + d2y) +
+                           0.5 * k * (d1x * d1x + d1y * d1y) + w.p[c];
+  }
+};
+
 // State <-> FP64 [18][ny][nx], one thread per cell.
 template <class IO>
 __global__ __launch_bounds__(256) void k_pops_out(Consts K, IO st, double *dst) {
@@ -562,6 +582,17 @@ int dugks2p_monitors(dugks2p *h, double out[6]) {
   out[4] = v[4];
   out[5] = (double)h->nstep;
   if (v[4] > 0.0) return fail(DUGKS2P_ENONFINITE, "non-finite populations in the state");
+  return DUGKS2P_OK;
+}
+
+int dugks2p_laplace_pressure(dugks2p *h, double *P) {
+  if (!h || !P) return fail(DUGKS2P_EINVAL, "NULL argument");
+  const int rc = launch_macros(h);
+  if (rc) return rc;
+  GpuEx ex{h->stream, hipSuccess};
+  ex.grid(FLaplaceP{h->K, h->w, P}, h->K.nx, h->K.ny);
+  if (ex.err != hipSuccess)
+    return fail(DUGKS2P_EHIP, std::string("pressure launch: ") + hipGetErrorString(ex.err));
   return DUGKS2P_OK;
 }
 

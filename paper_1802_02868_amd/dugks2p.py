@@ -51,6 +51,8 @@ def _load():
     L.dugks2p_monitors.argtypes = [vp, P(d)]
     L.dugks2p_observables.restype = ctypes.c_int
     L.dugks2p_observables.argtypes = [vp, P(d)]
+    L.dugks2p_laplace_pressure.restype = ctypes.c_int
+    L.dugks2p_laplace_pressure.argtypes = [vp, vp]
     L.dugks2p_get_populations.restype = ctypes.c_int
     L.dugks2p_get_populations.argtypes = [vp, vp]
     L.dugks2p_set_populations.restype = ctypes.c_int
@@ -110,7 +112,8 @@ def _load():
 lib = _load()
 
 EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2p_moments",
-            "dugks2p_monitors", "dugks2p_observables", "dugks2p_get_populations",
+            "dugks2p_monitors", "dugks2p_observables", "dugks2p_laplace_pressure",
+            "dugks2p_get_populations",
             "dugks2p_set_populations",
             "dugks2p_state_bytes", "dugks2p_get_state", "dugks2p_set_state", "dugks2p_dt",
             "dugks2p_step_count", "dugks2p_kernel", "dugks2p_tile", "dugks2p_destroy",
@@ -253,6 +256,13 @@ class Simulation:
         out = (ctypes.c_double * 8)()
         _check(lib.dugks2p_observables(self._h, out))
         return np.array(out[:])
+
+    def laplace_pressure(self):
+        """The Laplace-test pressure field P [ny, nx] (include/dugks2p.h)."""
+        t = self.torch
+        out = t.empty((self.ny, self.nx), dtype=t.float64, device=self.device)
+        _check(lib.dugks2p_laplace_pressure(self._h, out.data_ptr()))
+        return out
 
     def populations(self):
         t = self.torch

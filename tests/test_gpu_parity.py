@@ -125,6 +125,30 @@ def test_paper_parameter_sets_match_oracle(D, oracle_mod, name):
     _compare(D, oracle_mod, case, 20, D.KERNEL_FUSED, "fused")
 
 
+def test_laplace_pressure_matches_oracle_and_law(D, oracle_mod):
+    """The Laplace-test pressure field on the GPU against the oracle's after
+    200 steps (same stencils and order of operations), then the Laplace law
+    itself on the GPU: after 6000 steps the pressure jump across the drop is
+    sigma / R within 5 % (Sec. 3.1)."""
+    import torch
+    case = W.drop_case(n=48, radius=10.0, sigma=1e-3, noise=0)
+    sim = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)
+    sim.step(200)
+    P = sim.laplace_pressure().cpu().numpy()
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(200)
+    R = o.laplace_pressure()
+    err = np.abs(P - R).max() / np.abs(R).max()
+    print("laplace pressure relmax %.3e bitwise %s" % (err, np.array_equal(P, R)), flush=True)
+    assert err <= 1e-12
+    sim.step(5800)
+    P = sim.laplace_pressure().cpu().numpy()
+    torch.cuda.synchronize()
+    dP = P[24, 24] - P[0, 0]
+    print("laplace law: dP R / sigma = %.4f" % (dP * 10.0 / 1e-3), flush=True)
+    assert abs(dP * 10.0 / 1e-3 - 1.0) < 0.05
+
+
 def test_checkpoint_resume_bitwise(D):
     case = W.rt_case(32, ny=64, amp_frac=0.2)
     a = D.Simulation.from_case(case, kernel=D.KERNEL_STAGED)

@@ -490,24 +490,13 @@ def test_free_energy_decreases_for_relaxing_drop(oracle_mod):
 # ---------------------------------------------------------------------------
 # Whole-method validation (Sec. 3.1, 3.2).
 # ---------------------------------------------------------------------------
-def _laplace_pressure(o, params, m):
-    phi = m["phi"]
-    b, k, pa, pb = params["beta"], params["kappa"], params["phi_a"], params["phi_b"]
-    psi = b * (phi - pa) ** 2 * (phi - pb) ** 2
-    dpsi = 2 * b * (phi - pa) * (phi - pb) * (2 * phi - pa - pb)
-    d1x, d2x = o.deriv(0, phi)
-    d1y, d2y = o.deriv(1, phi)
-    return phi * dpsi - psi - k * phi * (d2x + d2y) + 0.5 * k * (d1x ** 2 + d1y ** 2) + m["p"]
-
-
 @pytest.mark.slow
 @pytest.mark.parametrize("radius,sigma", [(10.0, 1e-3), (8.0, 5e-3)])
 def test_laplace_law(oracle_mod, radius, sigma):
     c = W.drop_case(n=48, radius=radius, sigma=sigma, noise=0)
     o = oracle_mod.Oracle.from_case(c)
     o.step(6000)
-    m = o.moments()
-    P = _laplace_pressure(o, c.params, m)
+    P = o.laplace_pressure()
     dP = P[24, 24] - P[0, 0]
     assert abs(dP * radius / sigma - 1.0) < 0.05
 
