@@ -149,6 +149,27 @@ def test_laplace_pressure_matches_oracle_and_law(D, oracle_mod):
     assert abs(dP * 10.0 / 1e-3 - 1.0) < 0.05
 
 
+@pytest.mark.parametrize("ratio,steps,tol", [(3.0, 200000, 2e-3), (30.0, 800000, 1e-3)])
+def test_paper_channel_reaches_two_layer_profile(D, ratio, steps, tol):
+    """The layered channel exactly as Sec. 3.2 sets it up (10 x 200 cells,
+    W = 4, centre velocity 5e-5) run to steady state on the GPU: away from
+    the diffuse interface (|y| > 2W) the velocity is the two-layer Poiseuille
+    profile of the same section within a relative L2 error of `tol`.  Fluid A
+    lies above y = 0 here, so the profile is taken with y -> -y."""
+    c = W.paper_channel_case(ratio, mu_a=1.0)
+    m = c.meta
+    sim = D.Simulation.from_case(c, kernel=D.KERNEL_FUSED)
+    sim.step(steps)
+    yc = W.centres(c.y_faces)
+    u = sim.moments()["ux"].cpu().numpy()
+    ua = W.poiseuille_profile(-yc, m["half"], m["gx"], m["mu_a"], m["mu_b"])
+    mask = np.abs(yc) > 2 * m["width"]
+    err = np.sqrt(np.sum((u[:, 0] - ua)[mask] ** 2) / np.sum(ua[mask] ** 2))
+    print("channel ratio %g: L2 rel err %.3e after %d steps" % (ratio, err, steps), flush=True)
+    assert err < tol
+    assert np.abs(u - u[:, :1]).max() <= 1e-12 * np.abs(ua).max()  # uniform along x
+
+
 def test_checkpoint_resume_bitwise(D):
     case = W.rt_case(32, ny=64, amp_frac=0.2)
     a = D.Simulation.from_case(case, kernel=D.KERNEL_STAGED)
