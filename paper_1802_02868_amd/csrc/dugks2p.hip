@@ -101,6 +101,11 @@ struct GpuEx {
     hipLaunchKernelGGL(k_adj_faces<TileSq>, dim3(nt), dim3(NTHR), 0, s, K, w, a, ntx, nt);
     note(hipGetLastError());
   }
+  void adj_cells(const Consts &K, const Work &w, const AdjWork &a, const double *st) {
+    const int ntx = tiles_x<TileSq>(K), nt = ntx * tiles_y<TileSq>(K);
+    hipLaunchKernelGGL(k_adj_cells<TileSq>, dim3(nt), dim3(NTHR), 0, s, K, w, a, st, ntx, nt);
+    note(hipGetLastError());
+  }
   void note(hipError_t e) {
     if (e != hipSuccess && err == hipSuccess) err = e;
   }

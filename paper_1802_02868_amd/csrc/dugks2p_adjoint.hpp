@@ -122,7 +122,6 @@ struct AdjWork {
   const double *lam;  // 18 planes: adjoint of the state after the step
   double *out;        // 18 planes: adjoint of the state before the step
   double *xs, *ys;    // face records: NFS planes of xplane / yplane
-  double *gxb, *gyb;  // per cell: adjoints of the population gradients (18 planes each)
   double *fb;         // NFB planes of per-cell field adjoints and parameter partials
   double *pacc;       // 3 planes: per-cell sums over steps of the kappa, gx, gy partials
 };
@@ -628,97 +627,203 @@ DFN CellFaces cell_faces(const Consts &K, int i, int j) {
   return f;
 }
 
-// Gather of the adjoints of a cell's population gradients from the bar
-// adjoints of its four faces (the cell's own bar+ adjoint is formed where it
-// is used, in FAdjCell).
-struct FAdjGather {
-  Consts K;
-  AdjWork a;
-  DFN void operator()(int i, int j) const {
-    const i64 c = (i64)j * K.ld + i, P = K.plane;
-    const CellFaces F = cell_faces(K, i, j);
-    const FaceSide sw = face_side<0>(K, F.iw, 1), se = face_side<0>(K, F.ie, 0);
-    const FaceSide ss = face_side<1>(K, F.js, 1), sn = face_side<1>(K, F.jn, 0);
-#pragma unroll
-    for (int q = 0; q < 18; ++q) {
-      double g[2] = {0.0, 0.0};
-      face_grad_back<0>(K, sw, q, a.xs[(FS_B + q) * K.xplane + F.fw], g);
-      face_grad_back<0>(K, se, q, a.xs[(FS_B + q) * K.xplane + F.fe], g);
-      face_grad_back<1>(K, ss, q, a.ys[(FS_B + q) * K.yplane + F.fs], g);
-      face_grad_back<1>(K, sn, q, a.ys[(FS_B + q) * K.yplane + F.fn], g);
-      a.gxb[q * P + c] = g[0];
-      a.gyb[q * P + c] = g[1];
-    }
-  }
+// Adjoint of the population gradients and of Step 2 (eqs. relations1 and
+// relations2), plus the face-field adjoints of each cell's faces: writes the
+// adjoint of tilde (before the macro part) and the cell-field adjoints.
+// One workgroup per tile, one thread per cell of the tile and its one-cell
+// ring.  For each velocity every thread gathers the adjoints of its cell's
+// f and g population gradients from the bar adjoints of the cell's four
+// faces into LDS (two buffers alternating by velocity, so one barrier per
+// velocity); a tile cell's bar+ adjoint is then the 4/3 bar+ part of tilde+,
+// its four faces' reconstruction, and the transposed gradient stencils over
+// its neighbours' gathered values.
+template <class S>
+struct AdjCellLds {
+  double g[2][2][2][S::WY][S::WX];  // [buffer][gradient axis][f, g][y][x]
 };
 
-// The cell's bar+ adjoint: the 4/3 bar+ of tilde+ (eq. relations2) and its
-// four faces' reconstruction.
-DFN double cell_ab(const Consts &K, const AdjWork &a, const CellFaces &F, const FaceSide fs[4],
-                   i64 c, int q) {
-  double ab = (4.0 / 3.0) * a.lam[q * K.plane + c];
-  ab += face_ab_back<0>(K, fs[0], q, a.xs[(FS_B + q) * K.xplane + F.fw]);
-  ab += face_ab_back<0>(K, fs[1], q, a.xs[(FS_B + q) * K.xplane + F.fe]);
-  ab += face_ab_back<1>(K, fs[2], q, a.ys[(FS_B + q) * K.yplane + F.fs]);
-  ab += face_ab_back<1>(K, fs[3], q, a.ys[(FS_B + q) * K.yplane + F.fn]);
-  return ab;
-}
-
-// Adjoint of the population gradients and of Step 2 at a cell (eqs.
-// relations1 and relations2), one direction at a time, plus the face-field
-// adjoints of the cell's faces; writes the adjoint of tilde (before the
-// macro part) and the cell-field adjoints.
-struct FAdjCell {
-  Consts K;
-  Work w;
-  AdjWork a;
+template <class S>
+struct AdjCellTile {
+  const Consts &K;
+  const Work &w;  // the step's tape
+  const AdjWork &a;
   const double *st;  // state before the step (FP64)
-  DFN void operator()(int i, int j) const {
-    const i64 c = (i64)j * K.ld + i, P = K.plane;
-    const TW tx = stencil_tw(K, 0, K.ax[0].pg, i, j), ty = stencil_tw(K, 1, K.ax[1].pg, i, j);
+  int x0, y0;
+  AdjCellLds<S> *L;
+  // one thread's registers across the phases
+  struct St {
+    int i, j, lx, ly;  // global cell (i < 0: outside a wall domain), window position
+    bool own;          // a cell of the tile
+    CellFaces F;
+    FaceSide fs[4];
+    double bb[2][4];  // face bar adjoints of the current f and g at W, E, S, N
+    double nb[2][4];  // the same for the next velocity (loaded ahead)
+    double lf, lg, sf;  // lam of the current f and g, and the current f~
+    int ox[3], oy[3];  // window offsets of the transpose stencils' cells
+    double wx[3], wy[3];
     Mac<double> m, mb;
-    cell_mac(K, w, c, m);
-    mac_zero(mb);
-    const double tf = w.tauf[c];
-    const double uu = m.ux * m.ux + m.uy * m.uy;
-    const double den = 1.0 / (2.0 * tf + K.dt);
-    const double fca = (2.0 * tf - K.h) * den, fcb = 3.0 * K.h * den, fcc = 3.0 * tf * K.h * den;
-    double fcab = 0.0, fcbb = 0.0, fccb = 0.0, uub = 0.0;
-    const CellFaces F = cell_faces(K, i, j);
-    const FaceSide fs[4] = {face_side<0>(K, F.iw, 1), face_side<0>(K, F.ie, 0),
-                            face_side<1>(K, F.js, 1), face_side<1>(K, F.jn, 0)};
-#pragma unroll 1
-    for (int i2 = 0; i2 < 9; ++i2) {
+    double tf, uu, den, fca, fcb, fcc, fcab, fcbb, fccb, uub;
+  };
+  DFN static int chk(int v, int lim) {
+#ifdef DUGKS2P_WINDOW_CHECK
+    if (v < 0 || v >= lim) {
+      printf("adjoint cell window check: %d outside [0, %d)\n", v, lim);
+#if !defined(__HIP_DEVICE_COMPILE__)
+      fflush(stdout);
+#endif
+      __builtin_trap();
+    }
+#else
+    (void)lim;
+#endif
+    return v;
+  }
+  DFN void setup(int tid, St &s) const {
+    s.lx = tid % S::WX;
+    s.ly = tid / S::WX;
+    const TileP0<S, AdjCellLds<S>> p{K, w, x0, y0, L};
+    s.i = p.gcol(x0 - 1 + s.lx, K.nx, K.ax[0].bc);
+    s.j = p.gcol(y0 - 1 + s.ly, K.ny, K.ax[1].bc);
+    s.own = s.lx >= 1 && s.lx <= S::TX && s.ly >= 1 && s.ly <= S::TY &&
+            x0 + s.lx - 1 < K.nx && y0 + s.ly - 1 < K.ny;
+    if (s.i < 0 || s.j < 0) {
+      s.i = -1;
+      s.own = false;
+      return;
+    }
+    s.F = cell_faces(K, s.i, s.j);
+    s.fs[0] = face_side<0>(K, s.F.iw, 1);
+    s.fs[1] = face_side<0>(K, s.F.ie, 0);
+    s.fs[2] = face_side<1>(K, s.F.js, 1);
+    s.fs[3] = face_side<1>(K, s.F.jn, 0);
+    load_bb(s.F, 0, s.bb);
+    if (!s.own) return;
+    const i64 c = (i64)s.j * K.ld + s.i;
+    // the transpose stencils' cells are lo(c), c, hi(c) along each axis: the
+    // window neighbours, or the cell itself where lo or hi is the cell
+    const TW tx = stencil_tw(K, 0, K.ax[0].pg, s.i, s.j), ty = stencil_tw(K, 1, K.ax[1].pg, s.i, s.j);
+    s.ox[0] = ax_lo(K.ax[0], s.i) == s.i ? 0 : -1;
+    s.ox[1] = 0;
+    s.ox[2] = ax_hi(K.ax[0], s.i) == s.i ? 0 : 1;
+    s.oy[0] = ax_lo(K.ax[1], s.j) == s.j ? 0 : -1;
+    s.oy[1] = 0;
+    s.oy[2] = ax_hi(K.ax[1], s.j) == s.j ? 0 : 1;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      s.wx[e] = tx.w[e];
+      s.wy[e] = ty.w[e];
+    }
+    cell_mac(K, w, c, s.m);
+    mac_zero(s.mb);
+    s.tf = w.tauf[c];
+    s.uu = s.m.ux * s.m.ux + s.m.uy * s.m.uy;
+    s.den = 1.0 / (2.0 * s.tf + K.dt);
+    s.fca = (2.0 * s.tf - K.h) * s.den;
+    s.fcb = 3.0 * K.h * s.den;
+    s.fcc = 3.0 * s.tf * K.h * s.den;
+    s.fcab = s.fcbb = s.fccb = s.uub = 0.0;
+  }
+  // the face bar adjoints of velocity i2's f and g at the cell's four faces
+  DFN void load_bb(const CellFaces &F, int i2, double bb[2][4]) const {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int q = 9 * k + i2;
+      bb[k][0] = a.xs[(FS_B + q) * K.xplane + F.fw];
+      bb[k][1] = a.xs[(FS_B + q) * K.xplane + F.fe];
+      bb[k][2] = a.ys[(FS_B + q) * K.yplane + F.fs];
+      bb[k][3] = a.ys[(FS_B + q) * K.yplane + F.fn];
+    }
+  }
+  // gradient adjoints of the f and g populations of velocity i2;
+  // the cell's own inputs of the cell phase are loaded here, ahead of the
+  // barrier
+  DFN void gather(int i2, St &s) const {
+    if (s.i < 0) return;
+    const int b = i2 & 1;
+    if (s.own) {
+      const i64 c = (i64)s.j * K.ld + s.i;
+      s.lf = a.lam[i2 * K.plane + c];
+      s.lg = a.lam[(9 + i2) * K.plane + c];
+      s.sf = st[i2 * K.plane + c];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int q = 9 * k + i2;
+      double g[2] = {0.0, 0.0};
+      face_grad_back<0>(K, s.fs[0], q, s.bb[k][0], g);
+      face_grad_back<0>(K, s.fs[1], q, s.bb[k][1], g);
+      face_grad_back<1>(K, s.fs[2], q, s.bb[k][2], g);
+      face_grad_back<1>(K, s.fs[3], q, s.bb[k][3], g);
+      L->g[b][0][k][s.ly][s.lx] = g[0];
+      L->g[b][1][k][s.ly][s.lx] = g[1];
+    }
+  }
+  // bar+ adjoint of population k (0: f, 1: g) of velocity i2: tilde+'s 4/3
+  // bar+, the four faces' reconstruction, the transposed gradient stencils
+  DFN double ob_of(int i2, int k, const St &s) const {
+    const int q = 9 * k + i2, b = i2 & 1;
+    double ab = (4.0 / 3.0) * (k == 0 ? s.lf : s.lg);
+    ab += face_ab_back<0>(K, s.fs[0], q, s.bb[k][0]);
+    ab += face_ab_back<0>(K, s.fs[1], q, s.bb[k][1]);
+    ab += face_ab_back<1>(K, s.fs[2], q, s.bb[k][2]);
+    ab += face_ab_back<1>(K, s.fs[3], q, s.bb[k][3]);
+    const double(*gx)[S::WX] = L->g[b][0][k];
+    const double(*gy)[S::WX] = L->g[b][1][k];
+    const double tx = s.wx[0] * gx[s.ly][chk(s.lx + s.ox[0], S::WX)] +
+                      s.wx[1] * gx[s.ly][s.lx] +
+                      s.wx[2] * gx[s.ly][chk(s.lx + s.ox[2], S::WX)];
+    const double ty = s.wy[0] * gy[chk(s.ly + s.oy[0], S::WY)][s.lx] +
+                      s.wy[1] * gy[s.ly][s.lx] +
+                      s.wy[2] * gy[chk(s.ly + s.oy[2], S::WY)][s.lx];
+    return ab + tx + ty;
+  }
+  // Step 2 adjoint of velocity i2 at a tile cell; every thread first issues
+  // the loads of the next velocity's face values
+  DFN void cell(int i2, St &s) const {
+    if (s.i < 0) return;
+    if (i2 < 8) load_bb(s.F, i2 + 1, s.nb);
+    if (s.own) {
+      const i64 c = (i64)s.j * K.ld + s.i, P = K.plane;
       const int qf = i2, qg = 9 + i2;
       double feq, geq, ff, fg;
-      point_eq1<double>(K, m, uu, i2, feq, geq, ff, fg);
-      const double obf = cell_ab(K, a, F, fs, c, qf) + tw_apply(tx, a.gxb + qf * P) +
-                         tw_apply(ty, a.gyb + qf * P);
-      const double obg = cell_ab(K, a, F, fs, c, qg) + tw_apply(tx, a.gxb + qg * P) +
-                         tw_apply(ty, a.gyb + qg * P);
-      // tilde+ = 4/3 bar+ - 1/3 tilde: the 4/3 part is in ab
-      a.out[qf * P + c] = fca * obf - (1.0 / 3.0) * a.lam[qf * P + c];
-      a.out[qg * P + c] = K.gca * obg - (1.0 / 3.0) * a.lam[qg * P + c];
-      fcab += st[qf * P + c] * obf;
-      fcbb += feq * obf;
-      fccb += ff * obf;
-      point_eq1_vjp(K, m, uu, i2, fcb * obf, K.gcb * obg, fcc * obf, K.gcc * obg, mb, uub);
+      point_eq1<double>(K, s.m, s.uu, i2, feq, geq, ff, fg);
+      const double obf = ob_of(i2, 0, s);
+      const double obg = ob_of(i2, 1, s);
+      a.out[qf * P + c] = s.fca * obf - (1.0 / 3.0) * s.lf;
+      a.out[qg * P + c] = K.gca * obg - (1.0 / 3.0) * s.lg;
+      s.fcab += s.sf * obf;
+      s.fcbb += feq * obf;
+      s.fccb += ff * obf;
+      point_eq1_vjp(K, s.m, s.uu, i2, s.fcb * obf, K.gcb * obg, s.fcc * obf, K.gcc * obg, s.mb,
+                    s.uub);
     }
-    mb.ux += 2.0 * m.ux * uub;
-    mb.uy += 2.0 * m.uy * uub;
-    // fca = (2 tf - h) den, fcb = 3 h den, fcc = 3 tf h den, den = 1/(2 tf + dt)
-    const double denb = (2.0 * tf - K.h) * fcab + 3.0 * K.h * fcbb + 3.0 * tf * K.h * fccb;
-    const double tfb = 2.0 * den * fcab + 3.0 * K.h * den * fccb - 2.0 * den * den * denb;
+    if (i2 < 8) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s.bb[k][e] = s.nb[k][e];
+    }
+  }
+  // the cell-field adjoints of a tile cell, after the last velocity
+  DFN void finish(St &s) const {
+    if (!s.own) return;
+    const i64 c = (i64)s.j * K.ld + s.i, P = K.plane;
+    Mac<double> &mb = s.mb;
+    const Mac<double> &m = s.m;
+    const double tf = s.tf, den = s.den;
+    mb.ux += 2.0 * m.ux * s.uub;
+    mb.uy += 2.0 * m.uy * s.uub;
+    const double denb = (2.0 * tf - K.h) * s.fcab + 3.0 * K.h * s.fcbb + 3.0 * tf * K.h * s.fccb;
+    const double tfb = 2.0 * den * s.fcab + 3.0 * K.h * den * s.fccb - 2.0 * den * den * denb;
     double dtp, dtr;
     tauf_grad(K, m.phi, m.rho, dtp, dtr);
-    // face-field adjoints of the four faces
     double fv[12];
 #pragma unroll
     for (int e = 0; e < 12; ++e) fv[e] = 0.0;
-    face_field_back<0>(fs[0], 1, a.xs + F.fw, K.xplane, fv);
-    face_field_back<0>(fs[1], 0, a.xs + F.fe, K.xplane, fv);
-    face_field_back<1>(fs[2], 1, a.ys + F.fs, K.yplane, fv);
-    face_field_back<1>(fs[3], 0, a.ys + F.fn, K.yplane, fv);
+    face_field_back<0>(s.fs[0], 1, a.xs + s.F.fw, K.xplane, fv);
+    face_field_back<0>(s.fs[1], 0, a.xs + s.F.fe, K.xplane, fv);
+    face_field_back<1>(s.fs[2], 1, a.ys + s.F.fs, K.yplane, fv);
+    face_field_back<1>(s.fs[3], 0, a.ys + s.F.fn, K.yplane, fv);
     double *fb = a.fb;
     fb[FB_MU * P + c] = fv[0] + mb.mu;
     fb[FB_D * P + c] = fv[1] + mb.D;
@@ -739,6 +844,25 @@ struct FAdjCell {
     fb[FB_FY * P + c] = mb.Fy;
   }
 };
+
+#if defined(__HIPCC__)
+template <class S>
+__global__ __launch_bounds__(NTHR) void k_adj_cells(Consts K, Work w, AdjWork a,
+                                                    const double *st, int ntx, int ntiles) {
+  __shared__ AdjCellLds<S> L;
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const AdjCellTile<S> ct{K, w, a, st, (tile % ntx) * S::TX, (tile / ntx) * S::TY, &L};
+  typename AdjCellTile<S>::St s;
+  ct.setup(threadIdx.x, s);
+#pragma unroll 1
+  for (int i2 = 0; i2 < 9; ++i2) {
+    ct.gather(i2, s);
+    __syncthreads();
+    ct.cell(i2, s);
+  }
+  ct.finish(s);
+}
+#endif
 
 // Adjoint of the cell macros (eqs. u, P; F; D): the p adjoint is completed
 // by the transpose of its gradient stencil.  init = 1: Step 1 form (u, p
@@ -881,8 +1005,7 @@ template <class Ex>
 void seq_adjoint_step(Ex &ex, const Consts &K, const Work &w, const AdjWork &a,
                       const double *st) {
   ex.adj_faces(K, w, a);
-  ex.grid(FAdjGather{K, a}, K.nx, K.ny);
-  ex.grid(FAdjCell{K, w, a, st}, K.nx, K.ny);
+  ex.adj_cells(K, w, a, st);
   ex.grid(FAdjMacro{K, w, a, 0}, K.nx, K.ny);
   ex.grid(FAdjMu{K, w, a}, K.nx, K.ny);
   ex.grid(FAdjPhi{K, a, nullptr}, K.nx, K.ny);
@@ -920,7 +1043,7 @@ struct AdjLayout {
   size_t field_bytes;  // one cell plane, padded
   size_t slot_bytes;   // one tape slot: 16 fields + bar+
   size_t state_bytes;  // 18 planes
-  size_t states, tape, dummy, facex, facey, fwork, lam[2], xs, ys, gxb, gyb, fb, pacc, red;
+  size_t states, tape, dummy, facex, facey, fwork, lam[2], xs, ys, fb, pacc, red;
   size_t total;
   int mseg;
 };
@@ -958,10 +1081,6 @@ inline AdjLayout make_adj_layout(const Consts &K, const AxisHost &ax, const Axis
   off += align256(NFS * sizeof(double) * (size_t)K.xplane);
   L.ys = off;
   off += align256(NFS * sizeof(double) * (size_t)K.yplane);
-  L.gxb = off;
-  off += L.state_bytes;
-  L.gyb = off;
-  off += L.state_bytes;
   L.fb = off;
   off += align256(NFB * sizeof(double) * P);
   L.pacc = off;
@@ -1008,8 +1127,6 @@ struct AdjBufs {
     a.out = lam(1 - in);
     a.xs = (double *)(base + L.xs);
     a.ys = (double *)(base + L.ys);
-    a.gxb = (double *)(base + L.gxb);
-    a.gyb = (double *)(base + L.gyb);
     a.fb = (double *)(base + L.fb);
     a.pacc = (double *)(base + L.pacc);
     return a;

@@ -56,6 +56,27 @@ struct CpuEx {
       for (int t = 0; t < NTHR; ++t) ft.faces(t);
     }
   }
+  // the adjoint's tiled gather and cell stage: phase by phase, one velocity
+  // at a time; each buffer is poisoned again before the gather that fills it
+  void adj_cells(const Consts &K, const Work &w, const AdjWork &a, const double *st) {
+    using S = TileSq;
+    using T = AdjCellTile<S>;
+    const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
+    std::vector<AdjCellLds<S>> L(1);
+    std::vector<typename T::St> s(NTHR);
+    for (int b = 0; b < nt; ++b) {
+      const int tile = xcd_tile(b, nt);
+      memset((void *)s.data(), 0xff, s.size() * sizeof(s[0]));
+      const T ct{K, w, a, st, (tile % ntx) * S::TX, (tile / ntx) * S::TY, L.data()};
+      for (int t = 0; t < NTHR; ++t) ct.setup(t, s[t]);
+      for (int i2 = 0; i2 < 9; ++i2) {
+        memset((void *)L[0].g[i2 & 1], 0xff, sizeof(L[0].g[0]));
+        for (int t = 0; t < NTHR; ++t) ct.gather(i2, s[t]);
+        for (int t = 0; t < NTHR; ++t) ct.cell(i2, s[t]);
+      }
+      for (int t = 0; t < NTHR; ++t) ct.finish(s[t]);
+    }
+  }
   template <class IO, class R, bool U, class S>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
