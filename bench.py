@@ -225,8 +225,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the step has no multi-GPU path; "
-              "see the sharding paragraph of the design notes); use --gpus 1", file=sys.stderr)
+        print("bench.py: the step runs on one GPU only (there is no multi-GPU path; the "
+              "design notes describe how it would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -40,7 +40,7 @@ enum {
   DUGKS2P_ENOMEM = -2,      /* device allocation failed or workspace too small */
   DUGKS2P_EHIP = -3,        /* a HIP runtime call failed                     */
   DUGKS2P_ENONFINITE = -4,  /* a population became NaN or infinite            */
-  DUGKS2P_EUNSUPPORTED = -5 /* valid request this build cannot perform        */
+  DUGKS2P_EUNSUPPORTED = -5 /* valid request the library cannot perform       */
 };
 
 enum { DUGKS2P_BC_PERIODIC = 0, DUGKS2P_BC_WALL = 1 };
