@@ -199,7 +199,10 @@ def poiseuille_profile(y, half, gx, mu_a, mu_b):
 def rt_case(nx=256, ny=None, atwood=0.5, re=3000.0, pe=1000.0, sigma=5e-5, width=4.0,
             amp_frac=0.1, cfl=0.283, steps=20000, recon=0) -> Case:
     """Rayleigh-Taylor instability: heavy A (phi_A = 1) over light B, periodic
-    in x, walls in y, domain nx x 4nx with the interface at mid height."""
+    in x, walls in y, domain nx x 4nx with the interface at mid height.
+    U = sqrt(g nx) = 0.04, nu = U nx / Re and mobility U nx / Pe (Sec. 3.4
+    takes Re, Pe, sigma and W from a lattice Boltzmann study that it cites;
+    the Peclet number is read as U L / lambda)."""
     ny = 4 * nx if ny is None else ny
     xf, yf = uniform_faces(nx), uniform_faces(ny)
     xc, yc = centres(xf), centres(yf)
@@ -209,7 +212,7 @@ def rt_case(nx=256, ny=None, atwood=0.5, re=3000.0, pe=1000.0, sigma=5e-5, width
     g = u_ref ** 2 / nx
     nu = u_ref * nx / re
     beta, kappa = beta_kappa(sigma, width)
-    lam = u_ref * nx / (pe * beta)
+    lam = u_ref * nx / pe
     X, Y = np.meshgrid(xc, yc)
     yi = ny / 2.0 + amp_frac * nx * np.cos(2 * np.pi * X / nx)
     phi = np.ascontiguousarray(tanh_profile(Y - yi, width))

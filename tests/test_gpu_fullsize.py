@@ -3,7 +3,8 @@ in the launch configuration
 bench.py times (fused kernel, square tiles; batch with its tuned tile; the
 adjoint with checkpoints every 50 steps), against the oracle: bit for bit
 for FP64, within 1e-4 for the FP32 state, and the adjoint against the
-oracle's central differences on the 512 x 2048 grid."""
+oracle's central differences on the 512 x 2048 grid; a 2000-step rollout's
+gradient on that grid against central differences of the forward step."""
 import dataclasses
 
 import numpy as np
@@ -130,3 +131,58 @@ def test_adjoint_rt512x2048_against_oracle_fd(D, oracle_mod):
         np.abs(gp - 1.0).max(), float(k2.grad), g2.grad.cpu().numpy()), flush=True)
     assert np.abs(gp - 1.0).max() <= 1e-10
     assert abs(float(k2.grad)) * k0 <= 1e-10 and np.abs(g2.grad.cpu().numpy()).max() * abs(g0) <= 1e-10
+
+
+def test_rollout_2000_steps_rt512x2048(D):
+    """A 2000-step differentiable rollout on the 512 x 2048 grid (64 interface
+    modes, checkpoints every 50 steps, recomputation inside each segment):
+    the rollout and its reverse sweep fit in device memory, and dJ of
+    J = sum (phi(T) - phi_ref)^2, phi_ref the initial interface of a second
+    seed, agrees along two seeded unit directions in scaled coordinates with
+    the central difference (step 1e-4) of two more rollouts of the same
+    forward step (which equals the oracle bit for bit, tests above)."""
+    import torch
+    from paper_1802_02868_amd.rollout import rollout
+    case = W.rt_case(512)
+    steps, every = 2000, 50
+    a0 = W.rt_mode_amplitudes(512, 64, seed=2024)
+    sig = 1e-3 * 512
+    k0, g0 = case.params["kappa"], case.params["gy"]
+    R = torch.from_numpy(W.rt_interface_phi0(W.rt_mode_amplitudes(512, 64, seed=77), case)).cuda()
+    print("rollout", case.name, steps, every, flush=True)
+    torch.cuda.reset_peak_memory_stats()
+    a = torch.tensor(a0, dtype=torch.float64, device="cuda", requires_grad=True)
+    kap = torch.tensor(k0, dtype=torch.float64, device="cuda", requires_grad=True)
+    g = torch.tensor([0.0, g0], dtype=torch.float64, device="cuda", requires_grad=True)
+    pops = rollout(W.rt_interface_phi0(a, case), kap, g, case, steps, every)
+    J = ((pops[9:].sum(0) - R) ** 2).sum()
+    J.backward()
+    peak = torch.cuda.max_memory_allocated()
+    print("  J %.6e, peak device memory %.1f GB" % (float(J.detach()), peak / 1e9), flush=True)
+    assert np.isfinite(float(J.detach()))
+    assert peak < torch.cuda.get_device_properties(0).total_memory
+    grad_s = np.concatenate([a.grad.cpu().numpy() * sig, [float(kap.grad) * k0],
+                             g.grad.cpu().numpy() * abs(g0)])
+    assert np.isfinite(grad_s).all()
+    theta = np.concatenate([a0 / sig, [1.0], [0.0, g0 / abs(g0)]])
+
+    def phi_T(th):
+        c = dataclasses.replace(case, phi0=W.rt_interface_phi0(th[:64] * sig, case),
+                                params=dict(case.params, kappa=th[64] * k0, gx=th[65] * abs(g0),
+                                            gy=th[66] * abs(g0)))
+        s = D.Simulation.from_case(c, precision=D.FP64)
+        s.step(steps)
+        out = s.populations()[9:].sum(0)
+        s.close()
+        return out
+
+    rng = np.random.default_rng(31)
+    eps = 1e-4
+    for _ in range(2):
+        d = rng.standard_normal(theta.size)
+        d /= np.linalg.norm(d)
+        pp, pm = phi_T(theta + eps * d), phi_T(theta - eps * d)
+        fd = float(((pp - pm) * (pp + pm - 2.0 * R)).sum()) / (2 * eps)
+        ad = float(grad_s @ d)
+        print("  direction: ad %.10e fd %.10e" % (ad, fd), flush=True)
+        assert abs(ad - fd) <= 1e-6 * abs(fd)
