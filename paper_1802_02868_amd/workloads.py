@@ -200,9 +200,10 @@ def rt_case(nx=256, ny=None, atwood=0.5, re=3000.0, pe=1000.0, sigma=5e-5, width
             amp_frac=0.1, cfl=0.283, steps=20000, recon=0) -> Case:
     """Rayleigh-Taylor instability: heavy A (phi_A = 1) over light B, periodic
     in x, walls in y, domain nx x 4nx with the interface at mid height.
-    U = sqrt(g nx) = 0.04, nu = U nx / Re and mobility U nx / Pe (Sec. 3.4
-    takes Re, Pe, sigma and W from a lattice Boltzmann study that it cites;
-    the Peclet number is read as U L / lambda)."""
+    U = sqrt(g nx) = 0.04; one dynamic viscosity mu = rho_A U nx / Re for
+    both fluids (Sec. 3.4 defines Re with a single mu); mobility U nx / Pe
+    (the section takes Re, Pe, sigma and W from a lattice Boltzmann study
+    that it cites; the Peclet number is read as U L / lambda)."""
     ny = 4 * nx if ny is None else ny
     xf, yf = uniform_faces(nx), uniform_faces(ny)
     xc, yc = centres(xf), centres(yf)
@@ -210,18 +211,18 @@ def rt_case(nx=256, ny=None, atwood=0.5, re=3000.0, pe=1000.0, sigma=5e-5, width
     rho_a = rho_b * (1 + atwood) / (1 - atwood)
     u_ref = 0.04
     g = u_ref ** 2 / nx
-    nu = u_ref * nx / re
+    mu = rho_a * u_ref * nx / re
     beta, kappa = beta_kappa(sigma, width)
     lam = u_ref * nx / pe
     X, Y = np.meshgrid(xc, yc)
     yi = ny / 2.0 + amp_frac * nx * np.cos(2 * np.pi * X / nx)
     phi = np.ascontiguousarray(tanh_profile(Y - yi, width))
     p = base_params(nx=nx, ny=ny, bc_x=0, bc_y=1, cfl=cfl, beta=beta, kappa=kappa,
-                    rho_a=rho_a, rho_b=rho_b, nu_a=nu, nu_b=nu, mobility=lam,
+                    rho_a=rho_a, rho_b=rho_b, nu_a=mu / rho_a, nu_b=mu / rho_b, mobility=lam,
                     gx=0.0, gy=-g, rho_ref=rho_b, recon=recon)
     z = np.zeros_like(phi)
     return Case("rt%dx%d" % (nx, ny), p, xf, yf, phi, z.copy(), z.copy(), z.copy(), steps,
-                dict(g=g, nu=nu, lam=lam, width=width))
+                dict(g=g, mu=mu, lam=lam, width=width))
 
 
 def bubble_case(nx, ny, eo, mo, rho_l=1.0, rho_g=0.1, visc_ratio=100.0, width=4.0,
