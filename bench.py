@@ -203,6 +203,8 @@ def main():
     ap.add_argument("--workload", default="rt256x1024")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
     ap.add_argument("--kernel", choices=("auto", "staged", "fused"), default="auto")
+    ap.add_argument("--recon", choices=("central", "upwind"), default="central",
+                    help="face reconstruction of Step 3 (central: the paper's)")
     ap.add_argument("--tile", choices=("auto", "square", "wide", "tall"), default="square",
                     help="tile shape of the headline run (auto: timed at creation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -238,6 +240,7 @@ def main():
     kern = {"auto": D.KERNEL_AUTO, "staged": D.KERNEL_STAGED, "fused": D.KERNEL_FUSED}[args.kernel]
     case.params["tile"] = {"auto": D.TILE_AUTO, "square": D.TILE_SQUARE, "wide": D.TILE_WIDE,
                            "tall": D.TILE_TALL}[args.tile]
+    case.params["recon"] = {"central": D.RECON_CENTRAL, "upwind": D.RECON_UPWIND}[args.recon]
     sim = D.Simulation.from_case(case, precision=prec, kernel=kern)
     stream = sim.stream
     cells = case.nx * case.ny
@@ -311,7 +314,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s %s (%dx%d cells, %s)" % (
             case.name, args.precision, case.nx, case.ny, describe(args.workload)), "cells": cells,
-            "kernel": args.kernel, "tile": ["auto", "14x14", "30x6", "6x30"][sim.tile], "dt": sim.dt},
+            "kernel": args.kernel, "recon": args.recon,
+            "tile": ["auto", "14x14", "30x6", "6x30", "12x12 two-ring"][sim.tile], "dt": sim.dt},
         "roofline": roof,
         "roofline_alu": roof_alu,
         "wall_s": round(wall, 3),
@@ -322,7 +326,7 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_vs_plain(args.batched_steps, D.FP32_STATE)
-    if not args.no_adjoint:
+    if not args.no_adjoint and args.recon == "central":  # the adjoint is of CENTRAL steps
         out["adjoint"] = adjoint_cost(case, args.adjoint_steps, 50)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)

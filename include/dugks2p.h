@@ -54,7 +54,10 @@ enum {
   DUGKS2P_TILE_AUTO = 0,
   DUGKS2P_TILE_SQUARE = 1, /* 14 x 14 */
   DUGKS2P_TILE_WIDE = 2,   /* 30 x 6  */
-  DUGKS2P_TILE_TALL = 3    /* 6 x 30  */
+  DUGKS2P_TILE_TALL = 3,   /* 6 x 30  */
+  DUGKS2P_TILE_UPWIND = 4  /* 12 x 12 with a two-cell bar+ ring: set by the
+                              library for UPWIND reconstruction, whatever
+                              tile was asked for */
 };
 
 /*
@@ -185,8 +188,9 @@ int dugks2p_set_state(dugks2p *h, const void *src);
 double dugks2p_dt(const dugks2p *h);
 int64_t dugks2p_step_count(const dugks2p *h);
 int dugks2p_kernel(const dugks2p *h);
-/* DUGKS2P_TILE_* shape the handle's fused kernel uses (AUTO resolved; the
- * staged form reports DUGKS2P_TILE_SQUARE). */
+/* DUGKS2P_TILE_* shape the handle's fused kernel uses (AUTO resolved;
+ * DUGKS2P_TILE_UPWIND for UPWIND reconstruction; the staged form reports
+ * DUGKS2P_TILE_SQUARE). */
 int dugks2p_tile(const dugks2p *h);
 
 /* Measurement aid.  While enabled, each step's tile kernel (the fused

@@ -6,6 +6,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -308,13 +309,9 @@ struct dugks2p {
 
 namespace {
 
-// The fused tile kernel implements CENTRAL reconstruction (its bar+ ring is
-// one cell wide); UPWIND runs on the staged kernels.
-bool use_staged(const dugks2p_params *P) {
-  if (P->kernel == DUGKS2P_KERNEL_STAGED) return true;
-  if (P->kernel == DUGKS2P_KERNEL_AUTO) return P->recon != DUGKS2P_RECON_CENTRAL;
-  return false;
-}
+// Both reconstructions run on the fused tile kernel (UPWIND with the
+// two-ring tiles) unless the staged kernels are asked for.
+bool use_staged(const dugks2p_params *P) { return P->kernel == DUGKS2P_KERNEL_STAGED; }
 
 struct Prepared {
   AxisHost ax, ay;
@@ -329,13 +326,16 @@ std::string prepare(const dugks2p_params *P, Prepared &pr) {
   build_axis(pr.ay, P->ny, P->bc_y, P->y_faces);
   pr.K = make_consts(P, pr.ax, pr.ay);
   if (!(pr.K.dt > 0.0) || !isfinite(pr.K.dt)) return "time step is not positive";
-  if (P->kernel == DUGKS2P_KERNEL_FUSED && P->recon != DUGKS2P_RECON_CENTRAL)
-    return "the fused kernel implements CENTRAL reconstruction only";
   if (P->precision == DUGKS2P_FP32_STATE && use_staged(P))
-    return "the FP32-state form runs on the fused kernel (CENTRAL reconstruction)";
+    return "the FP32-state form runs on the fused kernel";
   pr.L = make_layout(pr.K, pr.ax, pr.ay, P->precision, use_staged(P));
   return std::string();
 }
+
+// Non-unit lattice speeds instantiate square tiles only, plus the two-ring
+// tiles of UPWIND reconstruction.
+template <class S>
+using SqOrUpw = typename std::conditional<S::RG == 2, TileUpw, TileSq>::type;
 
 // Enqueue one time step from state[cur] into state[1 - cur] with tile shape
 // `shape` (fused form), without committing it.
@@ -351,8 +351,8 @@ int enqueue_step(dugks2p *h, int shape) {
       if (h->K.unit)
         seq_fused_step<GpuEx, IoF64, double, true, S>(ex, h->K, h->w, src, dst, h->sums_ok);
       else
-        seq_fused_step<GpuEx, IoF64, double, false, TileSq>(ex, h->K, h->w, src, dst,
-                                                            h->sums_ok);
+        seq_fused_step<GpuEx, IoF64, double, false, SqOrUpw<S>>(ex, h->K, h->w, src, dst,
+                                                                h->sums_ok);
     });
   } else {
     const IoE32 src = io_e32(h->state[h->cur], h->K, h->L);
@@ -362,8 +362,8 @@ int enqueue_step(dugks2p *h, int shape) {
       if (h->K.unit)
         seq_fused_step<GpuEx, IoE32, double, true, S>(ex, h->K, h->w, src, dst, h->sums_ok);
       else
-        seq_fused_step<GpuEx, IoE32, double, false, TileSq>(ex, h->K, h->w, src, dst,
-                                                            h->sums_ok);
+        seq_fused_step<GpuEx, IoE32, double, false, SqOrUpw<S>>(ex, h->K, h->w, src, dst,
+                                                                h->sums_ok);
     });
   }
   if (ex.err != hipSuccess)
@@ -390,8 +390,9 @@ int launch_step(dugks2p *h) {
 // real step rewrites) and keep the fastest.  Results do not depend on the
 // shape, only the speed does.
 int tune_tile(dugks2p *h) {
-  if (h->kernel != DUGKS2P_KERNEL_FUSED || !h->K.unit) {
-    h->tile = DUGKS2P_TILE_SQUARE;
+  if (h->kernel != DUGKS2P_KERNEL_FUSED || !h->K.unit || h->K.recon != 0) {
+    h->tile = h->kernel == DUGKS2P_KERNEL_FUSED && h->K.recon != 0 ? DUGKS2P_TILE_UPWIND
+                                                                     : DUGKS2P_TILE_SQUARE;
     return DUGKS2P_OK;
   }
   enum { WARM = 1, REPS = 3 };
@@ -464,9 +465,12 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
   h->stream = (hipStream_t)hip_stream;
   h->precision = P->precision;
   h->kernel = use_staged(P) ? DUGKS2P_KERNEL_STAGED : DUGKS2P_KERNEL_FUSED;
-  h->tile = (h->kernel == DUGKS2P_KERNEL_FUSED && pr.K.unit && P->tile != DUGKS2P_TILE_AUTO)
-                ? P->tile
-                : DUGKS2P_TILE_SQUARE;
+  if (h->kernel == DUGKS2P_KERNEL_FUSED && P->recon != DUGKS2P_RECON_CENTRAL)
+    h->tile = DUGKS2P_TILE_UPWIND;
+  else
+    h->tile = (h->kernel == DUGKS2P_KERNEL_FUSED && pr.K.unit && P->tile != DUGKS2P_TILE_AUTO)
+                  ? P->tile
+                  : DUGKS2P_TILE_SQUARE;
   h->cur = 0;
   h->nstep = 0;
   h->sums_ok = false;

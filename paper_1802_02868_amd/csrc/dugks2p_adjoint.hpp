@@ -463,6 +463,7 @@ struct AdjLds {
 
 template <class S>
 struct AdjFaceTile {
+  static_assert(S::RG == 1, "the face stage reads bar+ on a one-cell ring");
   const Consts &K;
   const Work &w;  // the step's tape
   const AdjWork &a;
@@ -644,6 +645,7 @@ struct AdjCellLds {
 
 template <class S>
 struct AdjCellTile {
+  static_assert(S::RG == 1, "one thread per cell of the tile and a one-cell ring");
   const Consts &K;
   const Work &w;  // the step's tape
   const AdjWork &a;

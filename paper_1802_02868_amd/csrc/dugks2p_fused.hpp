@@ -2,9 +2,10 @@
 //   1. FPhiSums: phi = sum g~ and the f~ sums (one thread per cell);
 //   2. FMacF:    mu, D, F, u, p (one thread per cell; mu of the four
 //                neighbours recomputed from phi);
-//   3. tile kernel: for a 14 x 14 tile, Step 2 (bar+) on the tile and a
-//                one-cell ring into LDS, Steps 3-4 at every face of the tile
-//                (each face once), flux exchange through LDS, Steps 5-6.
+//   3. tile kernel: for a tile (14 x 14 by default), Step 2 (bar+) on the
+//                tile and a one-cell ring (two cells for UPWIND) into LDS,
+//                Steps 3-4 at every face of the tile (each face once), flux
+//                exchange through LDS, Steps 5-6.
 // The populations are read once per step from HBM (ring cells from L2) and
 // written once.  Arithmetic is the same code as the staged stages, so FP64
 // results are bitwise identical to them.
@@ -20,13 +21,14 @@ namespace dg {
 
 enum { NTHR = 256 };  // threads of a tile workgroup
 
-// Tile shape: TX x TY cells, a one-cell ring for bar+ (the WX x WY window,
-// one thread per window cell) and a two-cell ring for the cell scalars (the
-// SX x SY window).  SM, FM: lengths of the per-axis weight and face tables.
-template <int TX_, int TY_>
+// Tile shape: TX x TY cells, an RG-cell ring for bar+ (the WX x WY window,
+// one thread per window cell) and an (RG + 1)-cell ring for the cell scalars
+// (the SX x SY window).  SM, FM: lengths of the per-axis weight and face
+// tables.
+template <int TX_, int TY_, int RG_ = 1>
 struct Tile {
   enum {
-    TX = TX_, TY = TY_, WX = TX + 2, WY = TY + 2, SX = TX + 4, SY = TY + 4,
+    TX = TX_, TY = TY_, RG = RG_, WX = TX + 2 * RG, WY = TY + 2 * RG, SX = WX + 2, SY = WY + 2,
     SM = SX > SY ? SX : SY, FM = (TX > TY ? TX : TY) + 1
   };
   static_assert(WX * WY == NTHR, "one thread per bar+ window cell");
@@ -34,6 +36,9 @@ struct Tile {
 typedef Tile<14, 14> TileSq;   // square tiles (the default)
 typedef Tile<30, 6> TileWide;  // wide tiles (long rows)
 typedef Tile<6, 30> TileTall;  // tall tiles (long columns)
+// UPWIND reconstruction: a face takes bar+ and both of its gradients at the
+// upwind cell, so the bar+ window reaches two cells beyond the tile
+typedef Tile<12, 12, 2> TileUpw;
 
 // x-face flux slots: directions with e_x != 0 (1, 3, 5, 6, 7, 8); y-face:
 // e_y != 0 (2, 4, 5, 6, 7, 8).  -1 = no flux across that face.
@@ -266,7 +271,7 @@ struct LAcc {
     H h;
     h.x = x;
     h.y = y;
-    const int px = win(x, x0 - 1, K->nx, S::WX), py = win(y, y0 - 1, K->ny, S::WY);
+    const int px = win(x, x0 - S::RG, K->nx, S::WX), py = win(y, y0 - S::RG, K->ny, S::WY);
     const int sxl = (X.bc != 0 && x == 0) ? 0 : 1, sxh = (X.bc != 0 && x == X.n - 1) ? 0 : 1;
     const int syl = (Y.bc != 0 && y == 0) ? 0 : 1, syh = (Y.bc != 0 && y == Y.n - 1) ? 0 : 1;
     const int lx1 = nbw(px - sxl, S::WX), hx1 = nbw(px + sxh, S::WX);
@@ -353,8 +358,8 @@ DFN int wrapi(int g, int n) {
   return r < 0 ? r + n : r;
 }
 
-// P0 of a tile with origin (x0, y0): phi, mu, p on the tile and a two-cell
-// ring, the App. B weight rows of the window's columns and rows, and the
+// P0 of a tile with origin (x0, y0): phi, mu, p on the scalar window (the
+// tile and an (RG + 1)-cell ring), the App. B weight rows of the window's columns and rows, and the
 // geometry and dt/|V| factors of the tile's faces and cells, into LDS.
 template <class S, class Lds = TileLds<S>>
 struct TileP0 {
@@ -380,8 +385,8 @@ struct TileP0 {
   // window element e: its global cell c, false outside the window or domain
   DFN bool win_elem(int e, i64 &c) const {
     if (e >= S::SX * S::SY) return false;
-    const int gx = gcol(x0 - 2 + e % S::SX, K.nx, K.ax[0].bc);
-    const int gy = gcol(y0 - 2 + e / S::SX, K.ny, K.ax[1].bc);
+    const int gx = gcol(x0 - S::RG - 1 + e % S::SX, K.nx, K.ax[0].bc);
+    const int gy = gcol(y0 - S::RG - 1 + e / S::SX, K.ny, K.ax[1].bc);
     if (gx < 0 || gy < 0) return false;
     c = (i64)gy * K.ld + gx;
     return true;
@@ -392,7 +397,7 @@ struct TileP0 {
     a = r < S::SX ? 0 : 1;
     pos = a == 0 ? r : r - S::SX;
     const Axis &X = K.ax[a];
-    g = gcol((a == 0 ? x0 : y0) - 2 + pos, X.n, X.bc);
+    g = gcol((a == 0 ? x0 : y0) - S::RG - 1 + pos, X.n, X.bc);
     return g >= 0;
   }
   // face role r: axis a, local face f, global face k
@@ -494,8 +499,8 @@ struct FusedTile {
   // window cell of thread tid: global column and row (-1 outside a wall domain)
   DFN void p1_cell(int tid, int &gx, int &gy) const {
     const int lx = tid % S::WX, ly = tid / S::WX;
-    gx = gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
-    gy = gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
+    gx = gcol(x0 - S::RG + lx, K.nx, K.ax[0].bc);
+    gy = gcol(y0 - S::RG + ly, K.ny, K.ax[1].bc);
   }
   DFN void p1_load(int tid, Pre &pr) const {
     int gx, gy;
@@ -516,7 +521,8 @@ struct FusedTile {
   DFN void p0_load(int tid, Pre0 &r) const { win().p0_load(tid, r); }
   DFN void p0_store(int tid, const Pre0 &r) const { win().p0_store(tid, r); }
 
-  // P1: Step 2 on the tile and a one-cell ring; tilde+ kept for the tile.
+  // P1: Step 2 on the bar+ window (the tile and its RG-cell ring); tilde+
+  // kept for the tile.
   DFN void p1(int tid, const Pre &pr) const {
     const int lx = tid % S::WX, ly = tid / S::WX;
     int gx, gy;
@@ -552,8 +558,8 @@ struct FusedTile {
     // tilde+ of the tile's own cells waits in LDS for P4, rounded as the
     // state encoding would round it; bar+ of those cells also goes to
     // w.barp when it is set (the adjoint's tape)
-    if (lx >= 1 && lx <= S::TX && ly >= 1 && ly <= S::TY && x0 + lx - 1 < K.nx &&
-        y0 + ly - 1 < K.ny) {
+    const int cx = lx - S::RG, cy = ly - S::RG;
+    if (cx >= 0 && cx < S::TX && cy >= 0 && cy < S::TY && x0 + cx < K.nx && y0 + cy < K.ny) {
       if (w.barp) {
         const i64 c = (i64)gy * K.ld + gx;
 #pragma unroll
@@ -565,7 +571,7 @@ struct FusedTile {
         tv[q] = (double)((R)(4.0 / 3.0) * (R)(double)out[q] - (R)(1.0 / 3.0) * til[q]);
       IO::roundtrip(tv);
 #pragma unroll
-      for (int q = 0; q < 18; ++q) L->T[q][ly - 1][lx - 1] = tv[q];
+      for (int q = 0; q < 18; ++q) L->T[q][cy][cx] = tv[q];
     }
   }
 
@@ -731,11 +737,14 @@ inline void swap_sums(Work &w) {
 }
 
 // Calls f(S{}) with the tile shape of a DUGKS2P_TILE_* value (1 square,
-// 2 wide, 3 tall).  The non-square shapes exist for unit lattice speed only;
-// other speeds always take square tiles.
+// 2 wide, 3 tall, 4 the two-ring tiles of UPWIND reconstruction).  Wide and
+// tall tiles exist for unit lattice speed only; other speeds take square
+// tiles for CENTRAL reconstruction.
 template <class F>
 void with_tile_shape(int shape, bool unit, F &&f) {
-  if (unit && shape == 2)
+  if (shape == 4)
+    f(TileUpw{});
+  else if (unit && shape == 2)
     f(TileWide{});
   else if (unit && shape == 3)
     f(TileTall{});

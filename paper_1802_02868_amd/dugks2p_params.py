@@ -11,7 +11,7 @@ BC_PERIODIC, BC_WALL = 0, 1
 FP64, FP32_STATE = 0, 1
 RECON_CENTRAL, RECON_UPWIND = 0, 1
 KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED = 0, 1, 2
-TILE_AUTO, TILE_SQUARE, TILE_WIDE, TILE_TALL = 0, 1, 2, 3
+TILE_AUTO, TILE_SQUARE, TILE_WIDE, TILE_TALL, TILE_UPWIND = 0, 1, 2, 3, 4
 ABI_VERSION = 1
 
 _DOUBLE_FIELDS = ("cfl", "c_max", "dt", "rt", "tau_g", "mobility", "tau_f", "beta", "kappa",

@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "../../paper_1802_02868_amd/csrc/dugks2p_fused.hpp"
@@ -117,8 +118,9 @@ static void run_steps(CpuEx &ex, const Consts &K, Work &w, IO st[2], int &cur, b
         if (K.unit)
           seq_fused_step<CpuEx, IO, double, true, S>(ex, K, w, st[cur], st[1 - cur], ready);
         else
-          seq_fused_step<CpuEx, IO, double, false, TileSq>(ex, K, w, st[cur], st[1 - cur],
-                                                           ready);
+          seq_fused_step<CpuEx, IO, double, false,
+                         typename std::conditional<S::RG == 2, TileUpw, TileSq>::type>(
+              ex, K, w, st[cur], st[1 - cur], ready);
       });
     cur = 1 - cur;
     swap_sums(w);
@@ -138,6 +140,8 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
   const bool fused = P->kernel == DUGKS2P_KERNEL_FUSED;
   const bool f32 = P->precision == DUGKS2P_FP32_STATE;
   if (f32 && !fused) return -2;
+  // the library's choice: UPWIND reconstruction runs on the two-ring tiles
+  const int shape = P->recon != DUGKS2P_RECON_CENTRAL ? DUGKS2P_TILE_UPWIND : P->tile;
   Layout L = make_layout(K, ax, ay, P->precision, true);
   std::vector<unsigned char> mem(L.total + 256, 0);
   unsigned char *base = (unsigned char *)(((uintptr_t)mem.data() + 255) & ~(uintptr_t)255);
@@ -156,7 +160,7 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
     IoF64 st[2] = {io_f64(base + L.state[0], K), io_f64(base + L.state[1], K)};
     seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
     if (fused) {
-      run_steps(ex, K, w, st, cur, true, nsteps, P->tile);
+      run_steps(ex, K, w, st, cur, true, nsteps, shape);
     } else {
       for (long long n = 0; n < nsteps; ++n) {
         seq_staged_step(ex, K, w, (const double *)st[cur].p, st[1 - cur].p);
@@ -172,7 +176,7 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
   } else {
     IoE32 st[2] = {io_e32(base + L.state[0], K, L), io_e32(base + L.state[1], K, L)};
     seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
-    run_steps(ex, K, w, st, cur, true, nsteps, P->tile);
+    run_steps(ex, K, w, st, cur, true, nsteps, shape);
     for (int j = 0; j < K.ny; ++j)
       for (int i = 0; i < K.nx; ++i) {
         st[cur].load((i64)j * K.ld + i, v);

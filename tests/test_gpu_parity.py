@@ -208,7 +208,7 @@ def test_nonfinite_detected(D):
     torch.cuda.synchronize()
 
 
-FUSED = {k: v for k, v in CASES.items() if "upwind" not in k}
+FUSED = dict(CASES)
 
 
 @pytest.mark.parametrize("name", sorted(FUSED))
@@ -222,7 +222,49 @@ def test_auto_kernel_choice(D):
     sim = D.Simulation.from_case(W.drop_case(n=16, radius=4.0))
     assert sim.kernel_kind == D.KERNEL_FUSED
     sim = D.Simulation.from_case(W.drop_case(n=16, radius=4.0, recon=1))
-    assert sim.kernel_kind == D.KERNEL_STAGED
+    assert sim.kernel_kind == D.KERNEL_FUSED and sim.tile == D.TILE_UPWIND
+
+
+UPWIND_CASES = [(lambda: W.rt_case(30, ny=50, amp_frac=0.2, recon=1), 12),
+                (lambda: W.bubble_case(32, 48, eo=20.0, mo=1e-3, recon=1), 12),
+                (lambda: W.drop_case(n=25, radius=8.0, recon=1), 9),
+                (lambda: W.tensor_drop_case(46, 30, 2.5, 0.5, bc_y=1, gx=2e-5), 9)]
+
+
+@pytest.mark.parametrize("k", range(len(UPWIND_CASES)))
+def test_fused_upwind_equals_staged_bitwise(D, k):
+    """UPWIND reconstruction on the fused kernel's two-ring tiles gives the
+    staged kernels' results bit for bit (walls, ragged tiles, a grid one
+    cell wider than two tiles, a stretched tensor mesh)."""
+    import torch
+    make, steps = UPWIND_CASES[k]
+    case = make()
+    case.params["recon"] = 1
+    print("upwind fused", case.name, steps, flush=True)
+    f = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)
+    assert f.kernel_kind == D.KERNEL_FUSED and f.tile == D.TILE_UPWIND
+    s = D.Simulation.from_case(case, kernel=D.KERNEL_STAGED)
+    f.step(steps)
+    s.step(steps)
+    assert torch.equal(f.populations(), s.populations())
+
+
+def test_fused_upwind_fp32_state_within_tolerance(D, oracle_mod):
+    """The FP32-state form with UPWIND reconstruction against the FP64
+    oracle: phi and u within 1e-4 (relative max-norm)."""
+    case = W.rt_case(64, ny=256, recon=1)
+    steps = 500
+    sim = D.Simulation.from_case(case, precision=D.FP32_STATE)
+    assert sim.kernel_kind == D.KERNEL_FUSED
+    sim.step(steps)
+    mom = {k2: v.cpu().numpy() for k2, v in sim.moments().items()}
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    m = o.moments()
+    errs = {f: relmax(mom[f], m[f]) for f in ("phi", "ux", "uy")}
+    print("fp32-state upwind", {f: "%.2e" % e for f, e in errs.items()}, flush=True)
+    for f, e in errs.items():
+        assert e <= FP32_TOL, (f, e)
 
 
 def test_fused_equals_staged_bitwise_rt(D):

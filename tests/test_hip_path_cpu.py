@@ -100,6 +100,34 @@ def test_fused_kernel_logic_bitwise_equal_to_oracle(oracle_mod, name):
     assert np.array_equal(pops, o.pops())
 
 
+UPWIND_FUSED_CASES = {
+    "drop": (lambda: W.drop_case(n=16, radius=5.0, recon=1), 10),
+    "rt_walls_ragged": (lambda: W.rt_case(30, ny=50, amp_frac=0.2, recon=1), 10),
+    "bubble_four_walls": (lambda: W.bubble_case(32, 48, eo=20.0, mo=1e-3, recon=1), 10),
+    "tile_plus_one": (lambda: W.drop_case(n=13, radius=4.0, recon=1), 5),
+    "single_cell": (lambda: W.drop_case(n=1, radius=0.3, noise=1e-3, recon=1), 3),
+    "two_cells": (lambda: W.drop_case(n=2, radius=0.7, noise=1e-3, recon=1), 3),
+    "tensor_walls_xy": (lambda: _upwind(W.tensor_drop_case(bc_x=1, bc_y=1, gx=2e-5)), 10),
+    "tensor_walls_y": (lambda: _upwind(W.tensor_drop_case(bc_x=0, bc_y=1, gy=-1e-5)), 10),
+}
+
+
+@pytest.mark.parametrize("name", sorted(UPWIND_FUSED_CASES))
+def test_fused_upwind_kernel_logic_bitwise_equal_to_oracle(oracle_mod, name):
+    """UPWIND reconstruction on the fused kernel's two-ring tiles (12 x 12
+    cells, bar+ two cells beyond the tile): host run of the phases against
+    the oracle, bit for bit."""
+    make, steps = UPWIND_FUSED_CASES[name]
+    case = make()
+    pops, mac = _emu.run(case, steps, kernel=2)
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    assert np.array_equal(pops, o.pops())
+    m = o.moments()
+    for k, f in enumerate(("phi", "rho", "ux", "uy", "p")):
+        assert np.array_equal(mac[k], m[f]), f
+
+
 @pytest.mark.parametrize("tile", [2, 3], ids=["wide30x6", "tall6x30"])
 @pytest.mark.parametrize("name", ["drop", "rt_walls_ragged", "bubble_four_walls",
                                   "single_cell", "tile_plus_one"])
@@ -127,13 +155,21 @@ def test_general_lattice_speed_kernel_logic(oracle_mod):
     for kernel in (1, 2):
         pops, _ = _emu.run(case, 8, kernel=kernel)
         assert np.array_equal(pops, o.pops()), kernel
+    # the same with UPWIND reconstruction (the two-ring tiles' general path)
+    case.params["recon"] = 1
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(8)
+    for kernel in (1, 2):
+        pops, _ = _emu.run(case, 8, kernel=kernel)
+        assert np.array_equal(pops, o.pops()), ("upwind", kernel)
 
 
 def test_fp32_state_kernel_logic_within_tolerance(oracle_mod):
     """FP32 state (f~ as floats, phi as FP64, g~ as float deviations) keeps
     phi and u within 1e-4 of the FP64 oracle."""
     for case, steps in [(W.rt_case(32, ny=128, amp_frac=0.2), 300),
-                        (W.drop_case(n=32, radius=8.0), 400)]:
+                        (W.drop_case(n=32, radius=8.0), 400),
+                        (W.rt_case(32, ny=128, amp_frac=0.2, recon=1), 300)]:
         case.params["precision"] = 1
         pops, mac = _emu.run(case, steps, kernel=2)
         o = oracle_mod.Oracle.from_case(case)
