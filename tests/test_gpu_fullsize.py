@@ -137,9 +137,9 @@ def test_rollout_2000_steps_rt512x2048(D):
     """A 2000-step differentiable rollout on the 512 x 2048 grid (64 interface
     modes, checkpoints every 50 steps, recomputation inside each segment):
     the rollout and its reverse sweep fit in device memory, and dJ of
-    J = sum (phi(T) - phi_ref)^2, phi_ref the initial interface of a second
-    seed, agrees along two seeded unit directions in scaled coordinates with
-    the central difference (step 1e-4) of two more rollouts of the same
+    J = sum (phi(T) - phi_ref(T))^2, phi_ref(T) from a rollout of a second
+    seed's modes, agrees along 8 seeded unit directions in scaled coordinates
+    with the central difference (step 1e-6) of two more rollouts of the same
     forward step (which equals the oracle bit for bit, tests above)."""
     import torch
     from paper_1802_02868_amd.rollout import rollout
@@ -148,8 +148,18 @@ def test_rollout_2000_steps_rt512x2048(D):
     a0 = W.rt_mode_amplitudes(512, 64, seed=2024)
     sig = 1e-3 * 512
     k0, g0 = case.params["kappa"], case.params["gy"]
-    R = torch.from_numpy(W.rt_interface_phi0(W.rt_mode_amplitudes(512, 64, seed=77), case)).cuda()
+
+    def phi_T(amps, kappa, gx, gy):
+        c = dataclasses.replace(case, phi0=W.rt_interface_phi0(amps, case),
+                                params=dict(case.params, kappa=kappa, gx=gx, gy=gy))
+        s = D.Simulation.from_case(c, precision=D.FP64)
+        s.step(steps)
+        out = s.populations()[9:].sum(0)
+        s.close()
+        return out
+
     print("rollout", case.name, steps, every, flush=True)
+    R = phi_T(W.rt_mode_amplitudes(512, 64, seed=77), k0, 0.0, g0)
     torch.cuda.reset_peak_memory_stats()
     a = torch.tensor(a0, dtype=torch.float64, device="cuda", requires_grad=True)
     kap = torch.tensor(k0, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -165,23 +175,13 @@ def test_rollout_2000_steps_rt512x2048(D):
                              g.grad.cpu().numpy() * abs(g0)])
     assert np.isfinite(grad_s).all()
     theta = np.concatenate([a0 / sig, [1.0], [0.0, g0 / abs(g0)]])
-
-    def phi_T(th):
-        c = dataclasses.replace(case, phi0=W.rt_interface_phi0(th[:64] * sig, case),
-                                params=dict(case.params, kappa=th[64] * k0, gx=th[65] * abs(g0),
-                                            gy=th[66] * abs(g0)))
-        s = D.Simulation.from_case(c, precision=D.FP64)
-        s.step(steps)
-        out = s.populations()[9:].sum(0)
-        s.close()
-        return out
-
     rng = np.random.default_rng(31)
-    eps = 1e-4
-    for _ in range(2):
+    eps = 1e-6
+    for _ in range(8):
         d = rng.standard_normal(theta.size)
         d /= np.linalg.norm(d)
-        pp, pm = phi_T(theta + eps * d), phi_T(theta - eps * d)
+        pp, pm = [phi_T(th[:64] * sig, th[64] * k0, th[65] * abs(g0), th[66] * abs(g0))
+                  for th in (theta + eps * d, theta - eps * d)]
         fd = float(((pp - pm) * (pp + pm - 2.0 * R)).sum()) / (2 * eps)
         ad = float(grad_s @ d)
         print("  direction: ad %.10e fd %.10e" % (ad, fd), flush=True)
