@@ -23,8 +23,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # 256 x 1024 workload, from FETCH_SIZE / WRITE_SIZE counters scaled by a
 # plain copy (profiles/fused_rt256x1024_fp64_traffic.md).  Valid only while
 # the kernel sources hash to the measured version.
-TRAFFIC = {"workload": "rt256x1024", "precision": "fp64", "tile": 1, "src_sha": "c20db4fc81a98950",
-           "bytes_per_launch": 104.13e6}
+TRAFFIC = {"workload": "rt256x1024", "precision": "fp64", "tile": 1, "src_sha": "abcf4fa157686e4d",
+           "bytes_per_launch": 104.28e6}
 
 FP64_VEC_PEAK_TF = 78.6    # MI355X FP64 vector
 FP32_VEC_PEAK_TF = 157.3

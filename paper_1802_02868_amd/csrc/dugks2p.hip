@@ -83,6 +83,11 @@ struct GpuEx {
     hipLaunchKernelGGL(k_macros, dim3(nb), dim3(MBX, MBY), 0, s, K, w, gx, nb);
     note(hipGetLastError());
   }
+  void macros_tape(const Consts &K, const Work &w, const Work &t) {
+    const int gx = (K.nx + MBX - 1) / MBX, nb = gx * ((K.ny + MBY - 1) / MBY);
+    hipLaunchKernelGGL(k_macros_tape, dim3(nb), dim3(MBX, MBY), 0, s, K, w, t, gx, nb);
+    note(hipGetLastError());
+  }
   template <class IO, class R, bool U, class S>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);

@@ -1073,8 +1073,8 @@ inline AdjLayout make_adj_layout(const Consts &K, const AxisHost &ax, const Axis
   off += align256(18 * sizeof(double) * (size_t)K.xplane);
   L.facey = off;
   off += align256(18 * sizeof(double) * (size_t)K.yplane);
-  L.fwork = off;  // cell fields of the fused step that advances the state
-  off += 23 * L.field_bytes;
+  L.fwork = off;  // phi and the f~ sums of the recomputed states (two sets)
+  off += 8 * L.field_bytes;
   for (int b = 0; b < 2; ++b) {
     L.lam[b] = off;
     off += L.state_bytes;
@@ -1113,13 +1113,13 @@ struct AdjBufs {
     return w;
   }
   // work fields of the fused step (its own, so the tape is untouched)
+  // phi and the f~ sums of the state being recomputed (phi, s0, jx, jy) and
+  // of the state the tile kernel writes (phin ..); the other fields are unset
   Work fused_work() const {
     Work w;
     memset(&w, 0, sizeof w);
-    double **f[23] = {&w.phi, &w.rho, &w.mu,  &w.dphx, &w.dphy, &w.dmux, &w.dmuy, &w.D,
-                      &w.Fx,  &w.Fy,  &w.ux,  &w.uy,   &w.p,    &w.dpx,  &w.dpy,  &w.tauf,
-                      &w.s0,  &w.jx,  &w.jy,  &w.phin, &w.s0n,  &w.jxn,  &w.jyn};
-    for (int k = 0; k < 23; ++k) *f[k] = (double *)(base + L.fwork + k * L.field_bytes);
+    double **f[8] = {&w.phi, &w.s0, &w.jx, &w.jy, &w.phin, &w.s0n, &w.jxn, &w.jyn};
+    for (int k = 0; k < 8; ++k) *f[k] = (double *)(base + L.fwork + k * L.field_bytes);
     return w;
   }
   double *lam(int b) const { return (double *)(base + L.lam[b]); }
@@ -1161,24 +1161,38 @@ void seq_adjoint_segment(Ex &ex, const Consts &K, const AdjBufs &B, const double
   for (int n = 0; n < nsteps; ++n) {
     const Work w = B.tape(n);
     const double *src = n == 0 ? pops0 : B.state(n);
-    // the tape: cell fields of the step and bar+.  bar+ is written by the
-    // fused step's tile kernel, which computes it with the same arithmetic
-    // (FCell only for the segment's last step, which has no fused step)
-    seq_staged_macros(ex, K, w, src);
-    if (n + 1 == nsteps)
-      ex.grid(FCell<double, double>{K, w, src}, K.nx, K.ny);
-    else
-      ex.grid(FCellFields<double>{K, w}, K.nx, K.ny);
-    // the next state, from the fused step (bitwise equal to the staged one)
-    if (n + 1 < nsteps) {
-      const IoF64 a{(double *)src, K.plane}, b{B.state(n + 1), K.plane};
-      wf.barp = w.barp;
-      // after the first step the tile kernel keeps the sums of the state
-      // it writes
+    const IoF64 a{(double *)src, K.plane};
+    // phi and the f~ sums of the state: computed for the checkpoint, then
+    // kept by the tile kernel for each state it writes
+    if (n == 0) {
       if (K.unit)
-        seq_fused_step<Ex, IoF64, double, true>(ex, K, wf, a, b, n > 0);
+        ex.grid(FPhiSums<IoF64, true>{K, wf, a}, K.nx, K.ny);
       else
-        seq_fused_step<Ex, IoF64, double, false>(ex, K, wf, a, b, n > 0);
+        ex.grid(FPhiSums<IoF64, false>{K, wf, a}, K.nx, K.ny);
+    }
+    // the tape: every cell field of the step from the macro kernel in tape
+    // mode (the arithmetic of the staged stages), then grad p and tau_f, and
+    // bar+.  bar+ comes from the tile kernel, which computes it with the
+    // same arithmetic (FCell only for the segment's last step, which has no
+    // fused step)
+    ex.macros_tape(K, wf, w);
+    if (n + 1 == nsteps) {
+      ex.grid(FCell<double, double>{K, w, src}, K.nx, K.ny);
+    } else {
+      ex.grid(FCellFields<double>{K, w}, K.nx, K.ny);
+      // the next state from the tile kernel (bitwise equal to the staged
+      // step), reading the tape's fields; the new state's sums go to the
+      // spare planes of wf
+      Work wt = w;
+      wt.phin = wf.phin;
+      wt.s0n = wf.s0n;
+      wt.jxn = wf.jxn;
+      wt.jyn = wf.jyn;
+      const IoF64 b{B.state(n + 1), K.plane};
+      if (K.unit)
+        ex.template tiles<IoF64, double, true, TileSq>(K, wt, a, b);
+      else
+        ex.template tiles<IoF64, double, false, TileSq>(K, wt, a, b);
       swap_sums(wf);
     }
   }

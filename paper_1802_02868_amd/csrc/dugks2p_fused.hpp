@@ -75,6 +75,7 @@ struct FPhiSums {
 // row (b1, b2).
 struct CellMac {
   double D, Fx, Fy, ux, uy, p;
+  double rho, dmux, dmuy, dphx, dphy;  // the intermediates, for the adjoint's tape
 };
 
 DFN CellMac macros_from(const Consts &K, double mc, double mxl, double mxh, double myl,
@@ -88,13 +89,18 @@ DFN CellMac macros_from(const Consts &K, double mc, double mxl, double mxh, doub
       (a2[0] * mxl + a2[1] * mc + a2[2] * mxh) + (b2[0] * myl + b2[1] * mc + b2[2] * myh);
   r.D = K.mobility * lapmu;
   const double rh = rho_of<double>(K, ph);
+  r.rho = rh;
+  r.dmux = dmux;
+  r.dmuy = dmuy;
   r.Fx = -ph * dmux + (rh - K.rho_ref) * K.gx;
   r.Fy = -ph * dmuy + (rh - K.rho_ref) * K.gy;
   const double icr = 1.0 / (K.cs2 * rh);
   r.ux = (jx + K.hdtcs2 * r.Fx) * icr;
   r.uy = (jy + K.hdtcs2 * r.Fy) * icr;
-  const double grx = K.drho * (a1[0] * pxl + a1[1] * ph + a1[2] * pxh);
-  const double gry = K.drho * (b1[0] * pyl + b1[1] * ph + b1[2] * pyh);
+  r.dphx = a1[0] * pxl + a1[1] * ph + a1[2] * pxh;
+  r.dphy = b1[0] * pyl + b1[1] * ph + b1[2] * pyh;
+  const double grx = K.drho * r.dphx;
+  const double gry = K.drho * r.dphy;
   r.p = s0 + K.hdtcs2 * (r.ux * grx + r.uy * gry - K.gam * rh * r.D);
   return r;
 }
@@ -144,6 +150,10 @@ struct MacBlock {
   const Work &w;
   int x0, y0;
   MacLds *L;
+  // tape mode (the adjoint's recomputation): every cell field of the step,
+  // phi and rho included, goes to *tape instead of w (phi and the sums are
+  // still read from w)
+  const Work *tape = nullptr;
   // global index of window offset g along an axis, or -1 outside a wall domain
   DFN int gcol(int g, int n, int bc) const {
     if (bc == 0) return wrapi(g, n);
@@ -175,13 +185,22 @@ struct MacBlock {
         L->mu[my + syh][mx], w.phi[c], w.phi[r + il], w.phi[r + ih], w.phi[(i64)jl * K.ld + i],
         w.phi[(i64)jh * K.ld + i], w.s0[c], w.jx[c], w.jy[c], X.d1 + 3 * i, X.d2 + 3 * i,
         Y.d1 + 3 * j, Y.d2 + 3 * j);
-    w.mu[c] = mc;
-    w.D[c] = m.D;
-    w.Fx[c] = m.Fx;
-    w.Fy[c] = m.Fy;
-    w.ux[c] = m.ux;
-    w.uy[c] = m.uy;
-    w.p[c] = m.p;
+    const Work &o = tape ? *tape : w;
+    if (tape) {
+      o.phi[c] = w.phi[c];
+      o.rho[c] = m.rho;
+      o.dphx[c] = m.dphx;
+      o.dphy[c] = m.dphy;
+      o.dmux[c] = m.dmux;
+      o.dmuy[c] = m.dmuy;
+    }
+    o.mu[c] = mc;
+    o.D[c] = m.D;
+    o.Fx[c] = m.Fx;
+    o.Fy[c] = m.Fy;
+    o.ux[c] = m.ux;
+    o.uy[c] = m.uy;
+    o.p[c] = m.p;
   }
 };
 
@@ -192,6 +211,18 @@ __global__ __launch_bounds__(MBX * MBY) void k_macros(Consts K, Work w, int gx, 
   __shared__ MacLds L;
   const int b = xcd_tile(blockIdx.x, nb);
   const MacBlock mb{K, w, (b % gx) * MBX, (b / gx) * MBY, &L};
+  const int tid = threadIdx.y * MBX + threadIdx.x;
+  mb.p0(tid);
+  __syncthreads();
+  mb.p1(tid);
+}
+
+// the same in tape mode: the cell fields of w's state into the tape slot t
+__global__ __launch_bounds__(MBX * MBY) void k_macros_tape(Consts K, Work w, Work t, int gx,
+                                                           int nb) {
+  __shared__ MacLds L;
+  const int b = xcd_tile(blockIdx.x, nb);
+  const MacBlock mb{K, w, (b % gx) * MBX, (b / gx) * MBY, &L, &t};
   const int tid = threadIdx.y * MBX + threadIdx.x;
   mb.p0(tid);
   __syncthreads();
