@@ -149,6 +149,38 @@ def batched_vs_plain(steps, precision):
             "precision": "fp64" if precision == D.FP64 else "fp32-state"}
 
 
+def upwind_rate(case, steps, prec):
+    """The same workload with UPWIND reconstruction: the fused step (two-ring
+    tiles) against the staged kernels, MLUPS from events around `steps`
+    steps each, and the fused tile kernel's time per launch."""
+    import dataclasses
+    import torch
+    from paper_1802_02868_amd import dugks2p as D
+    c = dataclasses.replace(case, params=dict(case.params, recon=D.RECON_UPWIND,
+                                              tile=D.TILE_AUTO))
+    out = {"recon": "upwind"}
+    for name, kern in (("fused", D.KERNEL_FUSED), ("staged", D.KERNEL_STAGED)):
+        if kern == D.KERNEL_STAGED and prec != D.FP64:
+            continue
+        sim = D.Simulation.from_case(c, precision=prec, kernel=kern)
+        sim.step(10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(sim.stream):
+            e0.record()
+            sim.step(steps)
+            e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[name + "_mlups"] = round(c.nx * c.ny / ms / 1e3, 1)
+        if kern == D.KERNEL_FUSED:
+            kms, n = sim.time_kernel(steps)
+            out["fused_tile_us"] = round(1e3 * kms / max(n, 1), 2)
+            out["tile"] = "12x12 two-ring" if sim.tile == D.TILE_UPWIND else sim.tile
+        out[name + "_nonfinite"] = int(sim.monitors(raise_nonfinite=False)[4])
+        sim.close()
+    return out
+
+
 def adjoint_cost(case, steps, every):
     """Forward rollout (fused FP64 steps, populations kept every `every`
     steps) against the reverse sweep (library adjoint: per segment the
@@ -211,6 +243,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-upwind", action="store_true",
+                    help="skip the UPWIND reconstruction leg")
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -324,6 +358,8 @@ def main():
                         "front_y": None if obs[6] != obs[6] else float(obs[6]),
                         "tip_y": None if obs[7] != obs[7] else float(obs[7])},
     }
+    if args.recon == "central" and not args.no_upwind:
+        out["upwind"] = upwind_rate(case, args.steps, prec)
     if not args.no_batched:
         out["batched"] = batched_vs_plain(args.batched_steps, D.FP32_STATE)
     if not args.no_adjoint and args.recon == "central":  # the adjoint is of CENTRAL steps
