@@ -395,9 +395,9 @@ int launch_step(dugks2p *h) {
 // real step rewrites) and keep the fastest.  Results do not depend on the
 // shape, only the speed does.
 int tune_tile(dugks2p *h) {
-  if (h->kernel != DUGKS2P_KERNEL_FUSED || !h->K.unit || h->K.recon != 0) {
-    h->tile = h->kernel == DUGKS2P_KERNEL_FUSED && h->K.recon != 0 ? DUGKS2P_TILE_UPWIND
-                                                                     : DUGKS2P_TILE_SQUARE;
+  const bool upw = h->K.recon != DUGKS2P_RECON_CENTRAL;
+  if (h->kernel != DUGKS2P_KERNEL_FUSED || !h->K.unit || upw) {
+    h->tile = h->kernel == DUGKS2P_KERNEL_FUSED && upw ? DUGKS2P_TILE_UPWIND : DUGKS2P_TILE_SQUARE;
     return DUGKS2P_OK;
   }
   enum { WARM = 1, REPS = 3 };
