@@ -216,8 +216,8 @@ const char *dugks2p_last_error(void);
  * 14x14 tile) entries), and runs of steps are captured once into HIP graphs
  * and replayed.  Each instance evolves exactly as a single handle with the
  * same parameters would (bit for bit).  All instances must share the
- * precision and use CENTRAL reconstruction (the fused kernel); one tile
- * shape serves the whole batch (dugks2p_batch_tile).
+ * precision and the reconstruction; one tile shape serves the whole batch
+ * (dugks2p_batch_tile; DUGKS2P_TILE_UPWIND for UPWIND reconstruction).
  *   params[n]: per-instance parameters (workspace fields ignored);
  *   phi0[n], ux0[n], uy0[n], p0[n]: device FP64 initial fields, each
  *   [ny_i][nx_i] for instance i.  The batch owns one device allocation. */
@@ -232,9 +232,10 @@ int dugks2p_batch_moments(dugks2p_batch *b, int32_t i, double *phi, double *rho,
 int dugks2p_batch_monitors(dugks2p_batch *b, int32_t i, double out[6]);
 int dugks2p_batch_get_populations(dugks2p_batch *b, int32_t i, double *dst);
 int64_t dugks2p_batch_cells(const dugks2p_batch *b);
-/* Tile shape of the batched tile kernel: the shape requested by every
- * instance when they agree on one, else (AUTO) the fastest shape found by
- * timing the batch's own step at creation. */
+/* Tile shape of the batched tile kernel: DUGKS2P_TILE_UPWIND for UPWIND
+ * reconstruction; else the shape requested by every instance when they
+ * agree on one, else (AUTO) the fastest shape found by timing the batch's
+ * own step at creation. */
 int dugks2p_batch_tile(const dugks2p_batch *b);
 int dugks2p_batch_destroy(dugks2p_batch *b);
 

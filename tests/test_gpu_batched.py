@@ -40,6 +40,33 @@ def test_batch_instances_bitwise_equal_single(D, prec):
         assert b.monitors(i)[5] == 32
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_upwind_batch_instances_bitwise_equal_single(D, prec):
+    """A batch of UPWIND instances (two-ring tiles) evolves bit for bit as
+    single handles, across graph boundaries."""
+    p = D.FP64 if prec == "fp64" else D.FP32_STATE
+    cases = _cases()
+    for c in cases:
+        c.params["recon"] = D.RECON_UPWIND
+    b = D.BatchSimulation(cases, precision=p)
+    assert b.tile == D.TILE_UPWIND
+    b.step(13)
+    b.step(19)
+    for i, c in enumerate(cases):
+        print("upwind batch", prec, i, c.name, flush=True)
+        s = D.Simulation.from_case(c, precision=p, kernel=D.KERNEL_FUSED)
+        assert s.tile == D.TILE_UPWIND
+        s.step(32)
+        assert np.array_equal(b.populations(i).cpu().numpy(), s.populations().cpu().numpy()), i
+
+
+def test_batch_rejects_mixed_reconstruction(D):
+    c = W.drop_case(n=16, radius=4.0)
+    c2 = W.drop_case(n=16, radius=4.0, recon=1)
+    with pytest.raises(D.DugksError):
+        D.BatchSimulation([c, c2])
+
+
 def test_batch_rejects_mixed_precision(D):
     c = W.drop_case(n=16, radius=4.0)
     c2 = W.drop_case(n=16, radius=4.0)
