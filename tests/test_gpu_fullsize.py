@@ -36,6 +36,21 @@ def test_rt256x1024_fp64_bitwise(D, oracle_mod):
     assert np.array_equal(s.populations().cpu().numpy(), o.pops())
 
 
+def test_rt256x1024_upwind_fp64_bitwise(D, oracle_mod):
+    """UPWIND reconstruction at the full headline size, on the fused kernel's
+    two-ring tiles as bench.py's UPWIND leg runs it: the oracle's populations
+    bit for bit after 60 steps."""
+    case = W.rt_case(256, recon=1)
+    steps = 60
+    print("full size fp64 upwind", case.name, steps, flush=True)
+    s = D.Simulation.from_case(case, precision=D.FP64)
+    assert s.kernel_kind == D.KERNEL_FUSED and s.tile == D.TILE_UPWIND
+    s.step(steps)
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    assert np.array_equal(s.populations().cpu().numpy(), o.pops())
+
+
 def test_rt256x1024_fp32_state_within_tolerance(D, oracle_mod):
     case = W.rt_case(256)
     case.params["tile"] = D.TILE_SQUARE
