@@ -374,3 +374,33 @@ def test_tile_tuner_picks_a_shape(D):
     with pytest.raises(D.DugksError):
         case.params["tile"] = 7
         D.Simulation.from_case(case)
+
+
+def _drop_profile_deviation(D, lam=0.1, cfl=0.4, radius=25.0, T=5000.0):
+    """Run the paper's 100 x 100 drop to time T; return the RMS deviation of
+    the density from the initial (analytic tanh) profile over rho_A - rho_B,
+    and the median-level mass before and after."""
+    c = W.paper_drop_case(radius, cfl=cfl, mobility=lam)
+    p = c.params
+    sim = D.Simulation.from_case(c, kernel=D.KERNEL_FUSED)
+    sim.step(int(round(T / sim.dt)))
+    m = sim.moments()
+    assert sim.monitors()[4] == 0
+    rho0 = p["rho_b"] + (p["rho_a"] - p["rho_b"]) * c.phi0
+    dev = np.sqrt(np.mean((m["rho"].cpu().numpy() - rho0) ** 2)) / (p["rho_a"] - p["rho_b"])
+    mass = (W.drop_mass_median(c.phi0), W.drop_mass_median(m["phi"].cpu().numpy()))
+    print("drop r %g lam %g cfl %g: profile deviation %.4e, mass %d -> %d" % (
+        radius, lam, cfl, dev, mass[0], mass[1]), flush=True)
+    return dev, mass
+
+
+def test_paper_drop_profile_trends(D):
+    """Sec. 3.1's qualitative findings on the stationary drop (the figures'
+    values are not in the text): the equilibrium density profile departs
+    further from the analytic one as the mobility grows (CFL 0.4), and a
+    smaller CFL number (time step) agrees better (mobility 0.1)."""
+    by_lam = [_drop_profile_deviation(D, lam=lam)[0] for lam in (0.01, 0.1, 0.5)]
+    assert by_lam[0] < by_lam[1] < by_lam[2], by_lam
+    by_cfl = [_drop_profile_deviation(D, cfl=cfl)[0] for cfl in (0.1, 0.4, 0.8)]
+    assert by_cfl[0] < by_cfl[1] < by_cfl[2], by_cfl
+
