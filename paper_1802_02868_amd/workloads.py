@@ -367,14 +367,15 @@ def paper_bubble_case(ratio=2, steps=20000) -> Case:
                 z.copy(), steps, dict(diameter=2 * l0 / 5.0, g=1e-5))
 
 
-def paper_rt_case(atwood=0.1, steps=20000) -> Case:
+def paper_rt_case(atwood=0.1, re=3000.0, steps=20000) -> Case:
     """Rayleigh-Taylor as Sec. 3.4 sets it up: d = L = 256 on [0, d] x
     [-2d, 2d], walls top and bottom, periodic sides, interface
-    2d + 0.05 d cos(2 pi x / L), Re = 3000, sqrt(g L) = 0.04, W = 4,
-    sigma = 5e-5; At = 0.1 with CFL 0.35, or At = 0.5 with CFL 0.283."""
+    2d + 0.05 d cos(2 pi x / L), Re = 3000 (150 in the same figure's first
+    row), sqrt(g L) = 0.04, W = 4, sigma = 5e-5; At = 0.1 with CFL 0.35, or
+    At = 0.5 with CFL 0.283."""
     cfl = 0.35 if atwood < 0.3 else 0.283
-    c = rt_case(256, atwood=atwood, re=3000.0, amp_frac=0.05, cfl=cfl, steps=steps)
-    c.name = "paper_rt256x1024_at%g" % atwood
+    c = rt_case(256, atwood=atwood, re=re, amp_frac=0.05, cfl=cfl, steps=steps)
+    c.name = "paper_rt256x1024_at%g%s" % (atwood, "" if re == 3000.0 else "_re%g" % re)
     return c
 
 
@@ -387,6 +388,7 @@ PAPER_CASES = {
     "paper_bubble160x480_ratio2": lambda: paper_bubble_case(2),
     "paper_bubble160x480_ratio5": lambda: paper_bubble_case(5),
     "paper_rt256x1024_at0.1": lambda: paper_rt_case(0.1),
+    "paper_rt256x1024_at0.1_re150": lambda: paper_rt_case(0.1, re=150.0),
 }
 
 
