@@ -231,7 +231,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    # the first few hundred steps run about 1.7 % slower than the steady state
+    # (clocks and caches settling); 500 untimed steps take about 33 ms
+    ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="rt256x1024")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
     ap.add_argument("--kernel", choices=("auto", "staged", "fused"), default="auto")
