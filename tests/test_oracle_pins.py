@@ -445,6 +445,22 @@ def test_mass_conservation(oracle_mod):
     assert abs(o.monitors()[0] - m0) / m0 < 1e-13
 
 
+def test_drop_energy_never_increases(oracle_mod):
+    """Without a body force the free energy (eq. freeenergyfunction) plus the
+    kinetic energy of a drop only decays: sampled every few steps it never
+    rises (a sanity check of the dissipative structure, not an exact pin)."""
+    for c, every in [(W.drop_case(n=32, radius=8.0, noise=1e-3), 20),
+                     (W.paper_drop_case(25.0), 50)]:
+        c.params.update(gx=0.0, gy=0.0)
+        o = oracle_mod.Oracle.from_case(c)
+        E = []
+        for _ in range(30):
+            m = o.monitors()
+            E.append(m[1] + m[2])
+            o.step(every)
+        assert np.all(np.diff(E) < 0.0), (c.name, np.diff(E))
+
+
 def test_shift_equivariance_bitwise(oracle_mod):
     c = W.drop_case(n=24, radius=6.0, noise=1e-3, seed=9, centre=(10.0, 13.0))
     a = oracle_mod.Oracle.from_case(c)
