@@ -28,6 +28,28 @@ def test_library_exports_every_declared_symbol():
     assert set(D.EXPORTED) <= set(names)
 
 
+def test_create_rejects_small_or_misaligned_workspace():
+    """dugks2p_create checks a caller's workspace before it touches the GPU:
+    fewer bytes than dugks2p_workspace_bytes() is ENOMEM, an address that is
+    not 256-byte aligned is EINVAL.  The device pointers passed here are
+    placeholders that these checks never dereference."""
+    import ctypes
+    from paper_1802_02868_amd import dugks2p as D
+    from paper_1802_02868_amd.dugks2p_params import make_params
+    c = W.drop_case(n=16, radius=4.0)
+    P = make_params(c.params, c.x_faces, c.y_faces, D.FP64, D.KERNEL_AUTO)
+    nb = int(D.lib.dugks2p_workspace_bytes(ctypes.byref(P)))
+    assert nb > 0
+    fake = ctypes.c_void_p(1 << 20)
+    h = ctypes.c_void_p()
+    for addr, size, code in [(1 << 20, nb - 1, D.ENOMEM), ((1 << 20) + 8, nb, D.EINVAL)]:
+        P.workspace = addr
+        P.workspace_bytes = size
+        rc = D.lib.dugks2p_create(ctypes.byref(P), fake, fake, fake, fake, None, ctypes.byref(h))
+        assert rc == code, (rc, D.lib.dugks2p_last_error())
+        assert not h.value
+
+
 def test_workspace_query_validates_parameters():
     from paper_1802_02868_amd import dugks2p as D
     c = W.drop_case(n=16, radius=4.0)
