@@ -35,7 +35,12 @@ def _cases():
     ragged = W.rt_case(7, 13)
     ragged.params.update(gx=1e-5)
     tensor = W.tensor_drop_case(18, 16, 1.5, 1.0, bc_x=1, bc_y=0, gx=1e-5, gy=-2e-5)
-    return [(drop, 3, 2), (rt, 7, 3), (pz, 5, 5), (bub, 6, 4), (ragged, 4, 3), (tensor, 5, 2)]
+    # a general lattice speed (RT = 0.3, c != 1): the general-direction code
+    speed = W.drop_case(n=20, radius=5.0, noise=1e-3)
+    speed.params.update(rt=0.3, c_max=0.0, cfl=0.4, gx=1e-5, gy=-2e-5, phi_clamp=0)
+    speed.name = "drop20_rt0.3"
+    return [(drop, 3, 2), (rt, 7, 3), (pz, 5, 5), (bub, 6, 4), (ragged, 4, 3), (tensor, 5, 2),
+            (speed, 7, 3)]
 
 
 CASES = _cases()

@@ -129,20 +129,3 @@ def test_adjoint_dot_product_tile_edges(oracle_mod, case):
     rhs = float(np.sum(g0 * d)) + float(g3 @ dp)
     assert abs(lhs - rhs) <= 1e-13 * float(np.sum(np.abs(lam * jv))), (lhs, rhs)
 
-
-def test_adjoint_dot_product_general_lattice_speed(oracle_mod):
-    """RT = 0.3 (lattice speed c != 1): the general-direction code of the
-    recomputation (tape kernel, tile kernel) and of the reverse stages, with
-    gravity in both axes, holds the identity to machine precision."""
-    from paper_1802_02868_amd import workloads as W
-    case = W.drop_case(n=20, radius=5.0, noise=1e-3)
-    case.params.update(rt=0.3, c_max=0.0, cfl=0.4, gx=1e-5, gy=-2e-5, phi_clamp=0)
-    rng = np.random.default_rng(5)
-    lam = rng.standard_normal((18, case.ny, case.nx))
-    _, g0, g3 = _emu.adjoint(case, 7, 3, lam)
-    d = rng.standard_normal((case.ny, case.nx))
-    dp = rng.standard_normal(3)
-    _, jv = oracle_mod.complex_step_jvp(case, 7, d, *dp)
-    lhs = float(np.sum(lam * jv))
-    rhs = float(np.sum(g0 * d)) + float(g3 @ dp)
-    assert abs(lhs - rhs) <= 1e-13 * float(np.sum(np.abs(lam * jv))), (lhs, rhs)
