@@ -263,7 +263,9 @@ typedef struct dugks2p_adj dugks2p_adj;
 size_t dugks2p_adjoint_workspace_bytes(const dugks2p_params *params, int32_t max_segment);
 
 /* New adjoint object (params.workspace, if given, must hold
- * dugks2p_adjoint_workspace_bytes bytes, 256-byte aligned). */
+ * dugks2p_adjoint_workspace_bytes bytes, 256-byte aligned).  Valid forward
+ * parameters outside the adjoint's scope (FP32 state, UPWIND, phi_clamp)
+ * return DUGKS2P_EUNSUPPORTED; invalid ones DUGKS2P_EINVAL. */
 int dugks2p_adjoint_create(const dugks2p_params *params, int32_t max_segment, void *hip_stream,
                            dugks2p_adj **out);
 

@@ -93,7 +93,7 @@ def test_gpu_adjoint_contracts(D):
         p.update(over)
         with pytest.raises(D.DugksError) as e:
             D.Adjoint(p, case.x_faces, case.y_faces, max_segment=4)
-        assert e.value.code == D.EINVAL
+        assert e.value.code == D.EUNSUPPORTED
     with pytest.raises(D.DugksError):
         D.Adjoint(case.params, case.x_faces, case.y_faces, max_segment=0)
     adj = D.Adjoint(case.params, case.x_faces, case.y_faces, max_segment=2)

@@ -50,6 +50,26 @@ def test_create_rejects_small_or_misaligned_workspace():
         assert not h.value
 
 
+def test_adjoint_create_scope_errors():
+    """dugks2p_adjoint_create before any GPU work: valid forward parameters
+    outside the adjoint's scope (FP32 state, UPWIND, phi_clamp) are
+    EUNSUPPORTED, an invalid segment length is EINVAL."""
+    import ctypes
+    from paper_1802_02868_amd import dugks2p as D
+    from paper_1802_02868_amd.dugks2p_params import make_params
+    c = W.drop_case(n=16, radius=4.0)
+    h = ctypes.c_void_p()
+    for over, mseg, code in [(dict(precision=D.FP32_STATE), 4, D.EUNSUPPORTED),
+                             (dict(recon=D.RECON_UPWIND), 4, D.EUNSUPPORTED),
+                             (dict(phi_clamp=1), 4, D.EUNSUPPORTED),
+                             ({}, 0, D.EINVAL), (dict(tau_g=-1.0), 4, D.EINVAL)]:
+        p = dict(c.params, **over)
+        P = make_params(p, c.x_faces, c.y_faces, p.get("precision", D.FP64), D.KERNEL_STAGED)
+        rc = D.lib.dugks2p_adjoint_create(ctypes.byref(P), mseg, None, ctypes.byref(h))
+        assert rc == code, (over, mseg, rc, D.lib.dugks2p_last_error())
+        assert not h.value
+
+
 def test_workspace_query_validates_parameters():
     from paper_1802_02868_amd import dugks2p as D
     c = W.drop_case(n=16, radius=4.0)
