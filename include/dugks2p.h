@@ -216,7 +216,8 @@ const char *dugks2p_last_error(void);
  * 14x14 tile) entries), and runs of steps are captured once into HIP graphs
  * and replayed.  Each instance evolves exactly as a single handle with the
  * same parameters would (bit for bit).  All instances must share the
- * precision and the reconstruction; one tile shape serves the whole batch
+ * precision and the reconstruction (else DUGKS2P_EUNSUPPORTED); one tile
+ * shape serves the whole batch
  * (dugks2p_batch_tile; DUGKS2P_TILE_UPWIND for UPWIND reconstruction).
  *   params[n]: per-instance parameters (workspace fields ignored);
  *   phi0[n], ux0[n], uy0[n], p0[n]: device FP64 initial fields, each

@@ -63,16 +63,18 @@ def test_upwind_batch_instances_bitwise_equal_single(D, prec):
 def test_batch_rejects_mixed_reconstruction(D):
     c = W.drop_case(n=16, radius=4.0)
     c2 = W.drop_case(n=16, radius=4.0, recon=1)
-    with pytest.raises(D.DugksError):
+    with pytest.raises(D.DugksError) as e:
         D.BatchSimulation([c, c2])
+    assert e.value.code == D.EUNSUPPORTED
 
 
 def test_batch_rejects_mixed_precision(D):
     c = W.drop_case(n=16, radius=4.0)
     c2 = W.drop_case(n=16, radius=4.0)
     c2.params = dict(c2.params, precision=1)
-    with pytest.raises(D.DugksError):
+    with pytest.raises(D.DugksError) as e:
         D.BatchSimulation([c, c2])
+    assert e.value.code == D.EUNSUPPORTED
 
 
 @pytest.mark.parametrize("tile", [0, 2, 3], ids=["tuned", "wide", "tall"])
