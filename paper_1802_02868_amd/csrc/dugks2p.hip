@@ -35,10 +35,12 @@ int fail(int code, const std::string &msg) {
 // One thread per (i, j) in a 64 x 4 block.  The grid is one-dimensional:
 // workgroups are dealt to the 8 XCDs round robin, and xcd_tile gives each
 // XCD a contiguous run of blocks (a band of rows), so that the rows a
-// stencil reads above and below a block sit in the same XCD's L2.
+// stencil reads above and below a block sit in the same XCD's L2.  xcd = 0
+// keeps the plain row-major block order (measured faster for the staged
+// step's face kernels, slower for the adjoint's per-cell stages).
 template <class F>
-__global__ __launch_bounds__(256) void k_grid(F f, int n0, int n1, int gx, int nb) {
-  const int b = xcd_tile(blockIdx.x, nb);
+__global__ __launch_bounds__(256) void k_grid(F f, int n0, int n1, int gx, int nb, int xcd) {
+  const int b = xcd ? xcd_tile(blockIdx.x, nb) : (int)blockIdx.x;
   const int i = (b % gx) * 64 + threadIdx.x;
   const int j = (b / gx) * 4 + threadIdx.y;
   if (i < n0 && j < n1) f(i, j);
@@ -70,11 +72,12 @@ struct GpuEx {
   hipStream_t s;
   hipError_t err;
   KernelTimer *kt = nullptr;
+  int xcd = 1;  // block order of the per-cell kernels (see k_grid)
   template <class F>
   void grid(const F &f, int n0, int n1) {
     if (n0 <= 0 || n1 <= 0) return;
     const int gx = (n0 + 63) / 64, nb = gx * ((n1 + 3) / 4);
-    hipLaunchKernelGGL(k_grid<F>, dim3(nb), dim3(64, 4), 0, s, f, n0, n1, gx, nb);
+    hipLaunchKernelGGL(k_grid<F>, dim3(nb), dim3(64, 4), 0, s, f, n0, n1, gx, nb, xcd);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess && err == hipSuccess) err = e;
   }
@@ -347,6 +350,7 @@ using SqOrUpw = typename std::conditional<S::RG == 2, TileUpw, TileSq>::type;
 int enqueue_step(dugks2p *h, int shape) {
   GpuEx ex{h->stream, hipSuccess, &h->kt};
   if (h->precision == DUGKS2P_FP64 && h->kernel == DUGKS2P_KERNEL_STAGED) {
+    ex.xcd = 0;
     seq_staged_step<GpuEx, double, double>(ex, h->K, h->w, (const double *)h->state[h->cur],
                                            (double *)h->state[1 - h->cur]);
   } else if (h->precision == DUGKS2P_FP64) {
