@@ -25,8 +25,9 @@ def build(openmp: bool = True) -> str:
     if openmp:
         base.append("-fopenmp")
     for extra, out in (([], LIB_PATH), (["-DORC_COMPLEX_STEP"], CS_LIB_PATH)):
-        subprocess.run(base + extra + ["-o", out + ".tmp", SRC_PATH, "-lm"], check=True)
-        os.replace(out + ".tmp", out)
+        tmp = "%s.tmp%d" % (out, os.getpid())  # concurrent test workers may build too
+        subprocess.run(base + extra + ["-o", tmp, SRC_PATH, "-lm"], check=True)
+        os.replace(tmp, out)
     return LIB_PATH
 
 
@@ -59,6 +60,7 @@ def lib():
         L.orc_cell_transforms.argtypes = [ctypes.c_void_p, P(d), P(d)]
         L.orc_reconstruct.argtypes = [ctypes.c_void_p, P(d), P(d), P(d)]
         L.orc_face_dists.argtypes = [ctypes.c_void_p, P(d), P(d)]
+        L.orc_face_fields.argtypes = [ctypes.c_void_p] + [P(d)] * 7
         _lib = L
     return _lib
 
@@ -233,6 +235,16 @@ class Oracle:
         fy = np.empty((18, self.ny + 1, self.nx))
         lib().orc_reconstruct(self._h, _ptr(barp), _ptr(fx), _ptr(fy))
         return fx, fy
+
+    def face_fields(self, field):
+        """The face operator of reading R5 applied to a cell field: value,
+        normal derivative and tangential derivative at every x face
+        ([ny, nx+1] each) and y face ([ny+1, nx] each)."""
+        field = _f64(field).reshape(self.ny, self.nx)
+        xs = [np.empty((self.ny, self.nx + 1)) for _ in range(3)]
+        ys = [np.empty((self.ny + 1, self.nx)) for _ in range(3)]
+        lib().orc_face_fields(self._h, _ptr(field), *[_ptr(a) for a in xs + ys])
+        return xs, ys
 
     def face_dists(self):
         fx = np.empty((18, self.ny, self.nx + 1))

@@ -902,6 +902,51 @@ void orc_reconstruct(const orc_sim *s, const double *barp, double *xface, double
   free(gx); free(gy); free(fx); free(fy);
 }
 
+/* R5 alone: the face operator applied to a given cell field F, with the
+ * tangential derivative taken by the App. B first-derivative stencil of the
+ * tangential axis, exactly as Step 4 feeds mu, phi and p to it. */
+void orc_face_fields(const orc_sim *s, const double *F, double *xv, double *xdn, double *xdt,
+                     double *yv, double *ydn, double *ydt) {
+  const int nx = s->nx, ny = s->ny, nfx = s->ax[0].nf, nfy = s->ax[1].nf;
+  const long N = s->N, NX = (long)ny * nfx, NY = (long)nfy * nx;
+  double *dfx = malloc(sizeof(double) * N), *dfy = malloc(sizeof(double) * N);
+  double *fx = malloc(sizeof(double) * 18 * NX), *fy = malloc(sizeof(double) * 18 * NY);
+  double *ox = malloc(sizeof(double) * 18 * (long)ny * (nx + 1));
+  double *oy = malloc(sizeof(double) * 18 * (long)(ny + 1) * nx);
+  if (!dfx || !dfy || !fx || !fy || !ox || !oy) {
+    free(dfx); free(dfy); free(fx); free(fy); free(ox); free(oy);
+    return;
+  }
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      dfx[(long)j * nx + i] = sx(s, s->ax[0].d1, F, i, j);
+      dfy[(long)j * nx + i] = sy(s, s->ax[1].d1, F, i, j);
+    }
+  /* planes 0..2 of the face layout carry value, normal and tangential
+   * derivative; copy_faces_out then maps the stored faces to nx+1 / ny+1 */
+  memset(fx, 0, sizeof(double) * 18 * NX);
+  memset(fy, 0, sizeof(double) * 18 * NY);
+  for (int j = 0; j < ny; ++j)
+    for (int k = 0; k < nfx; ++k) {
+      const long o = (long)j * nfx + k;
+      face_field(s, 0, k, j, F, dfy, &fx[o], &fx[NX + o], &fx[2 * NX + o]);
+    }
+  for (int k = 0; k < nfy; ++k)
+    for (int i = 0; i < nx; ++i) {
+      const long o = (long)k * nx + i;
+      face_field(s, 1, k, i, F, dfx, &fy[o], &fy[NY + o], &fy[2 * NY + o]);
+    }
+  copy_faces_out(s, fx, fy, ox, oy);
+  const long OX = (long)ny * (nx + 1), OY = (long)(ny + 1) * nx;
+  memcpy(xv, ox, sizeof(double) * OX);
+  memcpy(xdn, ox + OX, sizeof(double) * OX);
+  memcpy(xdt, ox + 2 * OX, sizeof(double) * OX);
+  memcpy(yv, oy, sizeof(double) * OY);
+  memcpy(ydn, oy + OY, sizeof(double) * OY);
+  memcpy(ydt, oy + 2 * OY, sizeof(double) * OY);
+  free(dfx); free(dfy); free(fx); free(fy); free(ox); free(oy);
+}
+
 void orc_face_dists(orc_sim *s, double *xface, double *yface) {
   cell_macros(s);
   cell_transforms(s);

@@ -85,6 +85,14 @@ void orc_cell_transforms(orc_sim *s, double *barp, double *tilp);
  * repeats face 0).  Wall faces use the wall rule. */
 void orc_reconstruct(const orc_sim *s, const double *barp, double *xface, double *yface);
 
+/* The face operator of R5 (value, normal derivative, tangential derivative
+ * of a cell field at every face; the tangential derivative from the App. B
+ * first-derivative stencil along the face) applied to a given cell field F
+ * [ny][nx].  Layout as orc_reconstruct: x faces [ny][nx+1], y faces
+ * [ny+1][nx]. */
+void orc_face_fields(const orc_sim *s, const double *F, double *xv, double *xdn, double *xdt,
+                     double *yv, double *ydn, double *ydt);
+
 /* Step 4 face distributions phi(x_b, t+h) of the current state, same layout. */
 void orc_face_dists(orc_sim *s, double *xface, double *yface);
 
