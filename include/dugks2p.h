@@ -83,8 +83,9 @@ enum {
  *   phi_clamp:   nonzero clamps phi into [phi_b, phi_a] inside rho() and
  *                mu_d() only (never in the state).
  *   precision:   DUGKS2P_FP64 (state and arithmetic in double) or
- *                DUGKS2P_FP32_STATE (float state, float arithmetic except the
- *                order parameter sum and the chemical potential, in double).
+ *                DUGKS2P_FP32_STATE (the populations stored as floats, with
+ *                the cell order parameter phi = sum g~ kept in double; every
+ *                arithmetic operation of the step still in double).
  *   recon:       face reconstruction of Step 3: CENTRAL = linear
  *                interpolation of value and gradient (the paper's choice);
  *                UPWIND = expansion from the upwind cell.
@@ -132,9 +133,18 @@ size_t dugks2p_workspace_bytes(const dugks2p_params *params);
 int dugks2p_create(const dugks2p_params *params, const double *phi0, const double *ux0,
                    const double *uy0, const double *p0, void *hip_stream, dugks2p **out);
 
-/* Advance nsteps >= 0 time steps (Steps 2-7 of Sec. 2.2), asynchronously on
- * the handle's stream. */
+/* Advance nsteps >= 0 time steps (Steps 2-7 of Sec. 2.2) on the handle's
+ * stream.  By default the call only enqueues work (asynchronous, no check
+ * of the result).  With checks enabled (dugks2p_set_checks), it also counts
+ * the non-finite populations after every `every`-th step of the call and
+ * after its last step, synchronising the stream for each count, and returns
+ * DUGKS2P_ENONFINITE at the first count that is nonzero; the handle then
+ * holds that state and dugks2p_step_count() tells how far it ran. */
 int dugks2p_step(dugks2p *h, int64_t nsteps);
+
+/* Checks of dugks2p_step: every > 0 enables them (see above), 0 (the
+ * default) disables them. */
+int dugks2p_set_checks(dugks2p *h, int64_t every);
 
 /* Cell fields at the current time (Step 7: eqs. oderrho, phi, u, P): writes
  * phi, rho, ux, uy, p (device, FP64, [ny][nx]); any pointer may be NULL. */
@@ -211,10 +221,10 @@ const char *dugks2p_last_error(void);
 
 /* ---- Batched form ------------------------------------------------------
  * n independent simulations of arbitrary, uneven sizes advanced together:
- * each time step is three launches over the concatenated work of all
+ * each time step is two launches over the concatenated work of all
  * instances (a flattened list of (instance, cell block) and (instance,
- * 14x14 tile) entries), and runs of steps are captured once into HIP graphs
- * and replayed.  Each instance evolves exactly as a single handle with the
+ * tile) entries; one more pass forms the population sums after creation),
+ * and runs of steps are captured once into HIP graphs and replayed.  Each instance evolves exactly as a single handle with the
  * same parameters would (bit for bit).  All instances must share the
  * precision and the reconstruction (else DUGKS2P_EUNSUPPORTED); one tile
  * shape serves the whole batch

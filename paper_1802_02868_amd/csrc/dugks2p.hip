@@ -273,6 +273,25 @@ struct FLaplaceP {
   }
 };
 
+// Number of non-finite populations of a state, added into *cnt (a rare
+// event, so one atomic per thread that finds any).
+template <class IO>
+__global__ __launch_bounds__(256) void k_count_nonfinite(Consts K, IO st,
+                                                         unsigned long long *cnt) {
+  const i64 n = (i64)K.nx * K.ny;
+  unsigned int bad = 0;
+  for (i64 r = (i64)blockIdx.x * 256 + threadIdx.x; r < n; r += (i64)gridDim.x * 256) {
+    const i64 j = r / K.nx, i = r - j * K.nx;
+    double v[18];
+    st.load(j * K.ld + i, v);
+    for (int q = 0; q < 18; ++q)
+      if (!(v[q] - v[q] == 0.0)) ++bad;
+  }
+  if (bad) atomicAdd(cnt, (unsigned long long)bad);
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+
 // State <-> FP64 [18][ny][nx], one thread per cell.
 template <class IO>
 __global__ __launch_bounds__(256) void k_pops_out(Consts K, IO st, double *dst) {
@@ -313,6 +332,7 @@ struct dugks2p {
   int64_t nstep;
   KernelTimer kt;
   bool sums_ok;  // w.phi, s0, jx, jy hold the sums of state[cur]
+  int64_t check_every;  // dugks2p_set_checks: 0 = no checks in dugks2p_step
 };
 
 namespace {
@@ -433,6 +453,24 @@ int tune_tile(dugks2p *h) {
   return rc;
 }
 
+// Count the non-finite populations of the current state; synchronises the
+// stream.  The counter is a spare slot after the monitor partials.
+int count_nonfinite(dugks2p *h, unsigned long long &bad) {
+  unsigned long long *cnt = (unsigned long long *)(h->mon_out + 12);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, h->stream, cnt);
+  HIPCHK(hipGetLastError());
+  if (h->precision == DUGKS2P_FP64)
+    hipLaunchKernelGGL(k_count_nonfinite<IoF64>, dim3(1024), dim3(256), 0, h->stream, h->K,
+                       io_f64(h->state[h->cur], h->K), cnt);
+  else
+    hipLaunchKernelGGL(k_count_nonfinite<IoE32>, dim3(1024), dim3(256), 0, h->stream, h->K,
+                       io_e32(h->state[h->cur], h->K, h->L), cnt);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(&bad, cnt, sizeof bad, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DUGKS2P_OK;
+}
+
 // Cell fields of the current state into the work arrays.
 int launch_macros(dugks2p *h) {
   GpuEx ex{h->stream, hipSuccess};
@@ -482,6 +520,7 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
                   : DUGKS2P_TILE_SQUARE;
   h->cur = 0;
   h->nstep = 0;
+  h->check_every = 0;
   h->sums_ok = false;
   if (P->workspace) {
     h->ws = (unsigned char *)P->workspace;
@@ -557,9 +596,27 @@ int dugks2p_step(dugks2p *h, int64_t nsteps) {
   if (!h) return fail(DUGKS2P_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(DUGKS2P_EINVAL, "nsteps must be >= 0");
   for (int64_t n = 0; n < nsteps; ++n) {
-    const int rc = launch_step(h);
+    int rc = launch_step(h);
     if (rc) return rc;
+    // optional checks (dugks2p_set_checks): after every check_every-th step
+    // of the call and after its last step
+    if (h->check_every > 0 && ((n + 1) % h->check_every == 0 || n + 1 == nsteps)) {
+      unsigned long long bad = 0;
+      rc = count_nonfinite(h, bad);
+      if (rc) return rc;
+      if (bad)
+        return fail(DUGKS2P_ENONFINITE, std::to_string(bad) +
+                                            " non-finite populations in the state after step " +
+                                            std::to_string(h->nstep));
+    }
   }
+  return DUGKS2P_OK;
+}
+
+int dugks2p_set_checks(dugks2p *h, int64_t every) {
+  if (!h) return fail(DUGKS2P_EINVAL, "handle is NULL");
+  if (every < 0) return fail(DUGKS2P_EINVAL, "every must be >= 0");
+  h->check_every = every;
   return DUGKS2P_OK;
 }
 

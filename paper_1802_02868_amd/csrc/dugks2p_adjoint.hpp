@@ -670,10 +670,8 @@ struct AdjCellTile {
 #ifdef DUGKS2P_WINDOW_CHECK
     if (v < 0 || v >= lim) {
       printf("adjoint cell window check: %d outside [0, %d)\n", v, lim);
-#if !defined(__HIP_DEVICE_COMPILE__)
       fflush(stdout);
-#endif
-      __builtin_trap();
+      abort();
     }
 #else
     (void)lim;

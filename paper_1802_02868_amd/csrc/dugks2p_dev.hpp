@@ -421,7 +421,7 @@ DFN void cell_barp(const Consts &K, const Mac<R> &m, R tf, const R til[18], R ou
 }
 
 // grad p, tau_f, and Step 2: bar+ into w.barp.  R is the arithmetic type of
-// the transforms (double, or float for the FP32-state form).
+// the transforms (double in every instantiation the library builds).
 template <class T, class R = double>
 struct FCell {
   Consts K;

@@ -1,8 +1,11 @@
-// dugks2p_fused.hpp -- the step as three launches:
-//   1. FPhiSums: phi = sum g~ and the f~ sums (one thread per cell);
-//   2. FMacF:    mu, D, F, u, p (one thread per cell; mu of the four
-//                neighbours recomputed from phi);
-//   3. tile kernel: for a tile (14 x 14 by default), Step 2 (bar+) on the
+// dugks2p_fused.hpp -- the step as two launches, plus a third after a
+// fresh state:
+//   0. FPhiSums: phi = sum g~ and the f~ sums (one thread per cell), only
+//                when the state did not come from a tile kernel, which
+//                writes these sums of the state it stores;
+//   1. k_macros: mu, D, F, u, p over 64 x 4 blocks of cells (FMacF is the
+//                same arithmetic one thread per cell);
+//   2. tile kernel: for a tile (14 x 14 by default), Step 2 (bar+) on the
 //                tile and a one-cell ring (two cells for UPWIND) into LDS,
 //                Steps 3-4 at every face of the tile (each face once), flux
 //                exchange through LDS, Steps 5-6.
@@ -16,6 +19,17 @@
 #pragma once
 
 #include "dugks2p_dev.hpp"
+
+// DUGKS2P_WINDOW_CHECK turns every LDS-window access of the tile code into a
+// bounds-checked one that aborts the process.  It exists for the host build
+// of the kernel logic (tests/emu); a GPU build must never carry it.
+#if defined(DUGKS2P_WINDOW_CHECK)
+#if defined(__HIP_DEVICE_COMPILE__)
+#error "DUGKS2P_WINDOW_CHECK is for the host build of the kernel logic only"
+#endif
+#include <stdio.h>
+#include <stdlib.h>
+#endif
 
 namespace dg {
 
@@ -326,10 +340,8 @@ struct LAcc {
 #ifdef DUGKS2P_WINDOW_CHECK
     if (off < 0 || off >= lim) {
       printf("window check: offset %d outside [0, %d)\n", off, lim);
-#if !defined(__HIP_DEVICE_COMPILE__)
       fflush(stdout);
-#endif
-      __builtin_trap();
+      abort();
     }
 #else
     (void)lim;
@@ -359,10 +371,8 @@ struct LAcc {
 #ifdef DUGKS2P_WINDOW_CHECK
     if (f < 0 || f > (a == 0 ? S::TX : S::TY)) {
       printf("face check: axis %d face %d local %d\n", a, k, f);
-#if !defined(__HIP_DEVICE_COMPILE__)
       fflush(stdout);
-#endif
-      __builtin_trap();
+      abort();
     }
 #endif
     FaceGeo g;

@@ -416,7 +416,7 @@ void seq_staged_macros(Ex &ex, const Consts &K, const Work &w, const T *src) {
 }
 
 // One time step with the staged kernels (one pass per stage).
-// R: arithmetic type of Steps 2-6 (double; float for the FP32-state form).
+// R: arithmetic type of Steps 2-6 (double: every form computes in FP64).
 template <class Ex, class T, class R = double>
 void seq_staged_step(Ex &ex, const Consts &K, const Work &w, const T *src, T *dst) {
   seq_staged_macros(ex, K, w, src);

@@ -46,6 +46,8 @@ def _load():
     L.dugks2p_create.argtypes = [P(Params), vp, vp, vp, vp, vp, P(vp)]
     L.dugks2p_step.restype = ctypes.c_int
     L.dugks2p_step.argtypes = [vp, ctypes.c_int64]
+    L.dugks2p_set_checks.restype = ctypes.c_int
+    L.dugks2p_set_checks.argtypes = [vp, ctypes.c_int64]
     L.dugks2p_moments.restype = ctypes.c_int
     L.dugks2p_moments.argtypes = [vp, vp, vp, vp, vp, vp]
     L.dugks2p_monitors.restype = ctypes.c_int
@@ -112,7 +114,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2p_moments",
+EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2p_set_checks",
+            "dugks2p_moments",
             "dugks2p_monitors", "dugks2p_observables", "dugks2p_laplace_pressure",
             "dugks2p_get_populations",
             "dugks2p_set_populations",
@@ -133,7 +136,7 @@ def _check(rc):
     return rc
 
 
-def workspace_bytes(p: dict, x_faces, y_faces, precision=FP64, kernel=KERNEL_AUTO) -> int:
+def workspace_bytes(p: dict, x_faces, y_faces, precision=None, kernel=None) -> int:
     P = make_params(p, x_faces, y_faces, precision, kernel)
     return int(lib.dugks2p_workspace_bytes(ctypes.byref(P)))
 
@@ -144,8 +147,8 @@ class Simulation:
     phi0, ux0, uy0, p0: torch float64 CUDA tensors (or numpy arrays, copied to
     the device) of shape [ny, nx]."""
 
-    def __init__(self, params: dict, x_faces, y_faces, phi0, ux0, uy0, p0, precision=FP64,
-                 kernel=KERNEL_AUTO, stream=None, torch_workspace=True):
+    def __init__(self, params: dict, x_faces, y_faces, phi0, ux0, uy0, p0, precision=None,
+                 kernel=None, stream=None, torch_workspace=True):
         import torch
         self.torch = torch
         self.nx, self.ny = int(params["nx"]), int(params["ny"])
@@ -224,6 +227,12 @@ class Simulation:
     def step(self, n=1):
         _check(lib.dugks2p_step(self._h, int(n)))
 
+    def set_checks(self, every):
+        """every > 0: step() counts the non-finite populations after every
+        `every`-th step and after its last step (synchronising) and raises
+        DugksError(ENONFINITE) at the first nonzero count; 0 disables."""
+        _check(lib.dugks2p_set_checks(self._h, int(every)))
+
     def time_kernel(self, n):
         """Run n steps with HIP events around the tile kernel; returns
         (total kernel milliseconds, timed launches)."""
@@ -293,7 +302,7 @@ class BatchSimulation:
     launches replayed from HIP graphs).  `cases`: objects with params,
     x_faces, y_faces, phi0, ux0, uy0, p0 (see workloads.Case)."""
 
-    def __init__(self, cases, precision=FP64, stream=None):
+    def __init__(self, cases, precision=None, stream=None):
         import torch
         self.torch = torch
         self.cases = list(cases)
@@ -372,7 +381,7 @@ class Adjoint:
         self.max_segment = int(max_segment)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        P = make_params(params, x_faces, y_faces, FP64, KERNEL_STAGED)
+        P = make_params(params, x_faces, y_faces)
         nb = int(lib.dugks2p_adjoint_workspace_bytes(ctypes.byref(P), self.max_segment))
         self._ws = None
         if nb:

@@ -28,16 +28,30 @@ class Params(ctypes.Structure):
                [("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
-def make_params(p: dict, x_faces, y_faces, precision=FP64, kernel=KERNEL_AUTO):
+def _choose(p: dict, name: str, arg, default: int) -> int:
+    """An explicit argument wins; the dictionary's entry is used when the
+    argument is None; the two may not disagree."""
+    if arg is None:
+        return int(p.get(name, default))
+    if name in p and int(p[name]) != int(arg):
+        raise ValueError("%s=%d conflicts with the parameter dictionary's %s=%d"
+                         % (name, int(arg), name, int(p[name])))
+    return int(arg)
+
+
+def make_params(p: dict, x_faces, y_faces, precision=None, kernel=None):
     """Fill a Params struct from the parameter dictionary used by the
-    workloads module; keeps the face arrays alive on the struct."""
+    workloads module; keeps the face arrays alive on the struct.
+    `precision` and `kernel` given explicitly take effect; None takes the
+    dictionary's entry (default FP64 / KERNEL_AUTO); a dictionary entry that
+    disagrees with an explicit argument raises ValueError."""
     P = Params()
     P.abi_version = ABI_VERSION
     for n in _INT_FIELDS[1:]:
         if n in p:
             setattr(P, n, int(p[n]))
-    P.precision = int(p.get("precision", precision))
-    P.kernel = int(p.get("kernel", kernel))
+    P.precision = _choose(p, "precision", precision, FP64)
+    P.kernel = _choose(p, "kernel", kernel, KERNEL_AUTO)
     for n in _DOUBLE_FIELDS:
         setattr(P, n, float(p[n]))
     xf = np.ascontiguousarray(x_faces, dtype=np.float64)

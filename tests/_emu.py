@@ -13,9 +13,9 @@ CSRC = os.path.join(os.path.dirname(HERE), "paper_1802_02868_amd", "csrc")
 
 def build():
     cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-Wall", "-Wno-unknown-pragmas",
-           "-o", LIB + ".tmp", SRC]
+           "-o", "%s.tmp%d" % (LIB, os.getpid()), SRC]
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace("%s.tmp%d" % (LIB, os.getpid()), LIB)
     return LIB
 
 

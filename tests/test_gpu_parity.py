@@ -228,6 +228,37 @@ def test_nonfinite_detected(D):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("kernel,prec", [("staged", "fp64"), ("fused", "fp64"),
+                                         ("fused", "fp32")])
+def test_step_checks_report_nonfinite(D, kernel, prec):
+    """With checks on, dugks2p_step itself returns ENONFINITE after the step
+    that leaves a non-finite population; with checks off it only enqueues;
+    a clean run with checks gives the same state bit for bit."""
+    import torch
+    case = W.drop_case(n=16, radius=4.0)
+    kw = dict(kernel=D.KERNEL_STAGED if kernel == "staged" else D.KERNEL_FUSED,
+              precision=D.FP64 if prec == "fp64" else D.FP32_STATE)
+    print("checks", kernel, prec, flush=True)
+    clean, ref = D.Simulation.from_case(case, **kw), D.Simulation.from_case(case, **kw)
+    clean.set_checks(3)
+    clean.step(7)
+    ref.step(7)
+    assert torch.equal(clean.populations(), ref.populations())
+    sim = D.Simulation.from_case(case, **kw)
+    pops = sim.populations()
+    pops[12, 5, 7] = float("nan")
+    sim.set_populations(pops)
+    sim.step(2)  # no checks: enqueued, no error
+    sim.set_checks(4)
+    with pytest.raises(D.DugksError) as e:
+        sim.step(9)
+    assert e.value.code == D.ENONFINITE
+    assert sim.nstep == 2 + 4  # stopped at the first check
+    sim.set_checks(0)
+    sim.step(1)
+    torch.cuda.synchronize()
+
+
 FUSED = dict(CASES)
 
 

@@ -231,3 +231,24 @@ def test_paper_parameter_sets_kernel_logic(oracle_mod, name):
     o = oracle_mod.Oracle.from_case(case)
     o.step(2)
     assert np.array_equal(pops, o.pops())
+
+
+def test_make_params_explicit_arguments_win():
+    """An explicit precision or kernel reaches the struct; a dictionary entry
+    is used only when the argument is left out, and a disagreement between
+    the two is an error rather than a silent switch."""
+    from paper_1802_02868_amd import dugks2p_params as DP
+    c = W.drop_case(n=8, radius=2.0)
+    P = DP.make_params(c.params, c.x_faces, c.y_faces, DP.FP32_STATE, DP.KERNEL_STAGED)
+    assert (P.precision, P.kernel) == (DP.FP32_STATE, DP.KERNEL_STAGED)
+    P = DP.make_params(c.params, c.x_faces, c.y_faces)
+    assert (P.precision, P.kernel) == (DP.FP64, DP.KERNEL_AUTO)
+    p = dict(c.params, precision=DP.FP32_STATE, kernel=DP.KERNEL_FUSED)
+    P = DP.make_params(p, c.x_faces, c.y_faces)
+    assert (P.precision, P.kernel) == (DP.FP32_STATE, DP.KERNEL_FUSED)
+    P = DP.make_params(p, c.x_faces, c.y_faces, DP.FP32_STATE, DP.KERNEL_FUSED)
+    assert (P.precision, P.kernel) == (DP.FP32_STATE, DP.KERNEL_FUSED)
+    with pytest.raises(ValueError):
+        DP.make_params(p, c.x_faces, c.y_faces, precision=DP.FP64)
+    with pytest.raises(ValueError):
+        DP.make_params(p, c.x_faces, c.y_faces, kernel=DP.KERNEL_STAGED)
