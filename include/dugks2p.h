@@ -158,6 +158,19 @@ int dugks2p_moments(dugks2p *h, double *phi, double *rho, double *ux, double *uy
  * filled). */
 int dugks2p_monitors(dugks2p *h, double out[6]);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the monitors of dugks2p_monitors, written by kernels on the handle's
+ * stream to out (device, 6 doubles, caller-owned) in the same order, with no
+ * allocation, no host copy and no synchronisation.  The per-block partials
+ * go to a statically allocated 16 MiB device array of the library, one per
+ * GPU, held until the process ends: grids of more than 419 428 blocks of
+ * 64 x 4 cells (about 107 million cells) return DUGKS2P_EINVAL.  Every call
+ * on a GPU shares that GPU's array, so calls that overlap in time on one GPU
+ * (on different streams or threads) race and must be ordered by the caller.
+ * The non-finite count is out[4]; the return value does not report it. */
+int dugks2p_monitors_noalloc(dugks2p *h, double *out);
+
 /* Interface observables at the current time, host out[8]:
  *   out[0]  number of cells with phi above the median level
  *           (phi_A + phi_B)/2: the droplet mass of Sec. 3.1 (Table 1);

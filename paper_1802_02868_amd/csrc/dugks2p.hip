@@ -6,6 +6,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -177,6 +178,18 @@ __global__ __launch_bounds__(256) void k_mon_final(const double *part, long long
     for (int m = 0; m < 5; ++m) out[m] = sh[m][0];
 }
 
+// Monitors into device memory (dugks2p_monitors_noalloc): v[5] as
+// k_mon_final leaves them -> out[6] with max |u| = sqrt(max |u|^2) and the
+// step count.
+__global__ void k_mon_out(const double *v, double step, double *out) {
+  out[0] = v[0];
+  out[1] = v[1];
+  out[2] = v[2];
+  out[3] = sqrt(v[3]);
+  out[4] = v[4];
+  out[5] = step;
+}
+
 // Observables (dugks2p_observables): per 64 x 4 block of cells, the sums
 // (cells above the median level, their area, c|V|, c|V| x, c|V| y, c|V| u_x,
 // c|V| u_y with c = (phi - phi_B)/(phi_A - phi_B)) and the largest and
@@ -333,6 +346,7 @@ struct dugks2p {
   KernelTimer kt;
   bool sums_ok;  // w.phi, s0, jx, jy hold the sums of state[cur]
   int64_t check_every;  // dugks2p_set_checks: 0 = no checks in dugks2p_step
+  int device;           // HIP device current at creation (holds the workspace)
 };
 
 namespace {
@@ -521,6 +535,10 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
   h->cur = 0;
   h->nstep = 0;
   h->check_every = 0;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(DUGKS2P_EHIP, "hipGetDevice");
+  }
   h->sums_ok = false;
   if (P->workspace) {
     h->ws = (unsigned char *)P->workspace;
@@ -658,6 +676,76 @@ int dugks2p_monitors(dugks2p *h, double out[6]) {
   out[5] = (double)h->nstep;
   if (v[4] > 0.0) return fail(DUGKS2P_ENONFINITE, "non-finite populations in the state");
   return DUGKS2P_OK;
+}
+
+}  // extern "C"
+
+// Scratch of dugks2p_monitors_noalloc: the per-block monitor partials and
+// the five reduced values, in a statically allocated array that every GPU
+// the library runs on holds until the process ends.  Host code never uses
+// the array's name as an address: the device address of each GPU's copy is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and kept in scratch_dev.
+namespace {
+enum : long long { SCRATCH_DOUBLES = 2 * 1024 * 1024 };  // 16 MiB
+enum { SCRATCH_MAX_DEV = 64 };
+}  // namespace
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+std::mutex scratch_mu;
+double *scratch_dev[SCRATCH_MAX_DEV];
+
+// Device address of `scratch` on device dev, which must be current.
+int scratch_ptr(int dev, double **out) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEV) return fail(DUGKS2P_EUNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DUGKS2P_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                    hipGetErrorString(e));
+    scratch_dev[dev] = (double *)p;
+  }
+  *out = scratch_dev[dev];
+  return DUGKS2P_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dugks2p_monitors_noalloc(dugks2p *h, double *out) {
+  if (!h || !out) return fail(DUGKS2P_EINVAL, "NULL argument");
+  const dim3 b(64, 4), g((h->K.nx + 63) / 64, (h->K.ny + 3) / 4);
+  const long long nb = (long long)g.x * g.y;
+  if (5 * nb + 8 > SCRATCH_DOUBLES)
+    return fail(DUGKS2P_EINVAL, "grid too large for the static monitor scratch: " +
+                                    std::to_string(nb) + " blocks of 64 x 4 cells, at most " +
+                                    std::to_string((SCRATCH_DOUBLES - 8) / 5));
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != h->device) HIPCHK(hipSetDevice(h->device));
+  double *part = nullptr;
+  int rc = scratch_ptr(h->device, &part);
+  if (rc == DUGKS2P_OK) rc = launch_macros(h);
+  if (rc == DUGKS2P_OK) {
+    double *v = part + 5 * nb;
+    if (h->precision == DUGKS2P_FP64)
+      hipLaunchKernelGGL(k_mon_partial<IoF64>, g, b, 0, h->stream, h->K, h->w,
+                         io_f64(h->state[h->cur], h->K), part);
+    else
+      hipLaunchKernelGGL(k_mon_partial<IoE32>, g, b, 0, h->stream, h->K, h->w,
+                         io_e32(h->state[h->cur], h->K, h->L), part);
+    hipLaunchKernelGGL(k_mon_final, dim3(1), dim3(256), 0, h->stream, (const double *)part, nb,
+                       v);
+    hipLaunchKernelGGL(k_mon_out, dim3(1), dim3(1), 0, h->stream, (const double *)v,
+                       (double)h->nstep, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = fail(DUGKS2P_EHIP, std::string("monitor launch: ") + hipGetErrorString(e));
+  }
+  if (cur != h->device) (void)hipSetDevice(cur);
+  return rc;
 }
 
 int dugks2p_laplace_pressure(dugks2p *h, double *P) {

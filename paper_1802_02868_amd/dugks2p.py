@@ -52,6 +52,8 @@ def _load():
     L.dugks2p_moments.argtypes = [vp, vp, vp, vp, vp, vp]
     L.dugks2p_monitors.restype = ctypes.c_int
     L.dugks2p_monitors.argtypes = [vp, P(d)]
+    L.dugks2p_monitors_noalloc.restype = ctypes.c_int
+    L.dugks2p_monitors_noalloc.argtypes = [vp, vp]
     L.dugks2p_observables.restype = ctypes.c_int
     L.dugks2p_observables.argtypes = [vp, P(d)]
     L.dugks2p_laplace_pressure.restype = ctypes.c_int
@@ -116,7 +118,7 @@ lib = _load()
 
 EXPORTED = ("dugks2p_workspace_bytes", "dugks2p_create", "dugks2p_step", "dugks2p_set_checks",
             "dugks2p_moments",
-            "dugks2p_monitors", "dugks2p_observables", "dugks2p_laplace_pressure",
+            "dugks2p_monitors", "dugks2p_monitors_noalloc", "dugks2p_observables", "dugks2p_laplace_pressure",
             "dugks2p_get_populations",
             "dugks2p_set_populations",
             "dugks2p_state_bytes", "dugks2p_get_state", "dugks2p_set_state", "dugks2p_dt",
@@ -259,6 +261,16 @@ class Simulation:
         if rc != OK and (raise_nonfinite or rc != ENONFINITE):
             _check(rc)
         return np.array(out[:])
+
+    def monitors_noalloc(self, out):
+        """The monitors into `out` (float64 CUDA tensor of 6 elements, the
+        caller's), enqueued on the handle's stream without allocation or
+        synchronisation (include/dugks2p.h)."""
+        if out.dtype != self.torch.float64 or not out.is_cuda or out.numel() < 6 \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 CUDA tensor of 6 elements")
+        _check(lib.dugks2p_monitors_noalloc(self._h, out.data_ptr()))
+        return out
 
     def observables(self):
         """[droplet cells, their area, phase-A centroid x, y, mean u_x, u_y,
