@@ -79,6 +79,18 @@ def describe(name: str) -> str:
     return "rising bubble, Eo 30, Mo 1e-3, four walls"
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(case, seconds=10.0):
     """The oracle as it stands, on the host cores, over a bounded number of
     steps of the same workload."""
@@ -96,7 +108,7 @@ def cpu_baseline(case, seconds=10.0):
     cells = case.nx * case.ny
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     return {"value": round(cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "%d steps of %s (%dx%d), FP64, OpenMP over rows" % (
                 n, case.name, case.nx, case.ny)}
 
@@ -109,6 +121,7 @@ def batched_vs_plain(steps, precision):
     from paper_1802_02868_amd import workloads as W
     cases = W.bubble_batch(48)
     cells = sum(c.nx * c.ny for c in cases)
+    rho_ratio = cases[0].params["rho_a"] / cases[0].params["rho_b"]
     b = D.BatchSimulation(cases, precision=precision)
     b.step(8)
     torch.cuda.synchronize()
@@ -146,7 +159,12 @@ def batched_vs_plain(steps, precision):
             "plain_loop_order": best[0], "speedup": round(best[1] / t_batch, 3),
             "nonfinite_instances": int(sum(1 for m in mon if m > 0)),
             "tile": ["auto", "14x14", "30x6", "6x30"][tile],
-            "precision": "fp64" if precision == D.FP64 else "fp32-state"}
+            "precision": "fp64" if precision == D.FP64 else "fp32-state",
+            # the benchmark plan's bubbles use rho_g / rho_l = 1e-3 and 5000
+            # steps; at that ratio the scheme (the oracle included) diverges
+            # within tens of steps, so the batch runs 0.1 for `steps` steps
+            "rho_g_over_rho_l": rho_ratio, "substituted_for": "48 bubbles, rho_g/rho_l 1e-3, 5000 steps",
+            "substitution_reason": "the oracle itself goes non-finite at rho_g/rho_l 1e-3"}
 
 
 def upwind_rate(case, steps, prec):
@@ -178,6 +196,70 @@ def upwind_rate(case, steps, prec):
             out["tile"] = "12x12 two-ring" if sim.tile == D.TILE_UPWIND else sim.tile
         out[name + "_nonfinite"] = int(sim.monitors(raise_nonfinite=False)[4])
         sim.close()
+    return out
+
+
+def kernel_rate(case, prec, kern, steps, warmup):
+    """MLUPS of `steps` steps (events on the handle's stream) and the tile
+    kernel's mean launch time (events the launches set), after `warmup`."""
+    import torch
+    from paper_1802_02868_amd import dugks2p as D
+    sim = D.Simulation.from_case(case, precision=prec, kernel=kern)
+    sim.step(warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kms, n = sim.time_kernel(steps)
+    tile_us = 1e3 * kms / max(n, 1)
+    bad = int(sim.monitors(raise_nonfinite=False)[4])
+    tile = sim.tile
+    sim.close()
+    cells = case.nx * case.ny
+    bpc = 288 if prec == D.FP64 else 152
+    return {"mlups": round(cells / ms / 1e3, 1), "ms_per_step": round(ms, 5),
+            "tile_us": round(tile_us, 2),
+            "frac": round(bpc * cells / (tile_us / 1e6) / 1e9 / HBM_PEAK_GBS, 4),
+            "step_frac": round(bpc * cells / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "tile": ["auto", "14x14", "30x6", "6x30", "12x12 two-ring"][tile],
+            "nonfinite": bad}
+
+
+def fma_leg(case, prec, steps, warmup):
+    """The FMA-contracted fused step (DUGKS2P_KERNEL_FUSED_FMA) on the same
+    workload, and the largest population deviation from the exact kernel
+    after the same number of steps."""
+    import torch
+    from paper_1802_02868_amd import dugks2p as D
+    out = kernel_rate(case, prec, D.KERNEL_FUSED_FMA, steps, warmup)
+    a = D.Simulation.from_case(case, precision=prec, kernel=D.KERNEL_FUSED)
+    b = D.Simulation.from_case(case, precision=prec, kernel=D.KERNEL_FUSED_FMA)
+    a.step(200)
+    b.step(200)
+    pa, pb = a.populations(), b.populations()
+    dev = max(float((pb[q] - pa[q]).abs().max() / pa[q].abs().max()) for q in range(18))
+    torch.cuda.synchronize()
+    a.close()
+    b.close()
+    out["relmax_vs_exact_after_200_steps"] = dev
+    return out
+
+
+def large_grid(nx, prec, steps, warmup):
+    """The same physics on nx x 4nx, a state far larger than the 256 MB
+    MALL, exact and FMA-contracted."""
+    from paper_1802_02868_amd import dugks2p as D
+    from paper_1802_02868_amd import workloads as W
+    case = W.rt_case(nx)
+    case.params["tile"] = D.TILE_SQUARE
+    bpc = 288 if prec == D.FP64 else 152
+    out = {"workload": "%s (%dx%d cells, %.1f GB ping-pong state)" % (
+        case.name, case.nx, case.ny, 2 * bpc / 2 * case.nx * case.ny / 1e9)}
+    out["exact"] = kernel_rate(case, prec, D.KERNEL_FUSED, steps, warmup)
+    out["fma"] = kernel_rate(case, prec, D.KERNEL_FUSED_FMA, steps, warmup)
     return out
 
 
@@ -236,7 +318,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="rt256x1024")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
-    ap.add_argument("--kernel", choices=("auto", "staged", "fused"), default="auto")
+    ap.add_argument("--kernel", choices=("auto", "staged", "fused", "fma"), default="auto")
     ap.add_argument("--recon", choices=("central", "upwind"), default="central",
                     help="face reconstruction of Step 3 (central: the paper's)")
     ap.add_argument("--tile", choices=("auto", "square", "wide", "tall"), default="square",
@@ -245,6 +327,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-fma", action="store_true", help="skip the FMA-contracted leg")
+    ap.add_argument("--large-nx", type=int, default=2048,
+                    help="out-of-MALL leg on nx x 4nx (0: skip)")
     ap.add_argument("--no-upwind", action="store_true",
                     help="skip the UPWIND reconstruction leg")
     ap.add_argument("--adjoint-steps", type=int, default=200)
@@ -273,7 +358,8 @@ def main():
     torch.cuda.set_device(0)
     case = workload(args.workload)
     prec = D.FP64 if args.precision == "fp64" else D.FP32_STATE
-    kern = {"auto": D.KERNEL_AUTO, "staged": D.KERNEL_STAGED, "fused": D.KERNEL_FUSED}[args.kernel]
+    kern = {"auto": D.KERNEL_AUTO, "staged": D.KERNEL_STAGED, "fused": D.KERNEL_FUSED,
+            "fma": D.KERNEL_FUSED_FMA}[args.kernel]
     case.params["tile"] = {"auto": D.TILE_AUTO, "square": D.TILE_SQUARE, "wide": D.TILE_WIDE,
                            "tall": D.TILE_TALL}[args.tile]
     case.params["recon"] = {"central": D.RECON_CENTRAL, "upwind": D.RECON_UPWIND}[args.recon]
@@ -305,14 +391,14 @@ def main():
 
     # populations read + written once: 18 doubles, or the 76-byte FP32 state
     bytes_per_cell = 288 if prec == D.FP64 else 152
-    fused = sim.kernel_kind == D.KERNEL_FUSED
+    fused = sim.kernel_kind in (D.KERNEL_FUSED, D.KERNEL_FUSED_FMA)
     # the dominant kernel's own launch time: HIP events around the tile
     # kernel on the handle's stream, over a second pass of the same steps
     kms, klaunch = sim.time_kernel(args.steps) if fused else (0.0, 0)
     kernel_ms = kms / klaunch if klaunch else ms_per_step
     achieved = bytes_per_cell * cells / (kernel_ms / 1e3) / 1e9
     traffic = None
-    if (fused and prec == D.FP64 and args.workload == TRAFFIC["workload"]
+    if (sim.kernel_kind == D.KERNEL_FUSED and prec == D.FP64 and args.workload == TRAFFIC["workload"]
             and sim.tile == TRAFFIC["tile"] and kernel_src_sha() == TRAFFIC["src_sha"]):
         traffic = TRAFFIC["bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -323,8 +409,10 @@ def main():
             "timed_launches": klaunch,
             "algorithmic_bytes_per_cell": bytes_per_cell,
             "step_effective_gbs": round(bytes_per_cell * cells / (ms_per_step / 1e3) / 1e9, 1),
+            "step_frac": round(bytes_per_cell * cells / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "launches_per_step": 2 if fused else 7}
-    if (VALU["fp64_flop_per_cell"] and fused and prec == D.FP64 and sim.tile == TRAFFIC["tile"]
+    if (VALU["fp64_flop_per_cell"] and sim.kernel_kind == D.KERNEL_FUSED and prec == D.FP64
+            and sim.tile == TRAFFIC["tile"]
             and args.workload == VALU["workload"] and kernel_src_sha() == VALU["src_sha"]):
         tf = VALU["fp64_flop_per_cell"] * cells / (kernel_ms / 1e3) / 1e12
         roof_alu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VEC_PEAK_TF,
@@ -350,7 +438,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s %s (%dx%d cells, %s)" % (
             case.name, args.precision, case.nx, case.ny, describe(args.workload)), "cells": cells,
-            "kernel": args.kernel, "recon": args.recon,
+            "kernel": ["auto", "staged", "fused", "fused_fma"][sim.kernel_kind], "recon": args.recon,
             "tile": ["auto", "14x14", "30x6", "6x30", "12x12 two-ring"][sim.tile], "dt": sim.dt},
         "roofline": roof,
         "roofline_alu": roof_alu,
@@ -360,6 +448,10 @@ def main():
                         "front_y": None if obs[6] != obs[6] else float(obs[6]),
                         "tip_y": None if obs[7] != obs[7] else float(obs[7])},
     }
+    if not args.no_fma and sim.kernel_kind == D.KERNEL_FUSED:
+        out["fma"] = fma_leg(case, prec, args.steps, args.warmup)
+    if args.large_nx:
+        out["out_of_mall"] = large_grid(args.large_nx, prec, 20, 20)
     if args.recon == "central" and not args.no_upwind:
         out["upwind"] = upwind_rate(case, args.steps, prec)
     if not args.no_batched:

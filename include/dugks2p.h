@@ -46,7 +46,19 @@ enum {
 enum { DUGKS2P_BC_PERIODIC = 0, DUGKS2P_BC_WALL = 1 };
 enum { DUGKS2P_FP64 = 0, DUGKS2P_FP32_STATE = 1 };
 enum { DUGKS2P_RECON_CENTRAL = 0, DUGKS2P_RECON_UPWIND = 1 };
-enum { DUGKS2P_KERNEL_AUTO = 0, DUGKS2P_KERNEL_STAGED = 1, DUGKS2P_KERNEL_FUSED = 2 };
+/* Implementation of the step.  AUTO = FUSED.  STAGED: one kernel per stage
+ * (FP64 only).  FUSED: cell macros plus one tile kernel, FP64 arithmetic in
+ * the oracle's order without FMA contraction (bit-identical results).
+ * FUSED_FMA: the same kernels compiled with FMA contraction: a multiply and
+ * the add that consumes it may round once, so results differ from the exact
+ * form in the last bits and stay within the FP64 parity bar (1e-11 relative
+ * max-norm after 1000 steps of the stationary drop); fewer instructions. */
+enum {
+  DUGKS2P_KERNEL_AUTO = 0,
+  DUGKS2P_KERNEL_STAGED = 1,
+  DUGKS2P_KERNEL_FUSED = 2,
+  DUGKS2P_KERNEL_FUSED_FMA = 3
+};
 /* Tile shape of the fused kernel: cells per tile (x by y).  AUTO times the
  * shapes on the problem at creation and keeps the fastest.  The wide and
  * tall shapes apply at unit lattice speed (RT = 1/3); otherwise square. */
@@ -89,7 +101,8 @@ enum {
  *   recon:       face reconstruction of Step 3: CENTRAL = linear
  *                interpolation of value and gradient (the paper's choice);
  *                UPWIND = expansion from the upwind cell.
- *   kernel:      DUGKS2P_KERNEL_* implementation choice (AUTO = fused).
+ *   kernel:      DUGKS2P_KERNEL_* implementation choice (AUTO = fused;
+ *                the batched form always runs FUSED).
  *   tile:        DUGKS2P_TILE_* tile shape of the fused kernel (a
  *                performance choice: every shape gives the same results
  *                bit for bit).

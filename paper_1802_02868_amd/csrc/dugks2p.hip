@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "dugks2p_adjoint.hpp"
+#include "dugks2p_fma.h"
 #include "dugks2p_fused.hpp"
 #include "dugks2p_host.hpp"
 
@@ -82,9 +83,9 @@ struct GpuEx {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess && err == hipSuccess) err = e;
   }
-  void macros(const Consts &K, const Work &w) {
+  void macros(const Consts &K, const Work &w, bool fields) {
     const int gx = (K.nx + MBX - 1) / MBX, nb = gx * ((K.ny + MBY - 1) / MBY);
-    hipLaunchKernelGGL(k_macros, dim3(nb), dim3(MBX, MBY), 0, s, K, w, gx, nb);
+    hipLaunchKernelGGL(k_macros, dim3(nb), dim3(MBX, MBY), 0, s, K, w, gx, nb, fields ? 1 : 0);
     note(hipGetLastError());
   }
   void macros_tape(const Consts &K, const Work &w, const Work &t) {
@@ -354,6 +355,10 @@ namespace {
 // Both reconstructions run on the fused tile kernel (UPWIND with the
 // two-ring tiles) unless the staged kernels are asked for.
 bool use_staged(const dugks2p_params *P) { return P->kernel == DUGKS2P_KERNEL_STAGED; }
+// the fused forms (exact and FMA-contracted) share the tile kernel's host logic
+bool is_fused(int kernel) {
+  return kernel == DUGKS2P_KERNEL_FUSED || kernel == DUGKS2P_KERNEL_FUSED_FMA;
+}
 
 struct Prepared {
   AxisHost ax, ay;
@@ -383,7 +388,28 @@ using SqOrUpw = typename std::conditional<S::RG == 2, TileUpw, TileSq>::type;
 // `shape` (fused form), without committing it.
 int enqueue_step(dugks2p *h, int shape) {
   GpuEx ex{h->stream, hipSuccess, &h->kt};
-  if (h->precision == DUGKS2P_FP64 && h->kernel == DUGKS2P_KERNEL_STAGED) {
+  if (h->kernel == DUGKS2P_KERNEL_FUSED_FMA) {
+    // the FMA-contracted build of the same step (dugks2p_fma.hip)
+    const bool f32 = h->precision != DUGKS2P_FP64;
+    const IoF64 s64 = io_f64(h->state[h->cur], h->K), d64 = io_f64(h->state[1 - h->cur], h->K);
+    const IoE32 s32 = io_e32(h->state[h->cur], h->K, h->L);
+    const IoE32 d32 = io_e32(h->state[1 - h->cur], h->K, h->L);
+    FmaStepArgs a;
+    a.K = &h->K;
+    a.K_bytes = sizeof h->K;
+    a.w = &h->w;
+    a.w_bytes = sizeof h->w;
+    a.fp32 = f32 ? 1 : 0;
+    a.src = f32 ? (const void *)&s32 : (const void *)&s64;
+    a.dst = f32 ? (const void *)&d32 : (const void *)&d64;
+    a.io_bytes = f32 ? sizeof s32 : sizeof s64;
+    a.sums_ready = h->sums_ok ? 1 : 0;
+    a.shape = shape;
+    a.stream = h->stream;
+    a.e0 = a.e1 = nullptr;
+    if (h->kt.on) ex.note(h->kt.pair(a.e0, a.e1));
+    ex.note(dugks2p_fma_step(&a));
+  } else if (h->precision == DUGKS2P_FP64 && h->kernel == DUGKS2P_KERNEL_STAGED) {
     ex.xcd = 0;
     seq_staged_step<GpuEx, double, double>(ex, h->K, h->w, (const double *)h->state[h->cur],
                                            (double *)h->state[1 - h->cur]);
@@ -412,7 +438,7 @@ int enqueue_step(dugks2p *h, int shape) {
   if (ex.err != hipSuccess)
     return fail(DUGKS2P_EHIP, std::string("kernel launch: ") + hipGetErrorString(ex.err));
   // a fused step leaves the sums of state[cur] in w (computed or kept)
-  if (h->kernel == DUGKS2P_KERNEL_FUSED) h->sums_ok = true;
+  if (is_fused(h->kernel)) h->sums_ok = true;
   return DUGKS2P_OK;
 }
 
@@ -423,7 +449,7 @@ int launch_step(dugks2p *h) {
   h->cur = 1 - h->cur;
   h->nstep++;
   // the tile kernel wrote the new state's sums into the spare planes
-  if (h->kernel == DUGKS2P_KERNEL_FUSED) swap_sums(h->w);
+  if (is_fused(h->kernel)) swap_sums(h->w);
   else h->sums_ok = false;
   return DUGKS2P_OK;
 }
@@ -434,8 +460,8 @@ int launch_step(dugks2p *h) {
 // shape, only the speed does.
 int tune_tile(dugks2p *h) {
   const bool upw = h->K.recon != DUGKS2P_RECON_CENTRAL;
-  if (h->kernel != DUGKS2P_KERNEL_FUSED || !h->K.unit || upw) {
-    h->tile = h->kernel == DUGKS2P_KERNEL_FUSED && upw ? DUGKS2P_TILE_UPWIND : DUGKS2P_TILE_SQUARE;
+  if (!is_fused(h->kernel) || !h->K.unit || upw) {
+    h->tile = is_fused(h->kernel) && upw ? DUGKS2P_TILE_UPWIND : DUGKS2P_TILE_SQUARE;
     return DUGKS2P_OK;
   }
   enum { WARM = 1, REPS = 3 };
@@ -525,11 +551,13 @@ int dugks2p_create(const dugks2p_params *P, const double *phi0, const double *ux
   h->L = pr.L;
   h->stream = (hipStream_t)hip_stream;
   h->precision = P->precision;
-  h->kernel = use_staged(P) ? DUGKS2P_KERNEL_STAGED : DUGKS2P_KERNEL_FUSED;
-  if (h->kernel == DUGKS2P_KERNEL_FUSED && P->recon != DUGKS2P_RECON_CENTRAL)
+  h->kernel = use_staged(P) ? DUGKS2P_KERNEL_STAGED
+                            : (P->kernel == DUGKS2P_KERNEL_FUSED_FMA ? DUGKS2P_KERNEL_FUSED_FMA
+                                                                     : DUGKS2P_KERNEL_FUSED);
+  if (is_fused(h->kernel) && P->recon != DUGKS2P_RECON_CENTRAL)
     h->tile = DUGKS2P_TILE_UPWIND;
   else
-    h->tile = (h->kernel == DUGKS2P_KERNEL_FUSED && pr.K.unit && P->tile != DUGKS2P_TILE_AUTO)
+    h->tile = (is_fused(h->kernel) && pr.K.unit && P->tile != DUGKS2P_TILE_AUTO)
                   ? P->tile
                   : DUGKS2P_TILE_SQUARE;
   h->cur = 0;

@@ -18,7 +18,7 @@
 #include "dugks2p_fused.hpp"
 #include "dugks2p_host.hpp"
 
-namespace dg {
+namespace DUGKS2P_NS {
 
 // ---------------------------------------------------------------------------
 // Pointwise adjoints.
@@ -1218,4 +1218,4 @@ void seq_adjoint_initial(Ex &ex, const Consts &K, const AdjBufs &B, const double
   seq_adjoint_init(ex, K, w, a, phi0_grad);
 }
 
-}  // namespace dg
+}  // namespace DUGKS2P_NS

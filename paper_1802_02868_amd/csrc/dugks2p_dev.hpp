@@ -17,7 +17,16 @@
 #define DFN inline
 #endif
 
-namespace dg {
+// The step's code lives in namespace dg.  The FMA-contracted build of the
+// fused step (dugks2p_fma.hip, a translation unit compiled with
+// -ffp-contract=fast) defines DUGKS2P_NS as dg_fma before including these
+// headers, so that its copies of the same templates and kernels coexist
+// with the exact ones in one library.
+#ifndef DUGKS2P_NS
+#define DUGKS2P_NS dg
+#endif
+
+namespace DUGKS2P_NS {
 
 typedef long long i64;
 
@@ -809,4 +818,4 @@ DFN void monitor_terms(const Consts &K, const Work &w, const IO &io, int i, int 
   out[4] = bad;
 }
 
-}  // namespace dg
+}  // namespace DUGKS2P_NS

@@ -31,7 +31,7 @@
 #include <stdlib.h>
 #endif
 
-namespace dg {
+namespace DUGKS2P_NS {
 
 enum { NTHR = 256 };  // threads of a tile workgroup
 
@@ -92,25 +92,43 @@ struct CellMac {
   double rho, dmux, dmuy, dphx, dphy;  // the intermediates, for the adjoint's tape
 };
 
+// F = -phi grad mu + F_b and eq. u at a cell from mu at the cell and its
+// neighbours, phi, rho and the f~ sums jx, jy (the part of the cell macros
+// that the tile kernel recomputes on its bar+ window).
+struct CellFU {
+  double dmux, dmuy, Fx, Fy, ux, uy;
+};
+DFN CellFU force_velocity(const Consts &K, double mc, double mxl, double mxh, double myl,
+                          double myh, double ph, double rh, double jx, double jy,
+                          const double *a1, const double *b1) {
+  CellFU r;
+  r.dmux = a1[0] * mxl + a1[1] * mc + a1[2] * mxh;
+  r.dmuy = b1[0] * myl + b1[1] * mc + b1[2] * myh;
+  r.Fx = -ph * r.dmux + (rh - K.rho_ref) * K.gx;
+  r.Fy = -ph * r.dmuy + (rh - K.rho_ref) * K.gy;
+  const double icr = 1.0 / (K.cs2 * rh);
+  r.ux = (jx + K.hdtcs2 * r.Fx) * icr;
+  r.uy = (jy + K.hdtcs2 * r.Fy) * icr;
+  return r;
+}
+
 DFN CellMac macros_from(const Consts &K, double mc, double mxl, double mxh, double myl,
                         double myh, double ph, double pxl, double pxh, double pyl, double pyh,
                         double s0, double jx, double jy, const double *a1, const double *a2,
                         const double *b1, const double *b2) {
   CellMac r;
-  const double dmux = a1[0] * mxl + a1[1] * mc + a1[2] * mxh;
-  const double dmuy = b1[0] * myl + b1[1] * mc + b1[2] * myh;
   const double lapmu =
       (a2[0] * mxl + a2[1] * mc + a2[2] * mxh) + (b2[0] * myl + b2[1] * mc + b2[2] * myh);
   r.D = K.mobility * lapmu;
   const double rh = rho_of<double>(K, ph);
   r.rho = rh;
-  r.dmux = dmux;
-  r.dmuy = dmuy;
-  r.Fx = -ph * dmux + (rh - K.rho_ref) * K.gx;
-  r.Fy = -ph * dmuy + (rh - K.rho_ref) * K.gy;
-  const double icr = 1.0 / (K.cs2 * rh);
-  r.ux = (jx + K.hdtcs2 * r.Fx) * icr;
-  r.uy = (jy + K.hdtcs2 * r.Fy) * icr;
+  const CellFU fu = force_velocity(K, mc, mxl, mxh, myl, myh, ph, rh, jx, jy, a1, b1);
+  r.dmux = fu.dmux;
+  r.dmuy = fu.dmuy;
+  r.Fx = fu.Fx;
+  r.Fy = fu.Fy;
+  r.ux = fu.ux;
+  r.uy = fu.uy;
   r.dphx = a1[0] * pxl + a1[1] * ph + a1[2] * pxh;
   r.dphy = b1[0] * pyl + b1[1] * ph + b1[2] * pyh;
   const double grx = K.drho * r.dphx;
@@ -168,6 +186,10 @@ struct MacBlock {
   // phi and rho included, goes to *tape instead of w (phi and the sums are
   // still read from w)
   const Work *tape = nullptr;
+  // false (the step): only mu, D and p are written; the tile kernel
+  // recomputes F and u of its bar+ window itself.  true: every field
+  // (moments, monitors, observables).
+  bool fields = true;
   // global index of window offset g along an axis, or -1 outside a wall domain
   DFN int gcol(int g, int n, int bc) const {
     if (bc == 0) return wrapi(g, n);
@@ -210,10 +232,12 @@ struct MacBlock {
     }
     o.mu[c] = mc;
     o.D[c] = m.D;
-    o.Fx[c] = m.Fx;
-    o.Fy[c] = m.Fy;
-    o.ux[c] = m.ux;
-    o.uy[c] = m.uy;
+    if (fields || tape) {
+      o.Fx[c] = m.Fx;
+      o.Fy[c] = m.Fy;
+      o.ux[c] = m.ux;
+      o.uy[c] = m.uy;
+    }
     o.p[c] = m.p;
   }
 };
@@ -221,10 +245,11 @@ struct MacBlock {
 #if defined(__HIPCC__)
 // one-dimensional grid of nb blocks, gx per block row, in the XCD-aware
 // order of xcd_tile (an XCD takes a band of rows)
-__global__ __launch_bounds__(MBX * MBY) void k_macros(Consts K, Work w, int gx, int nb) {
+__global__ __launch_bounds__(MBX * MBY) void k_macros(Consts K, Work w, int gx, int nb,
+                                                      int fields) {
   __shared__ MacLds L;
   const int b = xcd_tile(blockIdx.x, nb);
-  const MacBlock mb{K, w, (b % gx) * MBX, (b / gx) * MBY, &L};
+  const MacBlock mb{K, w, (b % gx) * MBX, (b / gx) * MBY, &L, nullptr, fields != 0};
   const int tid = threadIdx.y * MBX + threadIdx.x;
   mb.p0(tid);
   __syncthreads();
@@ -268,6 +293,13 @@ struct TileLds {
   // dt / |V| factors of the tile's columns and rows
   double rdt[2][S::FM];
 };
+
+// Two tile workgroups share a CU (160 KiB of LDS): a tile's LDS must stay
+// within half of it, or occupancy halves.
+static_assert(sizeof(TileLds<TileSq>) <= 80 * 1024, "square tile LDS above 80 KiB");
+static_assert(sizeof(TileLds<TileWide>) <= 80 * 1024, "wide tile LDS above 80 KiB");
+static_assert(sizeof(TileLds<TileTall>) <= 80 * 1024, "tall tile LDS above 80 KiB");
+static_assert(sizeof(TileLds<TileUpw>) <= 80 * 1024, "two-ring tile LDS above 80 KiB");
 
 // Accessor of the face code over the tile's LDS (bar+, phi, mu, p) and the
 // global D.  Global cell (x, y) maps to the tile window, periodic images
@@ -394,8 +426,15 @@ struct LAcc {
   DFN double dp(int a, const H &h) const { return d1(a, h, &L->p[0][0]); }
 };
 
+// g modulo n in [0, n).  Window offsets lie within one period of the
+// domain unless the domain is narrower than a tile window, so the common
+// cases take a compare and an add; the remainder (an integer division on
+// the GPU) runs only for those narrow domains.
 DFN int wrapi(int g, int n) {
-  int r = g % n;
+  if (g >= 0 && g < n) return g;
+  if (g < 0 && g >= -n) return g + n;
+  if (g >= n && g < 2 * n) return g - n;
+  const int r = g % n;
   return r < 0 ? r + n : r;
 }
 
@@ -528,7 +567,7 @@ struct FusedTile {
   // global inputs of a window cell's Step 2, loaded ahead of P0 so that their
   // latency overlaps P0's loads
   struct Pre {
-    double tv[18], ux, uy, D, Fx, Fy;
+    double tv[18], D;
   };
 
   // global index along an axis of window offset o, or -1 outside a wall domain
@@ -549,11 +588,7 @@ struct FusedTile {
     if (gx < 0 || gy < 0) return;
     const i64 c = (i64)gy * K.ld + gx;
     src.load(c, pr.tv);
-    pr.ux = w.ux[c];
-    pr.uy = w.uy[c];
     pr.D = w.D[c];
-    pr.Fx = w.Fx[c];
-    pr.Fy = w.Fy[c];
   }
 
   // P0 (see TileP0)
@@ -573,18 +608,31 @@ struct FusedTile {
     const typename LAcc<S>::H hc = acc.cell(gx, gy);
     const double ph = acc.phi(hc);
     const double rh = rho_of<double>(K, ph);
+    // F and u of the macro kernel, recomputed from mu in LDS and the f~ sums
+    // of the loaded state (the values and the order of operations of the
+    // macro kernel, which then need not store them)
+    const double *mu = &L->mu[0][0];
+    double f[9], jx, jy;
+    {
+      double phs;
+      src.stored(pr.tv, phs, f);
+    }
+    xi_sums<double, U>(K, f, jx, jy);
+    const CellFU cm = force_velocity(K, mu[hc.o2], mu[hc.lo2[0]], mu[hc.hi2[0]], mu[hc.lo2[1]],
+                                     mu[hc.hi2[1]], ph, rh, jx, jy, L->d1w[0][hc.w2[0]],
+                                     L->d1w[1][hc.w2[1]]);
     Mac<R> m;
     m.phi = (R)ph;
     m.rho = (R)rh;
-    m.ux = (R)pr.ux;
-    m.uy = (R)pr.uy;
+    m.ux = (R)cm.ux;
+    m.uy = (R)cm.uy;
     m.p = (R)acc.p(hc);
     m.mu = (R)acc.mu(hc);
     m.grx = (R)(K.drho * acc.dphi(0, hc));
     m.gry = (R)(K.drho * acc.dphi(1, hc));
     m.D = (R)pr.D;
-    m.Fx = (R)pr.Fx;
-    m.Fy = (R)pr.Fy;
+    m.Fx = (R)cm.Fx;
+    m.Fy = (R)cm.Fy;
     L->D[ly][lx] = pr.D;
     m.gpx = (R)acc.dp(0, hc);
     m.gpy = (R)acc.dp(1, hc);
@@ -733,6 +781,7 @@ struct FusedTile {
 
 template <class S>
 DFN int tiles_x(const Consts &K) { return (K.nx + S::TX - 1) / S::TX; }
+
 template <class S>
 DFN int tiles_y(const Consts &K) { return (K.ny + S::TY - 1) / S::TY; }
 
@@ -763,7 +812,7 @@ template <class Ex, class IO, class R, bool U, class S = TileSq>
 void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const IO &src, const IO &dst,
                     bool sums_ready = false) {
   if (!sums_ready) ex.grid(FPhiSums<IO, U>{K, w, src}, K.nx, K.ny);
-  ex.macros(K, w);
+  ex.macros(K, w, false);
   ex.template tiles<IO, R, U, S>(K, w, src, dst);
 }
 
@@ -798,7 +847,7 @@ void with_tile_shape(int shape, bool unit, F &&f) {
 template <class Ex, class IO>
 void seq_moments(Ex &ex, const Consts &K, const Work &w, const IO &src) {
   ex.grid(FPhiSums<IO, false>{K, w, src}, K.nx, K.ny);
-  ex.macros(K, w);
+  ex.macros(K, w, true);
 }
 
-}  // namespace dg
+}  // namespace DUGKS2P_NS

@@ -15,7 +15,7 @@
 #include "../../include/dugks2p.h"
 #include "dugks2p_dev.hpp"
 
-namespace dg {
+namespace DUGKS2P_NS {
 
 // Tables of one axis in host memory (see struct Axis).
 struct AxisHost {
@@ -142,7 +142,7 @@ inline std::string validate(const dugks2p_params *P) {
     return "precision must be DUGKS2P_FP64 or DUGKS2P_FP32_STATE";
   if (P->recon != DUGKS2P_RECON_CENTRAL && P->recon != DUGKS2P_RECON_UPWIND)
     return "recon must be DUGKS2P_RECON_CENTRAL or DUGKS2P_RECON_UPWIND";
-  if (P->kernel < DUGKS2P_KERNEL_AUTO || P->kernel > DUGKS2P_KERNEL_FUSED)
+  if (P->kernel < DUGKS2P_KERNEL_AUTO || P->kernel > DUGKS2P_KERNEL_FUSED_FMA)
     return "kernel must be a DUGKS2P_KERNEL_* value";
   if (P->tile < DUGKS2P_TILE_AUTO || P->tile > DUGKS2P_TILE_TALL)
     return "tile must be a DUGKS2P_TILE_* value";
@@ -426,4 +426,4 @@ void seq_staged_step(Ex &ex, const Consts &K, const Work &w, const T *src, T *ds
   ex.grid(FUpdate<T, R>{K, w, src, dst}, K.nx, K.ny);
 }
 
-}  // namespace dg
+}  // namespace DUGKS2P_NS

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libdugks2p.so")
 
 from .dugks2p_params import (ABI_VERSION, BC_PERIODIC, BC_WALL, EHIP, EINVAL,  # noqa: F401
                              ENOMEM, ENONFINITE, EUNSUPPORTED, FP32_STATE, FP64,
-                             KERNEL_AUTO, KERNEL_FUSED, KERNEL_STAGED, OK, RECON_CENTRAL,
+                             KERNEL_AUTO, KERNEL_FUSED, KERNEL_FUSED_FMA, KERNEL_STAGED, OK,
+                             RECON_CENTRAL,
                              RECON_UPWIND, TILE_AUTO, TILE_SQUARE, TILE_TALL, TILE_UPWIND,
                              TILE_WIDE,
                              Params, make_params)

@@ -10,7 +10,7 @@ OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_WALL = 0, 1
 FP64, FP32_STATE = 0, 1
 RECON_CENTRAL, RECON_UPWIND = 0, 1
-KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED = 0, 1, 2
+KERNEL_AUTO, KERNEL_STAGED, KERNEL_FUSED, KERNEL_FUSED_FMA = 0, 1, 2, 3
 TILE_AUTO, TILE_SQUARE, TILE_WIDE, TILE_TALL, TILE_UPWIND = 0, 1, 2, 3, 4
 ABI_VERSION = 1
 

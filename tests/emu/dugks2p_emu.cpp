@@ -27,17 +27,17 @@ struct CpuEx {
   // Every workgroup of the tile kernel in turn; each phase runs for all 256
   // threads before the next (the barrier between phases).
   // every 64 x 4 block of the macro kernel in turn, phase by phase
-  void macros(const Consts &K, const Work &w, const Work *tape = nullptr) {
+  void macros(const Consts &K, const Work &w, bool fields, const Work *tape = nullptr) {
     std::vector<MacLds> L(1);
     for (int by = 0; by < (K.ny + MBY - 1) / MBY; ++by)
       for (int bx = 0; bx < (K.nx + MBX - 1) / MBX; ++bx) {
         memset((void *)L.data(), 0xff, sizeof(MacLds));  // NaN poison
-        const MacBlock mb{K, w, bx * MBX, by * MBY, L.data(), tape};
+        const MacBlock mb{K, w, bx * MBX, by * MBY, L.data(), tape, fields};
         for (int t = 0; t < MBX * MBY; ++t) mb.p0(t);
         for (int t = 0; t < MBX * MBY; ++t) mb.p1(t);
       }
   }
-  void macros_tape(const Consts &K, const Work &w, const Work &t) { macros(K, w, &t); }
+  void macros_tape(const Consts &K, const Work &w, const Work &t) { macros(K, w, true, &t); }
   // the adjoint's face stage: every workgroup in turn, phase by phase
   void adj_faces(const Consts &K, const Work &w, const AdjWork &a) {
     using S = TileSq;
