@@ -19,12 +19,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 
-# HBM bytes per launch of the fused FP64 step kernel on the Rayleigh-Taylor
-# 256 x 1024 workload, from FETCH_SIZE / WRITE_SIZE counters scaled by a
-# plain copy (profiles/fused_rt256x1024_fp64_traffic.md).  Valid only while
-# the kernel sources hash to the measured version.
-TRAFFIC = {"workload": "rt256x1024", "precision": "fp64", "tile": 1, "src_sha": "abcf4fa157686e4d",
-           "bytes_per_launch": 104.28e6}
+# HBM bytes per launch of the fused FP64 step kernel (square tiles), from
+# FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy
+# (profiles/fused_rt256x1024_fp64_traffic.md), for the exact and the
+# FMA-contracted builds on the headline grid and on the out-of-MALL grid.
+# Valid only while the kernel sources hash to the measured version.
+TRAFFIC = {"precision": "fp64", "tile": 1, "src_sha": "7d82dff3f8eeb17f",
+           "rt256x1024": {"exact": 95.40e6, "fma": 95.35e6},
+           "rt2048x8192": {"exact": 6554.07e6, "fma": 6554.24e6}}
 
 FP64_VEC_PEAK_TF = 78.6    # MI355X FP64 vector
 FP32_VEC_PEAK_TF = 157.3
@@ -34,7 +36,15 @@ FP32_VEC_PEAK_TF = 157.3
 # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters on the same workload
 # (profiles/fused_rt256x1024_fp64_valu.md); valid for the same sources.
 VALU = {"workload": "rt256x1024", "precision": "fp64", "src_sha": TRAFFIC["src_sha"],
-        "fp64_flop_per_cell": 2755.0}
+        "fp64_flop_per_cell": 2799.9, "fma_fp64_flop_per_cell": 2940.0}
+
+
+def traffic_for(workload, build, prec, tile):
+    """Counter bytes per launch of the tile kernel, or None when the sources,
+    the precision or the tile shape differ from the profiled ones."""
+    if prec != "fp64" or tile != TRAFFIC["tile"] or kernel_src_sha() != TRAFFIC["src_sha"]:
+        return None
+    return TRAFFIC.get(workload, {}).get(build)
 FP64_NOFMA_PEAK_TF = FP64_VEC_PEAK_TF / 2  # one add or multiply per instruction
 
 
@@ -199,7 +209,7 @@ def upwind_rate(case, steps, prec):
     return out
 
 
-def kernel_rate(case, prec, kern, steps, warmup):
+def kernel_rate(case, prec, kern, steps, warmup, workload=None):
     """MLUPS of `steps` steps (events on the handle's stream) and the tile
     kernel's mean launch time (events the launches set), after `warmup`."""
     import torch
@@ -220,21 +230,23 @@ def kernel_rate(case, prec, kern, steps, warmup):
     sim.close()
     cells = case.nx * case.ny
     bpc = 288 if prec == D.FP64 else 152
+    build = "fma" if kern == D.KERNEL_FUSED_FMA else "exact"
     return {"mlups": round(cells / ms / 1e3, 1), "ms_per_step": round(ms, 5),
             "tile_us": round(tile_us, 2),
             "frac": round(bpc * cells / (tile_us / 1e6) / 1e9 / HBM_PEAK_GBS, 4),
             "step_frac": round(bpc * cells / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(workload, build, "fp64" if prec == D.FP64 else "fp32", tile),
             "tile": ["auto", "14x14", "30x6", "6x30", "12x12 two-ring"][tile],
             "nonfinite": bad}
 
 
-def fma_leg(case, prec, steps, warmup):
+def fma_leg(case, prec, steps, warmup, workload):
     """The FMA-contracted fused step (DUGKS2P_KERNEL_FUSED_FMA) on the same
     workload, and the largest population deviation from the exact kernel
     after the same number of steps."""
     import torch
     from paper_1802_02868_amd import dugks2p as D
-    out = kernel_rate(case, prec, D.KERNEL_FUSED_FMA, steps, warmup)
+    out = kernel_rate(case, prec, D.KERNEL_FUSED_FMA, steps, warmup, workload)
     a = D.Simulation.from_case(case, precision=prec, kernel=D.KERNEL_FUSED)
     b = D.Simulation.from_case(case, precision=prec, kernel=D.KERNEL_FUSED_FMA)
     a.step(200)
@@ -258,8 +270,9 @@ def large_grid(nx, prec, steps, warmup):
     bpc = 288 if prec == D.FP64 else 152
     out = {"workload": "%s (%dx%d cells, %.1f GB ping-pong state)" % (
         case.name, case.nx, case.ny, 2 * bpc / 2 * case.nx * case.ny / 1e9)}
-    out["exact"] = kernel_rate(case, prec, D.KERNEL_FUSED, steps, warmup)
-    out["fma"] = kernel_rate(case, prec, D.KERNEL_FUSED_FMA, steps, warmup)
+    wl = "rt%dx%d" % (case.nx, case.ny)
+    out["exact"] = kernel_rate(case, prec, D.KERNEL_FUSED, steps, warmup, wl)
+    out["fma"] = kernel_rate(case, prec, D.KERNEL_FUSED_FMA, steps, warmup, wl)
     return out
 
 
@@ -397,10 +410,9 @@ def main():
     kms, klaunch = sim.time_kernel(args.steps) if fused else (0.0, 0)
     kernel_ms = kms / klaunch if klaunch else ms_per_step
     achieved = bytes_per_cell * cells / (kernel_ms / 1e3) / 1e9
-    traffic = None
-    if (sim.kernel_kind == D.KERNEL_FUSED and prec == D.FP64 and args.workload == TRAFFIC["workload"]
-            and sim.tile == TRAFFIC["tile"] and kernel_src_sha() == TRAFFIC["src_sha"]):
-        traffic = TRAFFIC["bytes_per_launch"]
+    traffic = traffic_for(args.workload,
+                          "fma" if sim.kernel_kind == D.KERNEL_FUSED_FMA else "exact",
+                          args.precision, sim.tile) if fused else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "traffic_unit": "bytes per launch (HBM, counters)",
@@ -449,7 +461,7 @@ def main():
                         "tip_y": None if obs[7] != obs[7] else float(obs[7])},
     }
     if not args.no_fma and sim.kernel_kind == D.KERNEL_FUSED:
-        out["fma"] = fma_leg(case, prec, args.steps, args.warmup)
+        out["fma"] = fma_leg(case, prec, args.steps, args.warmup, args.workload)
     if args.large_nx:
         out["out_of_mall"] = large_grid(args.large_nx, prec, 20, 20)
     if args.recon == "central" and not args.no_upwind:
