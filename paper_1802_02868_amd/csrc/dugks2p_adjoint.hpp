@@ -18,6 +18,15 @@
 #include "dugks2p_fused.hpp"
 #include "dugks2p_host.hpp"
 
+// The reverse arithmetic below (the vector-Jacobian products) may fuse a
+// multiply with the add that consumes it: the derivative is not held to bit
+// identity, only to rounding (its tests bound it against central
+// differences and complex-step derivatives of the oracle).  The forward
+// functions it calls keep the exact evaluation of their own definitions.
+#if defined(__clang__)
+#pragma clang fp contract(fast)
+#endif
+
 namespace DUGKS2P_NS {
 
 // ---------------------------------------------------------------------------
@@ -1219,3 +1228,7 @@ void seq_adjoint_initial(Ex &ex, const Consts &K, const AdjBufs &B, const double
 }
 
 }  // namespace DUGKS2P_NS
+
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
