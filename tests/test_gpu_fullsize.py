@@ -36,6 +36,34 @@ def test_rt256x1024_fp64_bitwise(D, oracle_mod):
     assert np.array_equal(s.populations().cpu().numpy(), o.pops())
 
 
+def test_rt2048x8192_out_of_mall_parity(D, oracle_mod):
+    """The out-of-MALL grid that bench.py times (RT 2048 x 8192, 16.8 M
+    cells, square tiles; 64-bit offsets beyond 2^31 bytes in every plane
+    loop): after 3 steps the exact kernel equals the oracle bit for bit and
+    the FMA-contracted build stays within the FP64 bar."""
+    import torch
+    case = W.rt_case(2048)
+    case.params["tile"] = D.TILE_SQUARE
+    steps = 3
+    print("out-of-MALL", case.name, steps, flush=True)
+    o = oracle_mod.Oracle.from_case(case)
+    o.step(steps)
+    ref = o.pops()
+    o.close()
+    for kern in (D.KERNEL_FUSED, D.KERNEL_FUSED_FMA):
+        s = D.Simulation.from_case(case, precision=D.FP64, kernel=kern)
+        s.step(steps)
+        got = s.populations().cpu().numpy()
+        s.close()
+        torch.cuda.empty_cache()
+        if kern == D.KERNEL_FUSED:
+            assert np.array_equal(got, ref)
+        else:
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            print("  fma relmax %.3e" % err, flush=True)
+            assert err <= 1e-11
+
+
 def test_rt256x1024_upwind_fp64_bitwise(D, oracle_mod):
     """UPWIND reconstruction at the full headline size, on the fused kernel's
     two-ring tiles as bench.py's UPWIND leg runs it: the oracle's populations
