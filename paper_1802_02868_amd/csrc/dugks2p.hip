@@ -93,17 +93,17 @@ struct GpuEx {
     hipLaunchKernelGGL(k_macros_tape, dim3(nb), dim3(MBX, MBY), 0, s, K, w, t, gx, nb);
     note(hipGetLastError());
   }
-  template <class IO, class R, bool U, class S>
+  template <class IO, class R, bool U, class S, int V>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (kt && kt->on) note(kt->pair(e0, e1));
     if (e0)
-      hipExtLaunchKernelGGL((k_fused_tile<IO, R, U, S>), dim3(nt), dim3(NTHR), 0, s, e0, e1, 0, K,
-                            w, src, dst, ntx, nt);
+      hipExtLaunchKernelGGL((k_fused_tile<IO, R, U, S, V>), dim3(nt), dim3(NTHR), 0, s, e0, e1, 0,
+                            K, w, src, dst, ntx, nt);
     else
-      hipLaunchKernelGGL((k_fused_tile<IO, R, U, S>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst,
-                         ntx, nt);
+      hipLaunchKernelGGL((k_fused_tile<IO, R, U, S, V>), dim3(nt), dim3(NTHR), 0, s, K, w, src,
+                         dst, ntx, nt);
     note(hipGetLastError());
   }
   // the adjoint's face stage over square tiles
@@ -379,14 +379,13 @@ std::string prepare(const dugks2p_params *P, Prepared &pr) {
   return std::string();
 }
 
-// Non-unit lattice speeds instantiate square tiles only, plus the two-ring
-// tiles of UPWIND reconstruction.
-template <class S>
-using SqOrUpw = typename std::conditional<S::RG == 2, TileUpw, TileSq>::type;
-
 // Enqueue one time step from state[cur] into state[1 - cur] with tile shape
 // `shape` (fused form), without committing it.
 int enqueue_step(dugks2p *h, int shape) {
+  // the tile code takes interior-face reconstruction from the tile shape
+  if (is_fused(h->kernel) &&
+      (shape == DUGKS2P_TILE_UPWIND) != (h->K.recon != DUGKS2P_RECON_CENTRAL))
+    return fail(DUGKS2P_EINVAL, "tile shape does not match the face reconstruction");
   GpuEx ex{h->stream, hipSuccess, &h->kt};
   if (h->kernel == DUGKS2P_KERNEL_FUSED_FMA) {
     // the FMA-contracted build of the same step (dugks2p_fma.hip)
@@ -415,24 +414,16 @@ int enqueue_step(dugks2p *h, int shape) {
                                            (double *)h->state[1 - h->cur]);
   } else if (h->precision == DUGKS2P_FP64) {
     const IoF64 src = io_f64(h->state[h->cur], h->K), dst = io_f64(h->state[1 - h->cur], h->K);
-    with_tile_shape(shape, h->K.unit, [&](auto sh) {
-      using S = decltype(sh);
-      if (h->K.unit)
-        seq_fused_step<GpuEx, IoF64, double, true, S>(ex, h->K, h->w, src, dst, h->sums_ok);
-      else
-        seq_fused_step<GpuEx, IoF64, double, false, SqOrUpw<S>>(ex, h->K, h->w, src, dst,
-                                                                h->sums_ok);
+    with_fused_kernel(shape, h->K, [&](auto u, auto sh, auto v) {
+      seq_fused_step<GpuEx, IoF64, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
+          ex, h->K, h->w, src, dst, h->sums_ok);
     });
   } else {
     const IoE32 src = io_e32(h->state[h->cur], h->K, h->L);
     const IoE32 dst = io_e32(h->state[1 - h->cur], h->K, h->L);
-    with_tile_shape(shape, h->K.unit, [&](auto sh) {
-      using S = decltype(sh);
-      if (h->K.unit)
-        seq_fused_step<GpuEx, IoE32, double, true, S>(ex, h->K, h->w, src, dst, h->sums_ok);
-      else
-        seq_fused_step<GpuEx, IoE32, double, false, SqOrUpw<S>>(ex, h->K, h->w, src, dst,
-                                                                h->sums_ok);
+    with_fused_kernel(shape, h->K, [&](auto u, auto sh, auto v) {
+      seq_fused_step<GpuEx, IoE32, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
+          ex, h->K, h->w, src, dst, h->sums_ok);
     });
   }
   if (ex.err != hipSuccess)

@@ -1196,10 +1196,10 @@ void seq_adjoint_segment(Ex &ex, const Consts &K, const AdjBufs &B, const double
       wt.jxn = wf.jxn;
       wt.jyn = wf.jyn;
       const IoF64 b{B.state(n + 1), K.plane};
-      if (K.unit)
-        ex.template tiles<IoF64, double, true, TileSq>(K, wt, a, b);
-      else
-        ex.template tiles<IoF64, double, false, TileSq>(K, wt, a, b);
+      with_fused_kernel(DUGKS2P_TILE_SQUARE, K, [&](auto u, auto sh, auto v) {
+        ex.template tiles<IoF64, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
+            K, wt, a, b);
+      });
       swap_sums(wf);
     }
   }

@@ -128,10 +128,16 @@ DFN R rho_of(const Consts &K, R phi) {
   return ((ph - (R)K.phi_b) * (R)K.rho_a + ((R)K.phi_a - ph) * (R)K.rho_b) * (R)K.inv_dphi;
 }
 
+// Viscosity model of the f~ relaxation time, as a kernel is compiled for it:
+// VIS_ANY reads it from Consts at run time (a given tau_f when K.tau_f > 0,
+// else the mixture viscosity); VIS_UNIFORM and VIS_MIXTURE fix one of the
+// two, and the host launches them only where K.tau_f agrees.
+enum { VIS_ANY = 0, VIS_UNIFORM = 1, VIS_MIXTURE = 2 };
+
 // eqs. kineticandmobility and mixvis: tau_f = mu_d / (rho c_s^2)
-template <class R>
+template <class R, int V = VIS_ANY>
 DFN R tauf_of(const Consts &K, R phi, R rho) {
-  if (K.tau_f > 0.0) return (R)K.tau_f;
+  if (V == VIS_UNIFORM || (V == VIS_ANY && K.tau_f > 0.0)) return (R)K.tau_f;
   R ph = phi;
   if (K.phi_clamp) ph = ph < (R)K.lo_phi ? (R)K.lo_phi : (ph > (R)K.hi_phi ? (R)K.hi_phi : ph);
   const R mud = (R)K.mumu / ((ph - (R)K.phi_b) * (R)K.mu_b + ((R)K.phi_a - ph) * (R)K.mu_a);
@@ -486,7 +492,7 @@ struct FaceFields {
   R mu, D, gmx, gmy, gfx, gfy, gpx, gpy;
 };
 
-template <class R, bool U = false>
+template <class R, bool U = false, int V = VIS_ANY>
 DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R out[18]) {
   Mac<R> m;
   R phib = (R)0.0;
@@ -514,7 +520,7 @@ DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R 
   m.uy = (jy + (R)K.hhcs2 * m.Fy) * m.icr;
   m.p = s0 + (R)K.hhcs2 * (m.ux * m.grx + m.uy * m.gry - (R)K.gam * m.rho * m.D);
   const R uu = m.ux * m.ux + m.uy * m.uy;
-  const R tf = tauf_of<R>(K, phib, m.rho);
+  const R tf = tauf_of<R, V>(K, phib, m.rho);
   const R den = (R)1.0 / ((R)2.0 * tf + (R)K.h);
   const R fk1 = (R)2.0 * tf * den, fk2 = (R)K.h * den, fk3 = tf * (R)K.h * den;
 #pragma unroll
@@ -529,8 +535,10 @@ DFN void face_dist(const Consts &K, const FaceFields<R> &fl, const R bar[18], R 
 // Steps 3-4 at face k of axis A (0: x-face between cells (k-1, t) and (k, t);
 // 1: y-face between (t, k-1) and (t, k)).  Acc provides bar+ (A), the cell
 // fields mu, D, phi, p and their derivatives dmu, dphi, dp along an axis.
-template <int A, class R, class Acc, bool U = false>
+template <int A, class R, class Acc, bool U = false, int V = VIS_ANY>
 DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
+  // reconstruction of interior faces: the accessor's own where it fixes one
+  const bool upw = Acc::RECON < 0 ? K.recon == 1 : Acc::RECON == 1;
   const FaceGeo fg = acc.geo(A, k);
   const int cl = fg.cl, cr = fg.cr;
   const R h = (R)K.h;
@@ -572,7 +580,7 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
     fl.gfy = A == 0 ? (R)tph : (R)0.0;
     fl.gpx = A == 0 ? (R)0.0 : (R)tp;
     fl.gpy = A == 0 ? (R)tp : (R)0.0;
-    face_dist<R, U>(K, fl, bar, out);
+    face_dist<R, U, V>(K, fl, bar, out);
 #pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int i = q % 9;
@@ -592,13 +600,13 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
     const int en = A == 0 ? ex_of(i) : ey_of(i);
     const R AL = (R)acc.A(q, HL), AR = (R)acc.A(q, HR);
     R val, sn, st;
-    if (K.recon == 1 && en > 0) {
+    if (upw && en > 0) {
       const R gx = (R)acc.pgrad(0, q, HL), gy = (R)acc.pgrad(1, q, HL);
       const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
       val = AL + (R)fg.offl * Gn;
       sn = Gn;
       st = Gt;
-    } else if (K.recon == 1 && en < 0) {
+    } else if (upw && en < 0) {
       const R gx = (R)acc.pgrad(0, q, HR), gy = (R)acc.pgrad(1, q, HR);
       const R Gn = A == 0 ? gx : gy, Gt = A == 0 ? gy : gx;
       val = AR + (R)fg.offr * Gn;
@@ -627,7 +635,7 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
   face_field(fw, acc.p(HL), acc.p(HR), acc.dp(TA, HL), acc.dp(TA, HR), tmp, gn, gt);
   fl.gpx = (R)(A == 0 ? gn : gt);
   fl.gpy = (R)(A == 0 ? gt : gn);
-  face_dist<R, U>(K, fl, bar, out);
+  face_dist<R, U, V>(K, fl, bar, out);
 #undef CX
 #undef CY
 }
@@ -635,6 +643,7 @@ DFN void face_core(const Consts &K, const Acc &acc, int k, int t, R out[18]) {
 // Accessor over the staged global arrays.  A cell handle is its linear
 // index and coordinates; derivatives use the App. B weights of the axis.
 struct GAcc {
+  static constexpr int RECON = -1;  // K.recon at run time
   const Consts *K;
   const Work *w;
   struct H {

@@ -49,21 +49,18 @@ struct FmaEx {
     hipLaunchKernelGGL(k_macros, dim3(nb), dim3(MBX, MBY), 0, s, K, w, gx, nb, fields ? 1 : 0);
     note(hipGetLastError());
   }
-  template <class IO, class R, bool U, class S>
+  template <class IO, class R, bool U, class S, int V>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
     if (e0)
-      hipExtLaunchKernelGGL((k_fused_tile<IO, R, U, S>), dim3(nt), dim3(NTHR), 0, s, e0, e1, 0, K,
-                            w, src, dst, ntx, nt);
+      hipExtLaunchKernelGGL((k_fused_tile<IO, R, U, S, V>), dim3(nt), dim3(NTHR), 0, s, e0, e1, 0,
+                            K, w, src, dst, ntx, nt);
     else
-      hipLaunchKernelGGL((k_fused_tile<IO, R, U, S>), dim3(nt), dim3(NTHR), 0, s, K, w, src, dst,
-                         ntx, nt);
+      hipLaunchKernelGGL((k_fused_tile<IO, R, U, S, V>), dim3(nt), dim3(NTHR), 0, s, K, w, src,
+                         dst, ntx, nt);
     note(hipGetLastError());
   }
 };
-
-template <class S>
-using SqOrUpw = typename std::conditional<S::RG == 2, TileUpw, TileSq>::type;
 
 template <class IO>
 hipError_t step(const FmaStepArgs *a) {
@@ -76,13 +73,9 @@ hipError_t step(const FmaStepArgs *a) {
   memcpy(&src, a->src, sizeof src);
   memcpy(&dst, a->dst, sizeof dst);
   FmaEx ex{a->stream, hipSuccess, a->e0, a->e1};
-  with_tile_shape(a->shape, K.unit, [&](auto sh) {
-    using S = decltype(sh);
-    if (K.unit)
-      seq_fused_step<FmaEx, IO, double, true, S>(ex, K, w, src, dst, a->sums_ready != 0);
-    else
-      seq_fused_step<FmaEx, IO, double, false, SqOrUpw<S>>(ex, K, w, src, dst,
-                                                           a->sums_ready != 0);
+  with_fused_kernel(a->shape, K, [&](auto u, auto sh, auto v) {
+    seq_fused_step<FmaEx, IO, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
+        ex, K, w, src, dst, a->sums_ready != 0);
   });
   return ex.err;
 }

@@ -18,6 +18,8 @@
 // run the phases thread by thread with the same barrier semantics.
 #pragma once
 
+#include <type_traits>
+
 #include "dugks2p_dev.hpp"
 
 // DUGKS2P_WINDOW_CHECK turns every LDS-window access of the tile code into a
@@ -308,6 +310,9 @@ static_assert(sizeof(TileLds<TileUpw>) <= 80 * 1024, "two-ring tile LDS above 80
 // its stencil neighbours, computed once per face.
 template <class S, class Lds = TileLds<S>>
 struct LAcc {
+  // interior-face reconstruction: UPWIND needs the two-cell bar+ ring, and
+  // the host runs UPWIND on the two-ring tiles only, CENTRAL on the others
+  static constexpr int RECON = S::RG == 2 ? 1 : 0;
   const Consts *K;
   const Work *w;
   const Lds *L;
@@ -550,8 +555,8 @@ struct TileP0 {
   }
 };
 
-// One tile of shape S with origin (x0, y0).
-template <class IO, class R, bool U = false, class S = TileSq>
+// One tile of shape S with origin (x0, y0); V: the viscosity model.
+template <class IO, class R, bool U = false, class S = TileSq, int V = VIS_ANY>
 struct FusedTile {
   const Consts &K;
   const Work &w;
@@ -637,7 +642,7 @@ struct FusedTile {
     m.gpx = (R)acc.dp(0, hc);
     m.gpy = (R)acc.dp(1, hc);
     m.icr = (R)1.0 / ((R)K.cs2 * m.rho);
-    const R tf = tauf_of<R>(K, (R)ph, (R)rh);
+    const R tf = tauf_of<R, V>(K, (R)ph, (R)rh);
     R til[18], out[18];
 #pragma unroll
     for (int q = 0; q < 18; ++q) til[q] = (R)pr.tv[q];
@@ -675,7 +680,7 @@ struct FusedTile {
     if (tx <= S::TX && ty < S::TY) {
       const int k = x0 + tx, t = y0 + ty;
       if (t < K.ny && k <= K.nx) {
-        face_core<0, R, LAcc<S>, U>(K, acc, (perx && k == K.nx) ? 0 : k, t, out);
+        face_core<0, R, LAcc<S>, U, V>(K, acc, (perx && k == K.nx) ? 0 : k, t, out);
 #pragma unroll
         for (int q = 0; q < 18; ++q) {
           const int s = xslot(q % 9);
@@ -687,7 +692,7 @@ struct FusedTile {
     if (tx < S::TX && ty <= S::TY) {
       const int k = y0 + ty, t = x0 + tx;
       if (t < K.nx && k <= K.ny) {
-        face_core<1, R, LAcc<S>, U>(K, acc, (pery && k == K.ny) ? 0 : k, t, out);
+        face_core<1, R, LAcc<S>, U, V>(K, acc, (pery && k == K.ny) ? 0 : k, t, out);
 #pragma unroll
         for (int q = 0; q < 18; ++q) {
           const int s = yslot(q % 9);
@@ -794,26 +799,28 @@ DFN int xcd_tile(int b, int n) {
 }
 
 #if defined(__HIPCC__)
-template <class IO, class R, bool U, class S>
-__global__ __launch_bounds__(NTHR) void k_fused_tile(Consts K, Work w, IO src, IO dst, int ntx,
-                                                     int ntiles) {
+// Two workgroups share a CU (their LDS fits), so registers are held to two
+// waves per SIMD.
+template <class IO, class R, bool U, class S, int V>
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_tile(
+    Consts K, Work w, IO src, IO dst, int ntx, int ntiles) {
   __shared__ TileLds<S> L;
   const int tile = xcd_tile(blockIdx.x, ntiles);
-  FusedTile<IO, R, U, S> ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY, &L};
+  FusedTile<IO, R, U, S, V> ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY, &L};
   ft.run(threadIdx.x);
 }
 #endif
 
-// One fused time step (Ex: grid(functor, n0, n1) and tiles<IO, R, U, S>(...)).
-// U: unit lattice speed (RT = 1/3), chosen by the host; S: tile shape.
-// sums_ready: phi and the f~ sums of src are already in w (written by the
-// previous step's tile kernel).
-template <class Ex, class IO, class R, bool U, class S = TileSq>
+// One fused time step (Ex: grid(functor, n0, n1) and tiles<IO, R, U, S, V>(...)).
+// U: unit lattice speed (RT = 1/3), S: tile shape, V: viscosity model, all
+// chosen by the host (with_fused_kernel).  sums_ready: phi and the f~ sums
+// of src are already in w (written by the previous step's tile kernel).
+template <class Ex, class IO, class R, bool U, class S = TileSq, int V = VIS_ANY>
 void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const IO &src, const IO &dst,
                     bool sums_ready = false) {
   if (!sums_ready) ex.grid(FPhiSums<IO, U>{K, w, src}, K.nx, K.ny);
   ex.macros(K, w, false);
-  ex.template tiles<IO, R, U, S>(K, w, src, dst);
+  ex.template tiles<IO, R, U, S, V>(K, w, src, dst);
 }
 
 // After a committed fused step the sums written for the new state become
@@ -840,6 +847,35 @@ void with_tile_shape(int shape, bool unit, F &&f) {
     f(TileTall{});
   else
     f(TileSq{});
+}
+
+// Calls f(u, s, v) with the compile-time choices of the single-handle tile
+// kernel for a DUGKS2P_TILE_* shape and the constants K: u the unit-speed
+// flag (std::bool_constant), s the tile shape, v the viscosity model
+// (std::integral_constant<int, VIS_*>).  At unit lattice speed every shape
+// is compiled for a given tau_f and for the mixture viscosity apart (the
+// run-time choice costs the tile kernel about a tenth of its speed); other
+// speeds take square or two-ring tiles and read the model at run time.
+// Shape 4 (the two-ring tiles) is UPWIND reconstruction and every other
+// shape CENTRAL: the caller keeps the two matched.
+template <class F>
+void with_fused_kernel(int shape, const Consts &K, F &&f) {
+  using Any = std::integral_constant<int, VIS_ANY>;
+  using Uni = std::integral_constant<int, VIS_UNIFORM>;
+  using Mix = std::integral_constant<int, VIS_MIXTURE>;
+  if (!K.unit) {
+    if (shape == 4)
+      f(std::false_type{}, TileUpw{}, Any{});
+    else
+      f(std::false_type{}, TileSq{}, Any{});
+    return;
+  }
+  with_tile_shape(shape, true, [&](auto sh) {
+    if (K.tau_f > 0.0)
+      f(std::true_type{}, sh, Uni{});
+    else
+      f(std::true_type{}, sh, Mix{});
+  });
 }
 
 // Cell fields of the current state for moments and monitors (phi, mu, D, F,

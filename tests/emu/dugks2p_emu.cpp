@@ -79,20 +79,20 @@ struct CpuEx {
       for (int t = 0; t < NTHR; ++t) ct.finish(s[t]);
     }
   }
-  template <class IO, class R, bool U, class S>
+  template <class IO, class R, bool U, class S, int V>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
+    using FT = FusedTile<IO, R, U, S, V>;
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
     std::vector<TileLds<S>> L(1);
-    std::vector<typename FusedTile<IO, R, U, S>::TS> ts(NTHR);
-    std::vector<typename FusedTile<IO, R, U, S>::Pre> pre(NTHR);
-    std::vector<typename FusedTile<IO, R, U, S>::Pre0> pre0(NTHR);
+    std::vector<typename FT::TS> ts(NTHR);
+    std::vector<typename FT::Pre> pre(NTHR);
+    std::vector<typename FT::Pre0> pre0(NTHR);
     for (int b = 0; b < nt; ++b) {
       const int tile = xcd_tile(b, nt);
       memset((void *)L.data(), 0xff, sizeof(TileLds<S>));  // NaN poison: stray reads show
       memset((void *)pre.data(), 0xff, pre.size() * sizeof(pre[0]));
       memset((void *)pre0.data(), 0xff, pre0.size() * sizeof(pre0[0]));
-      FusedTile<IO, R, U, S> ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY,
-                                L.data()};
+      FT ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY, L.data()};
       // the kernel's order: P0 and Step 2 loads, P0 stores, barrier, P1, ... P4
       for (int t = 0; t < NTHR; ++t) ft.p0_load(t, pre0[t]);
       for (int t = 0; t < NTHR; ++t) ft.p1_load(t, pre[t]);
@@ -114,14 +114,9 @@ static void run_steps(CpuEx &ex, const Consts &K, Work &w, IO st[2], int &cur, b
   bool ready = false;
   for (long long n = 0; n < nsteps; ++n) {
     if (fused)
-      with_tile_shape(shape, K.unit, [&](auto sh) {
-        using S = decltype(sh);
-        if (K.unit)
-          seq_fused_step<CpuEx, IO, double, true, S>(ex, K, w, st[cur], st[1 - cur], ready);
-        else
-          seq_fused_step<CpuEx, IO, double, false,
-                         typename std::conditional<S::RG == 2, TileUpw, TileSq>::type>(
-              ex, K, w, st[cur], st[1 - cur], ready);
+      with_fused_kernel(shape, K, [&](auto u, auto sh, auto v) {
+        seq_fused_step<CpuEx, IO, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
+            ex, K, w, st[cur], st[1 - cur], ready);
       });
     cur = 1 - cur;
     swap_sums(w);
