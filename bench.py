@@ -24,9 +24,9 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # (profiles/fused_rt256x1024_fp64_traffic.md), for the exact and the
 # FMA-contracted builds on the headline grid and on the out-of-MALL grid.
 # Valid only while the kernel sources hash to the measured version.
-TRAFFIC = {"precision": "fp64", "tile": 1, "src_sha": "7d82dff3f8eeb17f",
-           "rt256x1024": {"exact": 95.40e6, "fma": 95.35e6},
-           "rt2048x8192": {"exact": 6554.07e6, "fma": 6554.24e6}}
+TRAFFIC = {"precision": "fp64", "tile": 1, "src_sha": "b6253792c01b03ac",
+           "rt256x1024": {"exact": 95.30e6, "fma": 95.19e6},
+           "rt2048x8192": {"exact": 6552.79e6, "fma": 6561.67e6}}
 
 FP64_VEC_PEAK_TF = 78.6    # MI355X FP64 vector
 FP32_VEC_PEAK_TF = 157.3
@@ -36,7 +36,7 @@ FP32_VEC_PEAK_TF = 157.3
 # SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters on the same workload
 # (profiles/fused_rt256x1024_fp64_valu.md); valid for the same sources.
 VALU = {"workload": "rt256x1024", "precision": "fp64", "src_sha": TRAFFIC["src_sha"],
-        "fp64_flop_per_cell": 2799.9, "fma_fp64_flop_per_cell": 2940.0}
+        "fp64_flop_per_cell": 2799.9, "fma_fp64_flop_per_cell": 2944.0}
 
 
 def traffic_for(workload, build, prec, tile):
