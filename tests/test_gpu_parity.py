@@ -297,6 +297,20 @@ def test_fused_fp64_matches_oracle(D, oracle_mod, name):
     assert sim.kernel_kind == D.KERNEL_FUSED
 
 
+@pytest.mark.parametrize("recon", [0, 1], ids=["central", "upwind"])
+@pytest.mark.parametrize("tau_f", [0.0, 0.4], ids=["mixture", "given"])
+def test_fused_general_lattice_speed_matches_oracle(D, oracle_mod, recon, tau_f):
+    """RT = 0.3 (c != 1): the fused kernel's general-direction build, which
+    reads the viscosity model at run time, equals the oracle bit for bit."""
+    case = W.drop_case(n=20, radius=5.0, recon=recon, tau_f=tau_f)
+    case.params["rt"] = 0.3
+    case.params["c_max"] = 0.0
+    case.params["cfl"] = 0.4
+    sim, o = _compare(D, oracle_mod, case, 8, D.KERNEL_FUSED, "fused")
+    assert sim.kernel_kind == D.KERNEL_FUSED
+    assert np.array_equal(sim.populations().cpu().numpy(), o.pops())
+
+
 def test_auto_kernel_choice(D):
     sim = D.Simulation.from_case(W.drop_case(n=16, radius=4.0))
     assert sim.kernel_kind == D.KERNEL_FUSED
@@ -425,8 +439,9 @@ def test_tile_shapes_equal_staged_bitwise(D, tile):
     import torch
     for case, steps in [(W.rt_case(30, ny=50, amp_frac=0.2), 12),
                         (W.bubble_case(32, 48, eo=20.0, mo=1e-3), 12),
-                        (W.drop_case(n=31, radius=8.0), 9)]:
-        print("tile", tile, case.name, flush=True)
+                        (W.drop_case(n=31, radius=8.0), 9),
+                        (W.drop_case(n=33, radius=8.0, tau_f=0.5), 9)]:
+        print("tile", tile, case.name, case.params["tau_f"], flush=True)
         case.params["tile"] = tile
         f = D.Simulation.from_case(case, kernel=D.KERNEL_FUSED)
         assert f.tile == tile
