@@ -93,17 +93,17 @@ struct GpuEx {
     hipLaunchKernelGGL(k_macros_tape, dim3(nb), dim3(MBX, MBY), 0, s, K, w, t, gx, nb);
     note(hipGetLastError());
   }
-  template <class IO, class R, bool U, class S, int V>
+  template <class IO, class R, bool U, class S, int V, bool TG>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (kt && kt->on) note(kt->pair(e0, e1));
     if (e0)
-      hipExtLaunchKernelGGL((k_fused_tile<IO, R, U, S, V>), dim3(nt), dim3(NTHR), 0, s, e0, e1, 0,
-                            K, w, src, dst, ntx, nt);
+      hipExtLaunchKernelGGL((k_fused_tile<IO, R, U, S, V, TG>), dim3(nt), dim3(NTHR), 0, s, e0,
+                            e1, 0, K, w, src, dst, ntx, nt);
     else
-      hipLaunchKernelGGL((k_fused_tile<IO, R, U, S, V>), dim3(nt), dim3(NTHR), 0, s, K, w, src,
-                         dst, ntx, nt);
+      hipLaunchKernelGGL((k_fused_tile<IO, R, U, S, V, TG>), dim3(nt), dim3(NTHR), 0, s, K, w,
+                         src, dst, ntx, nt);
     note(hipGetLastError());
   }
   // the adjoint's face stage over square tiles
@@ -387,6 +387,8 @@ int enqueue_step(dugks2p *h, int shape) {
       (shape == DUGKS2P_TILE_UPWIND) != (h->K.recon != DUGKS2P_RECON_CENTRAL))
     return fail(DUGKS2P_EINVAL, "tile shape does not match the face reconstruction");
   GpuEx ex{h->stream, hipSuccess, &h->kt};
+  // a ping-pong state small enough to stay in the MALL
+  const bool resident = 2.0 * (double)h->L.state_bytes <= TILDE_OUT_MAX_STATE_BYTES;
   if (h->kernel == DUGKS2P_KERNEL_FUSED_FMA) {
     // the FMA-contracted build of the same step (dugks2p_fma.hip)
     const bool f32 = h->precision != DUGKS2P_FP64;
@@ -404,6 +406,7 @@ int enqueue_step(dugks2p *h, int shape) {
     a.io_bytes = f32 ? sizeof s32 : sizeof s64;
     a.sums_ready = h->sums_ok ? 1 : 0;
     a.shape = shape;
+    a.resident = resident ? 1 : 0;
     a.stream = h->stream;
     a.e0 = a.e1 = nullptr;
     if (h->kt.on) ex.note(h->kt.pair(a.e0, a.e1));
@@ -414,16 +417,16 @@ int enqueue_step(dugks2p *h, int shape) {
                                            (double *)h->state[1 - h->cur]);
   } else if (h->precision == DUGKS2P_FP64) {
     const IoF64 src = io_f64(h->state[h->cur], h->K), dst = io_f64(h->state[1 - h->cur], h->K);
-    with_fused_kernel(shape, h->K, [&](auto u, auto sh, auto v) {
-      seq_fused_step<GpuEx, IoF64, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
-          ex, h->K, h->w, src, dst, h->sums_ok);
+    with_fused_kernel(shape, h->K, resident, [&](auto u, auto sh, auto v, auto tg) {
+      seq_fused_step<GpuEx, IoF64, double, decltype(u)::value, decltype(sh), decltype(v)::value,
+                     decltype(tg)::value>(ex, h->K, h->w, src, dst, h->sums_ok);
     });
   } else {
     const IoE32 src = io_e32(h->state[h->cur], h->K, h->L);
     const IoE32 dst = io_e32(h->state[1 - h->cur], h->K, h->L);
-    with_fused_kernel(shape, h->K, [&](auto u, auto sh, auto v) {
-      seq_fused_step<GpuEx, IoE32, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
-          ex, h->K, h->w, src, dst, h->sums_ok);
+    with_fused_kernel(shape, h->K, resident, [&](auto u, auto sh, auto v, auto tg) {
+      seq_fused_step<GpuEx, IoE32, double, decltype(u)::value, decltype(sh), decltype(v)::value,
+                     decltype(tg)::value>(ex, h->K, h->w, src, dst, h->sums_ok);
     });
   }
   if (ex.err != hipSuccess)

@@ -1196,9 +1196,10 @@ void seq_adjoint_segment(Ex &ex, const Consts &K, const AdjBufs &B, const double
       wt.jxn = wf.jxn;
       wt.jyn = wf.jyn;
       const IoF64 b{B.state(n + 1), K.plane};
-      with_fused_kernel(DUGKS2P_TILE_SQUARE, K, [&](auto u, auto sh, auto v) {
-        ex.template tiles<IoF64, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
-            K, wt, a, b);
+      // (tilde+ in LDS: the segment's states and tape keep the MALL busy)
+      with_fused_kernel(DUGKS2P_TILE_SQUARE, K, false, [&](auto u, auto sh, auto v, auto tg) {
+        ex.template tiles<IoF64, double, decltype(u)::value, decltype(sh), decltype(v)::value,
+                          decltype(tg)::value>(K, wt, a, b);
       });
       swap_sums(wf);
     }

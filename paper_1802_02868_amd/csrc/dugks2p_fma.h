@@ -18,6 +18,7 @@ struct FmaStepArgs {
   size_t io_bytes;
   int sums_ready;   // phi and the f~ sums of src are already in w
   int shape;        // DUGKS2P_TILE_* (AUTO not allowed)
+  int resident;     // the ping-pong state stays in the MALL (with_fused_kernel)
   hipStream_t stream;
   hipEvent_t e0, e1;  // optional: set to the tile kernel's start and end
 };

@@ -49,15 +49,15 @@ struct FmaEx {
     hipLaunchKernelGGL(k_macros, dim3(nb), dim3(MBX, MBY), 0, s, K, w, gx, nb, fields ? 1 : 0);
     note(hipGetLastError());
   }
-  template <class IO, class R, bool U, class S, int V>
+  template <class IO, class R, bool U, class S, int V, bool TG>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
     if (e0)
-      hipExtLaunchKernelGGL((k_fused_tile<IO, R, U, S, V>), dim3(nt), dim3(NTHR), 0, s, e0, e1, 0,
-                            K, w, src, dst, ntx, nt);
+      hipExtLaunchKernelGGL((k_fused_tile<IO, R, U, S, V, TG>), dim3(nt), dim3(NTHR), 0, s, e0,
+                            e1, 0, K, w, src, dst, ntx, nt);
     else
-      hipLaunchKernelGGL((k_fused_tile<IO, R, U, S, V>), dim3(nt), dim3(NTHR), 0, s, K, w, src,
-                         dst, ntx, nt);
+      hipLaunchKernelGGL((k_fused_tile<IO, R, U, S, V, TG>), dim3(nt), dim3(NTHR), 0, s, K, w,
+                         src, dst, ntx, nt);
     note(hipGetLastError());
   }
 };
@@ -73,9 +73,9 @@ hipError_t step(const FmaStepArgs *a) {
   memcpy(&src, a->src, sizeof src);
   memcpy(&dst, a->dst, sizeof dst);
   FmaEx ex{a->stream, hipSuccess, a->e0, a->e1};
-  with_fused_kernel(a->shape, K, [&](auto u, auto sh, auto v) {
-    seq_fused_step<FmaEx, IO, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
-        ex, K, w, src, dst, a->sums_ready != 0);
+  with_fused_kernel(a->shape, K, a->resident != 0, [&](auto u, auto sh, auto v, auto tg) {
+    seq_fused_step<FmaEx, IO, double, decltype(u)::value, decltype(sh), decltype(v)::value,
+                   decltype(tg)::value>(ex, K, w, src, dst, a->sums_ready != 0);
   });
   return ex.err;
 }

@@ -272,8 +272,10 @@ __global__ __launch_bounds__(MBX * MBY) void k_macros_tape(Consts K, Work w, Wor
 #endif
 
 // LDS of one tile.  A (bar+ on the tile and its ring) is dead once the faces
-// are computed; the face fluxes then reuse its space.
-template <class S>
+// are computed; the face fluxes then reuse its space.  TG: tilde+ of the
+// tile's cells waits in the output buffer instead of T (which then shrinks to
+// one element), and the LDS left lets three workgroups share a CU.
+template <class S, bool TG = false>
 struct TileLds {
   union {
     double A[18][S::WY][S::WX];
@@ -285,7 +287,7 @@ struct TileLds {
   double phi[S::SY][S::SX], mu[S::SY][S::SX], p[S::SY][S::SX];
   // tilde+ of the tile's cells (Step 2 output kept for Step 6) and D over the
   // bar+ window
-  double T[18][S::TY][S::TX];
+  double T[TG ? 1 : 18][TG ? 1 : S::TY][TG ? 1 : S::TX];
   double D[S::WY][S::WX];
   // App. B weights (population gradient, first derivative) of the tile's
   // columns (axis 0) and rows (axis 1) at the scalar-window positions, and
@@ -302,6 +304,10 @@ static_assert(sizeof(TileLds<TileSq>) <= 80 * 1024, "square tile LDS above 80 Ki
 static_assert(sizeof(TileLds<TileWide>) <= 80 * 1024, "wide tile LDS above 80 KiB");
 static_assert(sizeof(TileLds<TileTall>) <= 80 * 1024, "tall tile LDS above 80 KiB");
 static_assert(sizeof(TileLds<TileUpw>) <= 80 * 1024, "two-ring tile LDS above 80 KiB");
+// ... and three workgroups when tilde+ goes through the output buffer (the
+// allocation granule of LDS is 512 bytes)
+static_assert(3 * ((sizeof(TileLds<TileSq, true>) + 511) / 512 * 512) <= 160 * 1024,
+              "square tile LDS without tilde+ above a third of a CU");
 
 // Accessor of the face code over the tile's LDS (bar+, phi, mu, p) and the
 // global D.  Global cell (x, y) maps to the tile window, periodic images
@@ -555,15 +561,18 @@ struct TileP0 {
   }
 };
 
-// One tile of shape S with origin (x0, y0); V: the viscosity model.
-template <class IO, class R, bool U = false, class S = TileSq, int V = VIS_ANY>
+// One tile of shape S with origin (x0, y0); V: the viscosity model; TG:
+// tilde+ of the tile's cells kept in the output buffer between P1 and P4
+// (else in LDS).
+template <class IO, class R, bool U = false, class S = TileSq, int V = VIS_ANY, bool TG = false>
 struct FusedTile {
+  using Lds = TileLds<S, TG>;
   const Consts &K;
   const Work &w;
   IO src;
   IO dst;
   int x0, y0;
-  TileLds<S> *L;
+  Lds *L;
 
   struct TS {
     R fx[12], fy[12];
@@ -597,8 +606,8 @@ struct FusedTile {
   }
 
   // P0 (see TileP0)
-  using Pre0 = typename TileP0<S>::Pre0;
-  DFN TileP0<S> win() const { return TileP0<S>{K, w, x0, y0, L}; }
+  using Pre0 = typename TileP0<S, Lds>::Pre0;
+  DFN TileP0<S, Lds> win() const { return TileP0<S, Lds>{K, w, x0, y0, L}; }
   DFN void p0_load(int tid, Pre0 &r) const { win().p0_load(tid, r); }
   DFN void p0_store(int tid, const Pre0 &r) const { win().p0_store(tid, r); }
 
@@ -609,8 +618,8 @@ struct FusedTile {
     int gx, gy;
     p1_cell(tid, gx, gy);
     if (gx < 0 || gy < 0) return;
-    const LAcc<S> acc{&K, &w, L, x0, y0};
-    const typename LAcc<S>::H hc = acc.cell(gx, gy);
+    const LAcc<S, Lds> acc{&K, &w, L, x0, y0};
+    const typename LAcc<S, Lds>::H hc = acc.cell(gx, gy);
     const double ph = acc.phi(hc);
     const double rh = rho_of<double>(K, ph);
     // F and u of the macro kernel, recomputed from mu in LDS and the f~ sums
@@ -663,9 +672,15 @@ struct FusedTile {
 #pragma unroll
       for (int q = 0; q < 18; ++q)
         tv[q] = (double)((R)(4.0 / 3.0) * (R)(double)out[q] - (R)(1.0 / 3.0) * til[q]);
-      IO::roundtrip(tv);
+      if (TG) {
+        // into the cell's slot of the output buffer, which P4 reads back
+        // (load after store is the encoding's round trip) and overwrites
+        dst.store((i64)gy * K.ld + gx, tv);
+      } else {
+        IO::roundtrip(tv);
 #pragma unroll
-      for (int q = 0; q < 18; ++q) L->T[q][cy][cx] = tv[q];
+        for (int q = 0; q < 18; ++q) L->T[TG ? 0 : q][TG ? 0 : cy][TG ? 0 : cx] = tv[q];
+      }
     }
   }
 
@@ -673,14 +688,14 @@ struct FusedTile {
   // of tile row ty.
   DFN void p2(int tid, TS &ts) const {
     const int tx = tid % S::WX, ty = tid / S::WX;
-    const LAcc<S> acc{&K, &w, L, x0, y0};
+    const LAcc<S, Lds> acc{&K, &w, L, x0, y0};
     ts.hx = ts.hy = false;
     R out[18];
     const bool perx = K.ax[0].bc == 0, pery = K.ax[1].bc == 0;
     if (tx <= S::TX && ty < S::TY) {
       const int k = x0 + tx, t = y0 + ty;
       if (t < K.ny && k <= K.nx) {
-        face_core<0, R, LAcc<S>, U, V>(K, acc, (perx && k == K.nx) ? 0 : k, t, out);
+        face_core<0, R, LAcc<S, Lds>, U, V>(K, acc, (perx && k == K.nx) ? 0 : k, t, out);
 #pragma unroll
         for (int q = 0; q < 18; ++q) {
           const int s = xslot(q % 9);
@@ -692,7 +707,7 @@ struct FusedTile {
     if (tx < S::TX && ty <= S::TY) {
       const int k = y0 + ty, t = x0 + tx;
       if (t < K.nx && k <= K.ny) {
-        face_core<1, R, LAcc<S>, U, V>(K, acc, (pery && k == K.ny) ? 0 : k, t, out);
+        face_core<1, R, LAcc<S, Lds>, U, V>(K, acc, (pery && k == K.ny) ? 0 : k, t, out);
 #pragma unroll
         for (int q = 0; q < 18; ++q) {
           const int s = yslot(q % 9);
@@ -744,8 +759,12 @@ struct FusedTile {
     const i64 c = (i64)gy * K.ld + gx;
     const R rx = (R)L->rdt[0][cx], ry = (R)L->rdt[1][cy];
     double tv[18];
+    if (TG) {
+      dst.load(c, tv);
+    } else {
 #pragma unroll
-    for (int q = 0; q < 18; ++q) tv[q] = L->T[q][cy][cx];
+      for (int q = 0; q < 18; ++q) tv[q] = L->T[TG ? 0 : q][TG ? 0 : cy][TG ? 0 : cx];
+    }
 #pragma unroll
     for (int q = 0; q < 18; ++q) {
       const int d = q % 9, sx = xslot(d), sy = yslot(d);
@@ -799,28 +818,29 @@ DFN int xcd_tile(int b, int n) {
 }
 
 #if defined(__HIPCC__)
-// Two workgroups share a CU (their LDS fits), so registers are held to two
-// waves per SIMD.
-template <class IO, class R, bool U, class S, int V>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_tile(
-    Consts K, Work w, IO src, IO dst, int ntx, int ntiles) {
-  __shared__ TileLds<S> L;
+// Registers are held to the waves per SIMD that the LDS allows: two
+// workgroups per CU, or three without tilde+ in LDS.
+template <class IO, class R, bool U, class S, int V, bool TG>
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(TG ? 3 : 2))) void
+k_fused_tile(Consts K, Work w, IO src, IO dst, int ntx, int ntiles) {
+  __shared__ TileLds<S, TG> L;
   const int tile = xcd_tile(blockIdx.x, ntiles);
-  FusedTile<IO, R, U, S, V> ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY, &L};
+  FusedTile<IO, R, U, S, V, TG> ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY, &L};
   ft.run(threadIdx.x);
 }
 #endif
 
-// One fused time step (Ex: grid(functor, n0, n1) and tiles<IO, R, U, S, V>(...)).
-// U: unit lattice speed (RT = 1/3), S: tile shape, V: viscosity model, all
-// chosen by the host (with_fused_kernel).  sums_ready: phi and the f~ sums
-// of src are already in w (written by the previous step's tile kernel).
-template <class Ex, class IO, class R, bool U, class S = TileSq, int V = VIS_ANY>
+// One fused time step (Ex: grid(functor, n0, n1) and
+// tiles<IO, R, U, S, V, TG>(...)).  U: unit lattice speed (RT = 1/3), S: tile
+// shape, V: viscosity model, TG: tilde+ through the output buffer, all chosen
+// by the host (with_fused_kernel).  sums_ready: phi and the f~ sums of src
+// are already in w (written by the previous step's tile kernel).
+template <class Ex, class IO, class R, bool U, class S = TileSq, int V = VIS_ANY, bool TG = false>
 void seq_fused_step(Ex &ex, const Consts &K, const Work &w, const IO &src, const IO &dst,
                     bool sums_ready = false) {
   if (!sums_ready) ex.grid(FPhiSums<IO, U>{K, w, src}, K.nx, K.ny);
   ex.macros(K, w, false);
-  ex.template tiles<IO, R, U, S, V>(K, w, src, dst);
+  ex.template tiles<IO, R, U, S, V, TG>(K, w, src, dst);
 }
 
 // After a committed fused step the sums written for the new state become
@@ -849,33 +869,53 @@ void with_tile_shape(int shape, bool unit, F &&f) {
     f(TileSq{});
 }
 
-// Calls f(u, s, v) with the compile-time choices of the single-handle tile
-// kernel for a DUGKS2P_TILE_* shape and the constants K: u the unit-speed
-// flag (std::bool_constant), s the tile shape, v the viscosity model
-// (std::integral_constant<int, VIS_*>).  At unit lattice speed every shape
-// is compiled for a given tau_f and for the mixture viscosity apart (the
-// run-time choice costs the tile kernel about a tenth of its speed); other
-// speeds take square or two-ring tiles and read the model at run time.
+// Ping-pong states up to this size (both buffers, bytes) stay in the MALL
+// (256 MB) while a step runs, so the square-tile kernel at unit lattice speed
+// keeps tilde+ in the output buffer there: the store and reload then cost no
+// HBM traffic, and the LDS they free lets three workgroups share a CU.  On
+// larger states the reload goes to HBM and the LDS form is faster.
+constexpr double TILDE_OUT_MAX_STATE_BYTES = 128.0 * 1024.0 * 1024.0;
+
+// Calls f(u, s, v, tg) with the compile-time choices of the single-handle
+// tile kernel for a DUGKS2P_TILE_* shape and the constants K: u the
+// unit-speed flag (std::bool_constant), s the tile shape, v the viscosity
+// model (std::integral_constant<int, VIS_*>), tg whether tilde+ goes through
+// the output buffer (std::bool_constant; taken for square tiles at unit
+// speed when the caller's ping-pong state is at most
+// TILDE_OUT_MAX_STATE_BYTES, passed as resident).  At unit lattice speed every
+// shape is compiled for a given tau_f and for the mixture viscosity apart
+// (the run-time choice costs the tile kernel about a tenth of its speed);
+// other speeds take square or two-ring tiles and read the model at run time.
 // Shape 4 (the two-ring tiles) is UPWIND reconstruction and every other
 // shape CENTRAL: the caller keeps the two matched.
 template <class F>
-void with_fused_kernel(int shape, const Consts &K, F &&f) {
+void with_fused_kernel(int shape, const Consts &K, bool resident, F &&f) {
   using Any = std::integral_constant<int, VIS_ANY>;
   using Uni = std::integral_constant<int, VIS_UNIFORM>;
   using Mix = std::integral_constant<int, VIS_MIXTURE>;
   if (!K.unit) {
     if (shape == 4)
-      f(std::false_type{}, TileUpw{}, Any{});
+      f(std::false_type{}, TileUpw{}, Any{}, std::false_type{});
     else
-      f(std::false_type{}, TileSq{}, Any{});
+      f(std::false_type{}, TileSq{}, Any{}, std::false_type{});
     return;
   }
-  with_tile_shape(shape, true, [&](auto sh) {
+  auto vis = [&](auto sh, auto tg) {
     if (K.tau_f > 0.0)
-      f(std::true_type{}, sh, Uni{});
+      f(std::true_type{}, sh, Uni{}, tg);
     else
-      f(std::true_type{}, sh, Mix{});
-  });
+      f(std::true_type{}, sh, Mix{}, tg);
+  };
+  if (shape == 4)
+    vis(TileUpw{}, std::false_type{});
+  else if (shape == 2)
+    vis(TileWide{}, std::false_type{});
+  else if (shape == 3)
+    vis(TileTall{}, std::false_type{});
+  else if (resident)
+    vis(TileSq{}, std::true_type{});
+  else
+    vis(TileSq{}, std::false_type{});
 }
 
 // Cell fields of the current state for moments and monitors (phi, mu, D, F,

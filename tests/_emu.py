@@ -39,16 +39,28 @@ def lib():
     return _lib
 
 
-def run(case, steps, kernel=1):
-    """Initialise + `steps` steps in the host build; returns (pops, macros)."""
+def run(case, steps, kernel=1, tilde=None):
+    """Initialise + `steps` steps in the host build; returns (pops, macros).
+    tilde: "lds" or "out" forces where the square-tile kernel keeps tilde+
+    (LDS, or the output buffer); None takes the library's choice by state
+    size (the output buffer for every grid of these tests)."""
     from paper_1802_02868_amd.dugks2p_params import make_params  # noqa: E402
     P = make_params(case.params, case.x_faces, case.y_faces, kernel=kernel)
     dp = ctypes.POINTER(ctypes.c_double)
     pops = np.empty((18, case.ny, case.nx))
     mac = np.empty((5, case.ny, case.nx))
     fl = [np.ascontiguousarray(a, dtype=np.float64) for a in (case.phi0, case.ux0, case.uy0, case.p0)]
-    rc = lib().emu_run(ctypes.byref(P), *[a.ctypes.data_as(dp) for a in fl], ctypes.c_longlong(steps),
-                       pops.ctypes.data_as(dp), mac.ctypes.data_as(dp))
+    old = os.environ.pop("DUGKS2P_EMU_TILDE", None)
+    if tilde is not None:
+        os.environ["DUGKS2P_EMU_TILDE"] = tilde
+    try:
+        rc = lib().emu_run(ctypes.byref(P), *[a.ctypes.data_as(dp) for a in fl],
+                           ctypes.c_longlong(steps), pops.ctypes.data_as(dp),
+                           mac.ctypes.data_as(dp))
+    finally:
+        os.environ.pop("DUGKS2P_EMU_TILDE", None)
+        if old is not None:
+            os.environ["DUGKS2P_EMU_TILDE"] = old
     assert rc == 0
     return pops, mac
 

@@ -79,17 +79,17 @@ struct CpuEx {
       for (int t = 0; t < NTHR; ++t) ct.finish(s[t]);
     }
   }
-  template <class IO, class R, bool U, class S, int V>
+  template <class IO, class R, bool U, class S, int V, bool TG>
   void tiles(const Consts &K, const Work &w, const IO &src, const IO &dst) {
-    using FT = FusedTile<IO, R, U, S, V>;
+    using FT = FusedTile<IO, R, U, S, V, TG>;
     const int ntx = tiles_x<S>(K), nt = ntx * tiles_y<S>(K);
-    std::vector<TileLds<S>> L(1);
+    std::vector<typename FT::Lds> L(1);
     std::vector<typename FT::TS> ts(NTHR);
     std::vector<typename FT::Pre> pre(NTHR);
     std::vector<typename FT::Pre0> pre0(NTHR);
     for (int b = 0; b < nt; ++b) {
       const int tile = xcd_tile(b, nt);
-      memset((void *)L.data(), 0xff, sizeof(TileLds<S>));  // NaN poison: stray reads show
+      memset((void *)L.data(), 0xff, sizeof(typename FT::Lds));  // NaN poison: stray reads show
       memset((void *)pre.data(), 0xff, pre.size() * sizeof(pre[0]));
       memset((void *)pre0.data(), 0xff, pre0.size() * sizeof(pre0[0]));
       FT ft{K, w, src, dst, (tile % ntx) * S::TX, (tile / ntx) * S::TY, L.data()};
@@ -108,15 +108,20 @@ struct CpuEx {
 
 // Fused steps as the runtime runs them: the sums kernel only before the
 // first step, then the tile kernel's own sums of the state it writes.
+// resident: the library's choice of tilde+ through the output buffer, or the
+// one DUGKS2P_EMU_TILDE names ("lds" or "out"), so that tests run both forms.
 template <class IO>
 static void run_steps(CpuEx &ex, const Consts &K, Work &w, IO st[2], int &cur, bool fused,
-                      long long nsteps, int shape) {
+                      long long nsteps, int shape, bool resident) {
+  const char *force = getenv("DUGKS2P_EMU_TILDE");
+  if (force && !strcmp(force, "lds")) resident = false;
+  if (force && !strcmp(force, "out")) resident = true;
   bool ready = false;
   for (long long n = 0; n < nsteps; ++n) {
     if (fused)
-      with_fused_kernel(shape, K, [&](auto u, auto sh, auto v) {
-        seq_fused_step<CpuEx, IO, double, decltype(u)::value, decltype(sh), decltype(v)::value>(
-            ex, K, w, st[cur], st[1 - cur], ready);
+      with_fused_kernel(shape, K, resident, [&](auto u, auto sh, auto v, auto tg) {
+        seq_fused_step<CpuEx, IO, double, decltype(u)::value, decltype(sh), decltype(v)::value,
+                       decltype(tg)::value>(ex, K, w, st[cur], st[1 - cur], ready);
       });
     cur = 1 - cur;
     swap_sums(w);
@@ -139,6 +144,7 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
   // the library's choice: UPWIND reconstruction runs on the two-ring tiles
   const int shape = P->recon != DUGKS2P_RECON_CENTRAL ? DUGKS2P_TILE_UPWIND : P->tile;
   Layout L = make_layout(K, ax, ay, P->precision, true);
+  const bool resident = 2.0 * (double)L.state_bytes <= TILDE_OUT_MAX_STATE_BYTES;
   std::vector<unsigned char> mem(L.total + 256, 0);
   unsigned char *base = (unsigned char *)(((uintptr_t)mem.data() + 255) & ~(uintptr_t)255);
   std::vector<unsigned char> tb;
@@ -156,7 +162,7 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
     IoF64 st[2] = {io_f64(base + L.state[0], K), io_f64(base + L.state[1], K)};
     seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
     if (fused) {
-      run_steps(ex, K, w, st, cur, true, nsteps, shape);
+      run_steps(ex, K, w, st, cur, true, nsteps, shape, resident);
     } else {
       for (long long n = 0; n < nsteps; ++n) {
         seq_staged_step(ex, K, w, (const double *)st[cur].p, st[1 - cur].p);
@@ -172,7 +178,7 @@ extern "C" int emu_run(const dugks2p_params *P, const double *phi0, const double
   } else {
     IoE32 st[2] = {io_e32(base + L.state[0], K, L), io_e32(base + L.state[1], K, L)};
     seq_init(ex, K, w, phi0, ux0, uy0, p0, st[0]);
-    run_steps(ex, K, w, st, cur, true, nsteps, shape);
+    run_steps(ex, K, w, st, cur, true, nsteps, shape, resident);
     for (int j = 0; j < K.ny; ++j)
       for (int i = 0; i < K.nx; ++i) {
         st[cur].load((i64)j * K.ld + i, v);

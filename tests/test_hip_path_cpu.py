@@ -130,13 +130,15 @@ FUSED_CASES = {
 }
 
 
+@pytest.mark.parametrize("tilde", ["out", "lds"])
 @pytest.mark.parametrize("name", sorted(FUSED_CASES))
-def test_fused_kernel_logic_bitwise_equal_to_oracle(oracle_mod, name):
+def test_fused_kernel_logic_bitwise_equal_to_oracle(oracle_mod, name, tilde):
     """Host run of the fused tile kernel (phases with barrier semantics, LDS
-    poisoned with NaN) against the oracle."""
+    poisoned with NaN) against the oracle, with tilde+ kept in the output
+    buffer or in LDS."""
     make, steps = FUSED_CASES[name]
     case = make()
-    pops, mac = _emu.run(case, steps, kernel=2)
+    pops, mac = _emu.run(case, steps, kernel=2, tilde=tilde)
     o = oracle_mod.Oracle.from_case(case)
     o.step(steps)
     assert np.array_equal(pops, o.pops())
@@ -204,6 +206,19 @@ def test_general_lattice_speed_kernel_logic(oracle_mod):
     for kernel in (1, 2):
         pops, _ = _emu.run(case, 8, kernel=kernel)
         assert np.array_equal(pops, o.pops()), ("upwind", kernel)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_state"])
+def test_tilde_in_lds_or_output_buffer_identical(prec):
+    """Where the square-tile kernel keeps tilde+ between Step 2 and the update
+    changes nothing: for the FP32 state the output buffer's store and load
+    round it exactly as the encoding's round trip does in LDS."""
+    for case, steps in [(W.rt_case(30, ny=50, amp_frac=0.2), 40),
+                        (W.drop_case(n=33, radius=8.0, tau_f=0.5), 30)]:
+        case.params["precision"] = prec
+        a, ma = _emu.run(case, steps, kernel=2, tilde="out")
+        b, mb = _emu.run(case, steps, kernel=2, tilde="lds")
+        assert np.array_equal(a, b) and np.array_equal(ma, mb), case.name
 
 
 def test_fp32_state_kernel_logic_within_tolerance(oracle_mod):

@@ -36,7 +36,7 @@ def sanitized(tmp_path_factory):
     return out
 
 
-def _run(exe, tmp, case, steps, kind=0, mseg=0, kernel=2, lam=None):
+def _run(exe, tmp, case, steps, kind=0, mseg=0, kernel=2, lam=None, tilde=None):
     P = make_params(case.params, case.x_faces, case.y_faces, kernel=kernel)
     n = case.nx * case.ny
     fin, fout = str(tmp / "case.bin"), str(tmp / "out.bin")
@@ -49,6 +49,9 @@ def _run(exe, tmp, case, steps, kind=0, mseg=0, kernel=2, lam=None):
             f.write(np.ascontiguousarray(lam, dtype=np.float64).tobytes())
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    env.pop("DUGKS2P_EMU_TILDE", None)
+    if tilde is not None:
+        env["DUGKS2P_EMU_TILDE"] = tilde
     r = subprocess.run([exe, fin, fout], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, (case.name, r.returncode, r.stdout[-2000:], r.stderr[-4000:])
     assert "runtime error" not in r.stderr and "window check" not in r.stdout, r.stderr[-2000:]
@@ -71,21 +74,24 @@ FORWARD = [
 ]
 
 
+@pytest.mark.parametrize("tilde", ["out", "lds"])
 @pytest.mark.parametrize("name,make,kernel,steps", FORWARD, ids=[f[0] for f in FORWARD])
-def test_sanitized_forward(sanitized, tmp_path, name, make, kernel, steps):
+def test_sanitized_forward(sanitized, tmp_path, name, make, kernel, steps, tilde):
+    """tilde: where the square-tile kernel keeps tilde+ (output buffer or LDS)."""
     case = make()
     if name.startswith("wide"):
         case.params["tile"] = 2
-    got = _run(sanitized, tmp_path, case, steps, kernel=kernel)
-    ref, _ = _emu.run(case, steps, kernel=kernel)
+    got = _run(sanitized, tmp_path, case, steps, kernel=kernel, tilde=tilde)
+    ref, _ = _emu.run(case, steps, kernel=kernel, tilde=tilde)
     assert np.array_equal(got, ref), name
 
 
-def test_sanitized_fp32_state(sanitized, tmp_path):
+@pytest.mark.parametrize("tilde", ["out", "lds"])
+def test_sanitized_fp32_state(sanitized, tmp_path, tilde):
     case = W.rt_case(28, ny=30, amp_frac=0.2)
     case.params["precision"] = 1
-    got = _run(sanitized, tmp_path, case, 2, kernel=2)
-    ref, _ = _emu.run(case, 2, kernel=2)
+    got = _run(sanitized, tmp_path, case, 2, kernel=2, tilde=tilde)
+    ref, _ = _emu.run(case, 2, kernel=2, tilde=tilde)
     assert np.array_equal(got, ref)
 
 
