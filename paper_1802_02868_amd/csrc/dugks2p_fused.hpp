@@ -308,6 +308,8 @@ static_assert(sizeof(TileLds<TileUpw>) <= 80 * 1024, "two-ring tile LDS above 80
 // allocation granule of LDS is 512 bytes)
 static_assert(3 * ((sizeof(TileLds<TileSq, true>) + 511) / 512 * 512) <= 160 * 1024,
               "square tile LDS without tilde+ above a third of a CU");
+static_assert(3 * ((sizeof(TileLds<TileUpw, true>) + 511) / 512 * 512) <= 160 * 1024,
+              "two-ring tile LDS without tilde+ above a third of a CU");
 
 // Accessor of the face code over the tile's LDS (bar+, phi, mu, p) and the
 // global D.  Global cell (x, y) maps to the tile window, periodic images
@@ -870,19 +872,20 @@ void with_tile_shape(int shape, bool unit, F &&f) {
 }
 
 // Ping-pong states up to this size (both buffers, bytes) stay in the MALL
-// (256 MB) while a step runs, so the square-tile kernel at unit lattice speed
-// keeps tilde+ in the output buffer there: the store and reload then cost no
-// HBM traffic, and the LDS they free lets three workgroups share a CU.  On
-// larger states the reload goes to HBM and the LDS form is faster.
+// (256 MB) while a step runs, so the square and two-ring tile kernels at unit
+// lattice speed keep tilde+ in the output buffer there: the store and reload
+// then cost no HBM traffic, and the LDS they free lets three workgroups share
+// a CU.  On larger states the reload goes to HBM and the LDS form is faster.
 constexpr double TILDE_OUT_MAX_STATE_BYTES = 128.0 * 1024.0 * 1024.0;
 
 // Calls f(u, s, v, tg) with the compile-time choices of the single-handle
 // tile kernel for a DUGKS2P_TILE_* shape and the constants K: u the
 // unit-speed flag (std::bool_constant), s the tile shape, v the viscosity
 // model (std::integral_constant<int, VIS_*>), tg whether tilde+ goes through
-// the output buffer (std::bool_constant; taken for square tiles at unit
-// speed when the caller's ping-pong state is at most
-// TILDE_OUT_MAX_STATE_BYTES, passed as resident).  At unit lattice speed every
+// the output buffer (std::bool_constant; taken for square and two-ring tiles
+// at unit speed when the caller's ping-pong state is at most
+// TILDE_OUT_MAX_STATE_BYTES, passed as resident; the wide and tall tiles
+// would not fit three to a CU even so).  At unit lattice speed every
 // shape is compiled for a given tau_f and for the mixture viscosity apart
 // (the run-time choice costs the tile kernel about a tenth of its speed);
 // other speeds take square or two-ring tiles and read the model at run time.
@@ -906,7 +909,9 @@ void with_fused_kernel(int shape, const Consts &K, bool resident, F &&f) {
     else
       f(std::true_type{}, sh, Mix{}, tg);
   };
-  if (shape == 4)
+  if (shape == 4 && resident)
+    vis(TileUpw{}, std::true_type{});
+  else if (shape == 4)
     vis(TileUpw{}, std::false_type{});
   else if (shape == 2)
     vis(TileWide{}, std::false_type{});

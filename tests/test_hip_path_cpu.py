@@ -156,14 +156,15 @@ UPWIND_FUSED_CASES = {
 }
 
 
+@pytest.mark.parametrize("tilde", ["out", "lds"])
 @pytest.mark.parametrize("name", sorted(UPWIND_FUSED_CASES))
-def test_fused_upwind_kernel_logic_bitwise_equal_to_oracle(oracle_mod, name):
+def test_fused_upwind_kernel_logic_bitwise_equal_to_oracle(oracle_mod, name, tilde):
     """UPWIND reconstruction on the fused kernel's two-ring tiles (12 x 12
     cells, bar+ two cells beyond the tile): host run of the phases against
-    the oracle, bit for bit."""
+    the oracle, bit for bit, with tilde+ in the output buffer or in LDS."""
     make, steps = UPWIND_FUSED_CASES[name]
     case = make()
-    pops, mac = _emu.run(case, steps, kernel=2)
+    pops, mac = _emu.run(case, steps, kernel=2, tilde=tilde)
     o = oracle_mod.Oracle.from_case(case)
     o.step(steps)
     assert np.array_equal(pops, o.pops())
@@ -214,7 +215,8 @@ def test_tilde_in_lds_or_output_buffer_identical(prec):
     changes nothing: for the FP32 state the output buffer's store and load
     round it exactly as the encoding's round trip does in LDS."""
     for case, steps in [(W.rt_case(30, ny=50, amp_frac=0.2), 40),
-                        (W.drop_case(n=33, radius=8.0, tau_f=0.5), 30)]:
+                        (W.drop_case(n=33, radius=8.0, tau_f=0.5), 30),
+                        (W.rt_case(26, ny=30, amp_frac=0.2, recon=1), 30)]:
         case.params["precision"] = prec
         a, ma = _emu.run(case, steps, kernel=2, tilde="out")
         b, mb = _emu.run(case, steps, kernel=2, tilde="lds")
