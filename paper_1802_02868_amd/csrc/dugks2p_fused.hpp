@@ -170,13 +170,17 @@ struct FMacF {
 DFN int wrapi(int g, int n);
 DFN int xcd_tile(int b, int n);
 
-// The same cell macros over a 64 x 4 block of cells: mu once on the block
-// and a one-cell ring in LDS (instead of at every cell's four neighbours),
-// then grad mu, D, F, u and p of the block's cells.  Two phases separated by
-// a workgroup barrier.
+// The same cell macros over a 64 x 4 block of cells, in three phases
+// separated by workgroup barriers: P0 stages phi on the block and a two-cell
+// ring and the App. B second-derivative weights of the mu window in LDS; P1
+// forms mu once on the block and a one-cell ring from them (instead of at
+// every cell's four neighbours); P2 forms grad mu, D, F, u and p of the
+// block's cells.  The arithmetic and its inputs are those of macros_at.
 enum { MBX = 64, MBY = 4 };
 struct MacLds {
+  double phi[MBY + 4][MBX + 4];
   double mu[MBY + 2][MBX + 2];
+  double wx[MBX + 2][3], wy[MBY + 2][3];  // d2 weights of the mu window's columns, rows
 };
 
 struct MacBlock {
@@ -192,21 +196,67 @@ struct MacBlock {
   // recomputes F and u of its bar+ window itself.  true: every field
   // (moments, monitors, observables).
   bool fields = true;
+  enum { PW = (MBX + 4) * (MBY + 4), NPHI = (PW + MBX * MBY - 1) / (MBX * MBY) };
+  static_assert((MBX + 2) + (MBY + 2) <= MBX * MBY, "weight roles exceed the block");
   // global index of window offset g along an axis, or -1 outside a wall domain
   DFN int gcol(int g, int n, int bc) const {
     if (bc == 0) return wrapi(g, n);
     return (g >= 0 && g < n) ? g : -1;
   }
+  // P0: phi of the two-ring window (elements tid, tid + 256, ...) and one
+  // weight row per thread of the first MBX + MBY + 4, loads first
   DFN void p0(int tid) const {
-    for (int e = tid; e < (MBX + 2) * (MBY + 2); e += MBX * MBY) {
-      const int lx = e % (MBX + 2), ly = e / (MBX + 2);
-      const int gx = gcol(x0 - 1 + lx, K.nx, K.ax[0].bc);
-      const int gy = gcol(y0 - 1 + ly, K.ny, K.ax[1].bc);
+    double ph[NPHI];
+    int at[NPHI];
+#pragma unroll
+    for (int k = 0; k < NPHI; ++k) {
+      const int e = tid + k * MBX * MBY;
+      at[k] = -1;
+      if (e >= PW) continue;
+      const int lx = e % (MBX + 4), ly = e / (MBX + 4);
+      const int gx = gcol(x0 - 2 + lx, K.nx, K.ax[0].bc);
+      const int gy = gcol(y0 - 2 + ly, K.ny, K.ax[1].bc);
       if (gx < 0 || gy < 0) continue;
-      L->mu[ly][lx] = mu_at(K, w.phi, gx, gy);
+      ph[k] = w.phi[(i64)gy * K.ld + gx];
+      at[k] = e;
+    }
+    double wt[3];
+    const int a = tid < MBX + 2 ? 0 : 1, pos = a == 0 ? tid : tid - (MBX + 2);
+    const int g = tid < (MBX + 2) + (MBY + 2)
+                      ? gcol((a == 0 ? x0 : y0) - 1 + pos, K.ax[a].n, K.ax[a].bc)
+                      : -1;
+    if (g >= 0) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) wt[m] = K.ax[a].d2[3 * g + m];
+    }
+#pragma unroll
+    for (int k = 0; k < NPHI; ++k)
+      if (at[k] >= 0) L->phi[at[k] / (MBX + 4)][at[k] % (MBX + 4)] = ph[k];
+    if (g >= 0) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) (a == 0 ? L->wx[pos] : L->wy[pos])[m] = wt[m];
     }
   }
+  // P1: mu on the one-ring window; a stencil neighbour is the adjacent
+  // window position, or the cell itself at a wall
   DFN void p1(int tid) const {
+    const Axis &X = K.ax[0], &Y = K.ax[1];
+    for (int e = tid; e < (MBX + 2) * (MBY + 2); e += MBX * MBY) {
+      const int mx = e % (MBX + 2), my = e / (MBX + 2);
+      const int gx = gcol(x0 - 1 + mx, K.nx, X.bc);
+      const int gy = gcol(y0 - 1 + my, K.ny, Y.bc);
+      if (gx < 0 || gy < 0) continue;
+      const int px = mx + 1, py = my + 1;
+      const double ph = L->phi[py][px];
+      const double xl = (X.bc != 0 && gx == 0) ? ph : L->phi[py][px - 1];
+      const double xh = (X.bc != 0 && gx == X.n - 1) ? ph : L->phi[py][px + 1];
+      const double yl = (Y.bc != 0 && gy == 0) ? ph : L->phi[py - 1][px];
+      const double yh = (Y.bc != 0 && gy == Y.n - 1) ? ph : L->phi[py + 1][px];
+      L->mu[my][mx] = mu_from(K, ph, xl, xh, yl, yh, L->wx[mx], L->wy[my]);
+    }
+  }
+  // P2: the cell macros of the block's cells
+  DFN void p2(int tid) const {
     const int tx = tid % MBX, ty = tid / MBX;
     const int i = x0 + tx, j = y0 + ty;
     if (i >= K.nx || j >= K.ny) return;
@@ -214,18 +264,18 @@ struct MacBlock {
     // neighbours: the adjacent window positions, or the cell itself at a wall
     const int sxl = (X.bc != 0 && i == 0) ? 0 : 1, sxh = (X.bc != 0 && i == X.n - 1) ? 0 : 1;
     const int syl = (Y.bc != 0 && j == 0) ? 0 : 1, syh = (Y.bc != 0 && j == Y.n - 1) ? 0 : 1;
-    const int mx = tx + 1, my = ty + 1;
-    const i64 c = (i64)j * K.ld + i, r = (i64)j * K.ld;
-    const int il = ax_lo(X, i), ih = ax_hi(X, i), jl = ax_lo(Y, j), jh = ax_hi(Y, j);
+    const int mx = tx + 1, my = ty + 1, px = tx + 2, py = ty + 2;
+    const i64 c = (i64)j * K.ld + i;
     const double mc = L->mu[my][mx];
+    const double ph = L->phi[py][px];
     const CellMac m = macros_from(
         K, mc, L->mu[my][mx - sxl], L->mu[my][mx + sxh], L->mu[my - syl][mx],
-        L->mu[my + syh][mx], w.phi[c], w.phi[r + il], w.phi[r + ih], w.phi[(i64)jl * K.ld + i],
-        w.phi[(i64)jh * K.ld + i], w.s0[c], w.jx[c], w.jy[c], X.d1 + 3 * i, X.d2 + 3 * i,
-        Y.d1 + 3 * j, Y.d2 + 3 * j);
+        L->mu[my + syh][mx], ph, L->phi[py][px - sxl], L->phi[py][px + sxh],
+        L->phi[py - syl][px], L->phi[py + syh][px], w.s0[c], w.jx[c], w.jy[c], X.d1 + 3 * i,
+        X.d2 + 3 * i, Y.d1 + 3 * j, Y.d2 + 3 * j);
     const Work &o = tape ? *tape : w;
     if (tape) {
-      o.phi[c] = w.phi[c];
+      o.phi[c] = ph;
       o.rho[c] = m.rho;
       o.dphx[c] = m.dphx;
       o.dphy[c] = m.dphy;
@@ -242,6 +292,16 @@ struct MacBlock {
     }
     o.p[c] = m.p;
   }
+#if defined(__HIPCC__)
+  // the phases in order, a workgroup barrier between them
+  __device__ void run(int tid) const {
+    p0(tid);
+    __syncthreads();
+    p1(tid);
+    __syncthreads();
+    p2(tid);
+  }
+#endif
 };
 
 #if defined(__HIPCC__)
@@ -252,10 +312,7 @@ __global__ __launch_bounds__(MBX * MBY) void k_macros(Consts K, Work w, int gx, 
   __shared__ MacLds L;
   const int b = xcd_tile(blockIdx.x, nb);
   const MacBlock mb{K, w, (b % gx) * MBX, (b / gx) * MBY, &L, nullptr, fields != 0};
-  const int tid = threadIdx.y * MBX + threadIdx.x;
-  mb.p0(tid);
-  __syncthreads();
-  mb.p1(tid);
+  mb.run(threadIdx.y * MBX + threadIdx.x);
 }
 
 // the same in tape mode: the cell fields of w's state into the tape slot t
@@ -264,10 +321,7 @@ __global__ __launch_bounds__(MBX * MBY) void k_macros_tape(Consts K, Work w, Wor
   __shared__ MacLds L;
   const int b = xcd_tile(blockIdx.x, nb);
   const MacBlock mb{K, w, (b % gx) * MBX, (b / gx) * MBY, &L, &t};
-  const int tid = threadIdx.y * MBX + threadIdx.x;
-  mb.p0(tid);
-  __syncthreads();
-  mb.p1(tid);
+  mb.run(threadIdx.y * MBX + threadIdx.x);
 }
 #endif
 

@@ -35,6 +35,7 @@ struct CpuEx {
         const MacBlock mb{K, w, bx * MBX, by * MBY, L.data(), tape, fields};
         for (int t = 0; t < MBX * MBY; ++t) mb.p0(t);
         for (int t = 0; t < MBX * MBY; ++t) mb.p1(t);
+        for (int t = 0; t < MBX * MBY; ++t) mb.p2(t);
       }
   }
   void macros_tape(const Consts &K, const Work &w, const Work &t) { macros(K, w, true, &t); }
