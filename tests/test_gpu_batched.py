@@ -26,6 +26,10 @@ def _cases():
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_instances_bitwise_equal_single(D, prec):
+    """Batch instances evolve bit for bit as single handles across graph
+    boundaries.  At these sizes a single handle keeps tilde+ in the output
+    buffer and the batch kernel keeps it in LDS, so this also holds the two
+    forms of the tile kernel to each other."""
     p = D.FP64 if prec == "fp64" else D.FP32_STATE
     cases = _cases()
     b = D.BatchSimulation(cases, precision=p)
@@ -43,7 +47,8 @@ def test_batch_instances_bitwise_equal_single(D, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_upwind_batch_instances_bitwise_equal_single(D, prec):
     """A batch of UPWIND instances (two-ring tiles) evolves bit for bit as
-    single handles, across graph boundaries."""
+    single handles, across graph boundaries (tilde+ in LDS against the
+    single handles' output buffer)."""
     p = D.FP64 if prec == "fp64" else D.FP32_STATE
     cases = _cases()
     for c in cases:
