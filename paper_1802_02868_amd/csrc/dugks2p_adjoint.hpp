@@ -669,6 +669,7 @@ struct AdjCellTile {
     FaceSide fs[4];
     double bb[2][4];  // face bar adjoints of the current f and g at W, E, S, N
     double nb[2][4];  // the same for the next velocity (loaded ahead)
+    double nnb[2][4];  // and for the one after it
     double lf, lg, sf;  // lam of the current f and g, and the current f~
     int ox[3], oy[3];  // window offsets of the transpose stencils' cells
     double wx[3], wy[3];
@@ -706,6 +707,7 @@ struct AdjCellTile {
     s.fs[2] = face_side<1>(K, s.F.js, 1);
     s.fs[3] = face_side<1>(K, s.F.jn, 0);
     load_bb(s.F, 0, s.bb);
+    load_bb(s.F, 1, s.nb);
     if (!s.own) return;
     const i64 c = (i64)s.j * K.ld + s.i;
     // the transpose stencils' cells are lo(c), c, hi(c) along each axis: the
@@ -787,10 +789,10 @@ struct AdjCellTile {
     return ab + tx + ty;
   }
   // Step 2 adjoint of velocity i2 at a tile cell; every thread first issues
-  // the loads of the next velocity's face values
+  // the loads of the face values two velocities ahead
   DFN void cell(int i2, St &s) const {
     if (s.i < 0) return;
-    if (i2 < 8) load_bb(s.F, i2 + 1, s.nb);
+    if (i2 < 7) load_bb(s.F, i2 + 2, s.nnb);
     if (s.own) {
       const i64 c = (i64)s.j * K.ld + s.i, P = K.plane;
       const int qf = i2, qg = 9 + i2;
@@ -810,7 +812,10 @@ struct AdjCellTile {
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) s.bb[k][e] = s.nb[k][e];
+        for (int e = 0; e < 4; ++e) {
+          s.bb[k][e] = s.nb[k][e];
+          s.nb[k][e] = s.nnb[k][e];
+        }
     }
   }
   // the cell-field adjoints of a tile cell, after the last velocity
