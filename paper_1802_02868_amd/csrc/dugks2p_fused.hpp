@@ -925,21 +925,14 @@ void with_tile_shape(int shape, bool unit, F &&f) {
     f(TileSq{});
 }
 
-// Ping-pong states up to this size (both buffers, bytes) stay in the MALL
-// (256 MB) while a step runs, so the square and two-ring tile kernels at unit
-// lattice speed keep tilde+ in the output buffer there: the store and reload
-// then cost no HBM traffic, and the LDS they free lets three workgroups share
-// a CU.  On larger states the reload goes to HBM and the LDS form is faster.
-constexpr double TILDE_OUT_MAX_STATE_BYTES = 128.0 * 1024.0 * 1024.0;
-
 // Calls f(u, s, v, tg) with the compile-time choices of the single-handle
 // tile kernel for a DUGKS2P_TILE_* shape and the constants K: u the
 // unit-speed flag (std::bool_constant), s the tile shape, v the viscosity
 // model (std::integral_constant<int, VIS_*>), tg whether tilde+ goes through
 // the output buffer (std::bool_constant; taken for square and two-ring tiles
-// at unit speed when the caller's ping-pong state is at most
-// TILDE_OUT_MAX_STATE_BYTES, passed as resident; the wide and tall tiles
-// would not fit three to a CU even so).  At unit lattice speed every
+// at unit speed when the caller passes resident, a ping-pong state that
+// stays in the MALL; the wide and tall tiles would not fit three to a CU
+// even so).  At unit lattice speed every
 // shape is compiled for a given tau_f and for the mixture viscosity apart
 // (the run-time choice costs the tile kernel about a tenth of its speed);
 // other speeds take square or two-ring tiles and read the model at run time.

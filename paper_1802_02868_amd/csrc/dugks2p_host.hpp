@@ -261,6 +261,15 @@ inline Consts make_consts(const dugks2p_params *P, AxisHost &ax, AxisHost &ay) {
 // ---------------------------------------------------------------------------
 // Workspace layout.  Every region starts on a 256-byte boundary.
 // ---------------------------------------------------------------------------
+// Ping-pong states up to this size (both buffers, bytes) stay in the MALL
+// (256 MB) while a step runs, so the square and two-ring tile kernels at unit
+// lattice speed keep tilde+ in the output buffer there (with_fused_kernel):
+// the store and reload then cost no HBM traffic, and the LDS they free lets
+// three workgroups share a CU.  On larger states the reload goes to HBM and
+// the LDS form is faster (measured: 6-8 % faster at 159-170 MB, 4 % slower
+// at 231 MB, 2 % slower at 302 MB).
+constexpr double TILDE_OUT_MAX_STATE_BYTES = 192.0 * 1024.0 * 1024.0;
+
 struct Layout {
   size_t tables[2];  // per-axis table block
   size_t state[2];   // ping-pong population buffers
