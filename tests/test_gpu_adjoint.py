@@ -48,6 +48,10 @@ def _gpu_adjoint(D, case, steps, mseg, lam):
 
 @pytest.mark.parametrize("case,steps,mseg", CASES, ids=[c[0].name for c in CASES])
 def test_gpu_adjoint_matches_host_build(D, case, steps, mseg):
+    """Consistency of the GPU build with the host build of the same reverse
+    kernels (compiler, scheduling, LDS and wavefront effects), not parity:
+    the derivative itself is held to the oracle by the finite-difference and
+    complex-step tests of this file and of the CPU suite."""
     print("adjoint vs host build:", case.name, steps, mseg, flush=True)
     lam = np.random.default_rng(7).standard_normal((18, case.ny, case.nx))
     pops, g0, g3 = _gpu_adjoint(D, case, steps, mseg, lam)
