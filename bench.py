@@ -472,7 +472,10 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_vs_plain(args.batched_steps, D.FP32_STATE)
     if not args.no_adjoint and args.recon == "central":  # the adjoint is of CENTRAL steps
-        out["adjoint"] = adjoint_cost(case, args.adjoint_steps, 50)
+        # the adjoint workload's grid (RT 512 x 2048, checkpoints every 50
+        # steps), and the headline workload's grid beside it
+        out["adjoint"] = adjoint_cost(workload("rt512x2048"), args.adjoint_steps, 50)
+        out["adjoint_headline_grid"] = adjoint_cost(case, args.adjoint_steps, 50)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)
