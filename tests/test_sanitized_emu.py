@@ -2,7 +2,7 @@
 UndefinedBehaviorSanitizer, with every LDS-window access bounds-checked
 (DUGKS2P_WINDOW_CHECK aborts on an offset outside the tile's window).
 
-The driver tests/emu/sanitize_main.cpp is compiled with g++ for the CPU and
+The stand-alone program tests/emu/sanitize_main.cpp is compiled with g++ and
 run as a child process on fused CENTRAL and UPWIND steps, FP32 state, the
 staged kernels and the adjoint, including grids of one and two tiles and
 ragged tiles.  A sanitizer report, a window overrun or a non-zero exit fails
